@@ -1,0 +1,191 @@
+"""Jacobi3D benchmark on one MI355X.
+
+Default workload: a 512^3 FP64 grid decomposed into 2x2x2 blocks of 256^3;
+every step is one full iteration of the hot path (pack the paired faces,
+exchange them through the pre-posted pairing, unpack, sweep).  Prints one
+JSON line with whole-job throughput in GLUP/s (1e9 interior lattice-site
+updates per second), the sweep kernel's bandwidth against the HBM roofline
+and the CPU oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--gpus 1] [--steps 1000] [--warmup 50] [--workload 512_2x2x2]
+                  [--mode staged|fused] [--no-cpu] [--copy-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor peak
+METRIC = "Jacobi3D GLUP/s + HBM GB/s (% peak); served solves/s, p50/p99 at 1e-10 resid"
+
+WORKLOADS = {
+    # name: (grid, block_dims or None, uneven cuts seed or None, default mode)
+    "512_2x2x2": ((512, 512, 512), (256, 256, 256), None, "staged"),
+    "64_single": ((64, 64, 64), None, None, "staged"),
+    "768_8x8x8": ((768, 768, 768), (96, 96, 96), None, "fused"),
+    "768_uneven": ((768, 768, 768), None, 12416, "fused"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="512_2x2x2", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default=None, choices=["staged", "fused"])
+    ap.add_argument("--seed", type=int, default=12416)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = 1 << 28                                   # 2 GiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+
+
+def cpu_baseline(grid, seed, seconds):
+    """The oracle as it stands, on the undecomposed grid, for a bounded
+    number of sweeps; returns GLUP/s and what was run."""
+    import numpy as np
+
+    import oracle
+    import synth
+    u = synth.boundary_field(grid, seed=seed)
+    v = u.copy()
+    lib = oracle.lib()
+    dp = oracle._dptr
+    nx, ny, nz = grid
+    sweeps = 0
+    t0 = time.perf_counter()
+    while True:
+        lib.oracle_sweep(dp(u), dp(v), None, nx, ny, nz)
+        u, v = v, u
+        sweeps += 1
+        if time.perf_counter() - t0 >= seconds and sweeps >= 2:
+            break
+    dt = time.perf_counter() - t0
+    lups = float(nx) * ny * nz * sweeps
+    del u, v
+    return dict(value=lups / dt / 1e9, unit="GLUP/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample="%d sweeps of the undecomposed %dx%dx%d grid (C oracle, OpenMP) in %.1f s"
+                       % (sweeps, nx, ny, nz, dt),
+                host_cpus=len(os.sched_getaffinity(0)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2102_12416_amd import Solver, _lib as L
+
+    grid, bd, uneven_seed, default_mode = WORKLOADS[args.workload]
+    mode = args.mode or default_mode
+    kw = {}
+    if bd is not None:
+        kw["block_dims"] = bd
+    if uneven_seed is not None:
+        kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
+    print("[bench] workload %s mode %s: building inputs" % (args.workload, mode), file=sys.stderr, flush=True)
+    u0 = synth.boundary_field(grid, seed=args.seed)
+    s = Solver(grid, mode=mode, use_graphs=False, **kw)
+    s.load(u0)
+    del u0
+    nb = s.num_blocks
+    tiles = s.tile_info()
+    s.iterate(args.warmup)
+    s.synchronize()
+    print("[bench] warmup done (%d iterations); timing %d" % (args.warmup, args.steps), file=sys.stderr,
+          flush=True)
+
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    t0 = time.perf_counter()
+    s.iterate(args.steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kinds = {"sweep": L.JC_K_SWEEP, "pack": L.JC_K_PACK, "exchange": L.JC_K_EXCHANGE,
+             "unpack": L.JC_K_UNPACK, "fused": L.JC_K_FUSED}
+    ktime = {k: s.kernel_time(v) for k, v in kinds.items()}
+    s.set_timing(False)
+    print("[bench] timed region done: %.3f s wall, %.3f ms on the stream" % (wall, gpu_ms), file=sys.stderr,
+          flush=True)
+
+    nx, ny, nz = grid
+    lups = float(nx) * ny * nz
+    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+    glups = lups * args.steps / (ms_per_step * args.steps * 1e-3) / 1e9
+    dom = "fused" if mode == "fused" else "sweep"
+    dom_ms, dom_n = ktime[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    sweep_bytes = 16.0 * lups                       # read u, write u' per cell update
+    achieved = sweep_bytes / (avg_ms * 1e-3) / 1e9
+    halo_values = sum(s.pair_info(q)["count"] for q in range(s.num_pairs))
+    step_bytes = sweep_bytes + (16.0 if mode == "fused" else 48.0) * halo_values
+    out = {
+        "metric": METRIC,
+        "value": round(glups, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
+                   "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
+                   "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
+        "hbm_gbs_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "pct_hbm_peak_step": round(100 * step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_sweep" if mode == "staged" else "k_sweep(fused)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": sweep_bytes, "avg_launch_ms": round(avg_ms, 5)},
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in ktime.items() if v[1]},
+    }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline (%.0f s budget)" % args.cpu_seconds, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(grid, args.seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * jc.h -- C-ABI of libjc, the one-GPU Jacobi3D hot path for MI355X (gfx950).
+ *
+ * The workload is the Jacobi3D proxy application of "Accelerating
+ * Communication for Parallel Programming Models on GPU Systems" (section
+ * 4.3): the Jacobi iterative method for the 3D 7-point stencil on a grid
+ * decomposed into equal-size cuboid blocks (chosen to minimise surface
+ * area), each block exchanging its halo with up to six neighbours, run for
+ * a fixed number of iterations.  Here every block lives on one GPU; the
+ * halo of each block face travels through a persistent pairing of device
+ * buffers fixed when the context is created -- the one-device counterpart of
+ * the Channel API of section 3.2.2, where a channel between a pair of
+ * objects is created once and afterwards both sides already know the buffer
+ * and the tag, so no host metadata message is needed per transfer.
+ *
+ * Conventions shared by every call
+ *  - Grid: interior nx*ny*nz cells, indexed 1..n per axis, surrounded by a
+ *    1-cell Dirichlet shell (indices 0 and n+1).  A "global padded array"
+ *    is a C array of (nz+2)*(ny+2)*(nx+2) binary64 values, x unit-stride.
+ *  - Update: u'(c) = (((((u(x-1)+u(x+1))+u(y-1))+u(y+1))+u(z-1))+u(z+1) [+ b(c)]) / 6,
+ *    summed in that order, one IEEE division; strict Jacobi (ping-pong).
+ *  - Residual: r = (b + s) - 6u with s the neighbour sum above; its 2-norm.
+ *  - Status codes: 0 ok, >0 informational, <0 error.  No C++ exception or
+ *    longjmp crosses this interface.  After a negative status,
+ *    jc_last_error() returns a message for the calling thread.
+ *  - Memory: the caller owns one device arena per context (jc_bind) and
+ *    keeps it alive until jc_destroy; the library carves it into blocks,
+ *    face buffers and tables and never allocates device memory for a
+ *    context.  Host pointers passed in are borrowed for the call only.
+ *  - Streams: every call is enqueued asynchronously on the stream given to
+ *    jc_bind, except jc_residual, jc_solve and jc_solve_ir, which wait for
+ *    the stream before returning.  A context is not thread-safe; distinct
+ *    contexts are independent.
+ *  - Errors of argument validation are reported before any device work is
+ *    enqueued; jc_footprint, jc_create*, the jc_*_info queries and
+ *    jc_destroy never touch the device.
+ */
+#ifndef JC_H
+#define JC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    JC_OK = 0,
+    JC_MAXITER = 1,          /* solve stopped at its iteration cap (not an error) */
+    JC_ERR_INVALID = -1,     /* bad argument */
+    JC_ERR_NOMEM = -2,       /* arena smaller than jc_footprint */
+    JC_ERR_DEVICE = -3,      /* a HIP call failed */
+    JC_ERR_STATE = -4,       /* call out of order (e.g. unpack before exchange) */
+    JC_ERR_NONFINITE = -5    /* residual became NaN or infinite */
+};
+
+/* ---- storage formats, fields, modes ----------------------------------- */
+enum { JC_F64 = 0, JC_F32 = 1, JC_BF16 = 2, JC_NONE = -1 };
+enum { JC_FIELD_U = 0, JC_FIELD_B = 1 };
+enum {
+    JC_MODE_STAGED = 0,      /* per iteration: pack, exchange, unpack, sweep kernels */
+    JC_MODE_FUSED = 1        /* per iteration: one launch; ghosts read from the
+                                neighbours' face buffers, faces written in the epilogue */
+};
+/* kinds for jc_kernel_time */
+enum { JC_K_SWEEP = 0, JC_K_PACK = 1, JC_K_EXCHANGE = 2, JC_K_UNPACK = 3,
+       JC_K_RESIDUAL = 4, JC_K_FUSED = 5, JC_K_IR_INNER = 6, JC_K_IR_OUTER = 7,
+       JC_K_COUNT = 8 };
+
+typedef struct jc_ctx jc_ctx;
+typedef struct jc_group jc_group;
+
+/* Creation options.  Zero-initialise and set what you need. */
+typedef struct jc_options {
+    int mode;            /* JC_MODE_STAGED or JC_MODE_FUSED */
+    int with_source;     /* 1: the context holds a source field b */
+    int ir_dtype;        /* JC_NONE (0 is treated as none too) or JC_F32/JC_BF16 with
+                            ir_enable = 1: allocate refinement buffers (d, r_lo) */
+    int ir_enable;
+    int tile_y;          /* rows per tile; 0 = auto */
+    int z_chunk;         /* planes per tile; 0 = auto */
+    int use_graphs;      /* 1: capture jc_iterate windows as HIP graphs */
+    int debug_epochs;    /* 1: stamp face buffers with the iteration and check them */
+} jc_options;
+
+/* Result of a solve. */
+typedef struct jc_solve_info {
+    int64_t iters;       /* sweeps performed (inner sweeps for jc_solve_ir) */
+    int64_t outer;       /* outer refinement steps (jc_solve_ir), else checks made */
+    double rel_resid;    /* |r_k| / |r_0| at the returned iterate */
+    double abs_resid;    /* |r_k| */
+    double r0;           /* |r_0| */
+    int status;          /* JC_OK (converged), JC_MAXITER, or an error */
+    double* history;     /* optional, caller-owned: residual norm at each check */
+    int64_t history_cap; /* capacity of history */
+    int64_t history_len; /* entries written */
+} jc_solve_info;
+
+/* ---- sizing and decomposition (host only) ------------------------------ */
+
+/* Device bytes a context with this geometry and these options needs.
+ * grid: interior sizes (nx, ny, nz), each >= 1.  block_dims: block
+ * interior sizes, 1 <= block_dims[i] <= grid[i]; when grid is not a
+ * multiple, the last block of an axis takes the remainder.
+ * Returns JC_ERR_INVALID on bad sizes.  Pure host arithmetic. */
+int jc_footprint(const int64_t grid[3], const int64_t block_dims[3],
+                 const jc_options* opt, size_t* bytes);
+int jc_footprint_rectilinear(const int64_t grid[3], const int64_t* const cuts[3],
+                             const int64_t ncuts[3], const jc_options* opt, size_t* bytes);
+
+/* Block counts (px, py, pz) with px*py*pz = nblocks that minimise the total
+ * block surface, the decomposition strategy of section 4.3; ties prefer
+ * more cuts along z, then y (long unit-stride rows).  parts[i] <= grid[i]. */
+int jc_min_surface_parts(const int64_t grid[3], int64_t nblocks, int64_t parts[3]);
+
+/* ---- lifetime -------------------------------------------------------- */
+
+/* Create a context for a uniform decomposition (see jc_footprint).  Builds
+ * the blocks, the face pairing table (one entry per directed pair of
+ * touching block faces: source block/face, destination block/face = the
+ * opposite face, value count, buffer offsets) and the tile work list.
+ * Host only; the context is unusable until jc_bind. */
+int jc_create(const int64_t grid[3], const int64_t block_dims[3],
+              const jc_options* opt, jc_ctx** out);
+
+/* Same for a rectilinear (tensor-product) decomposition: cuts[a] holds
+ * ncuts[a] block edges along axis a (x, y, z), each >= 1, summing to grid[a]. */
+int jc_create_rectilinear(const int64_t grid[3], const int64_t* const cuts[3],
+                          const int64_t ncuts[3], const jc_options* opt, jc_ctx** out);
+
+/* Attach the caller's device arena (>= jc_footprint bytes, 256-byte aligned)
+ * and HIP stream (hipStream_t, may be NULL for the null stream; graphs
+ * need a non-null stream).  Uploads the tables; enqueued on the stream. */
+int jc_bind(jc_ctx* ctx, void* dev_arena, size_t bytes, void* hip_stream);
+
+/* Frees the context's host data (and its graphs and events).  NULL-safe.
+ * The arena stays the caller's. */
+void jc_destroy(jc_ctx* ctx);
+
+/* Message for the last negative status on this thread ("" if none). */
+const char* jc_last_error(void);
+
+/* ---- fields -------------------------------------------------------- */
+
+/* Scatter a device global padded binary64 array into the blocks.
+ * JC_FIELD_U: shell = Dirichlet values, interior = initial iterate; both
+ * ping-pong copies of every block get their ghosts from it, so the halo of
+ * iterate 0 is current afterwards.  JC_FIELD_B: the source (needs
+ * with_source).  Resets the iteration count. */
+int jc_load_field(jc_ctx* ctx, int which, const void* dev_global_padded);
+
+/* Gather the current iterate (JC_FIELD_U, interior and Dirichlet shell) or
+ * the source into a device global padded binary64 array. */
+int jc_store_field(jc_ctx* ctx, int which, void* dev_global_padded);
+
+/* ---- the hot path (section 4.3: halo exchange, then stencil) ---------- */
+
+/* Copy the outermost interior plane of every paired block face of the
+ * current iterate into that pair's contiguous send buffer, ordered
+ * (slow, fast) over the shared plane: -x/+x faces (z, y), -y/+y (z, x),
+ * -z/+z (y, x).  The x faces are strided gathers. */
+int jc_pack_faces(jc_ctx* ctx);
+
+/* Move every send buffer into the receive buffer pre-posted for it at
+ * creation (the pairing); one batched device copy, no host work.
+ * JC_ERR_STATE unless jc_pack_faces ran since the last sweep. */
+int jc_exchange(jc_ctx* ctx);
+
+/* Copy every receive buffer into the ghost plane of the destination block
+ * face.  JC_ERR_STATE unless jc_exchange ran since the last pack. */
+int jc_unpack_faces(jc_ctx* ctx);
+
+/* One Jacobi sweep of every block from the current iterate into the other
+ * ping-pong buffer, then swap.  JC_ERR_STATE if inter-block ghosts are
+ * stale (staged mode: pack, exchange, unpack first). */
+int jc_sweep(jc_ctx* ctx);
+
+/* n full iterations.  Staged mode: n x (pack, exchange, unpack, sweep);
+ * fused mode: n single launches.  Graph-captured when use_graphs is set
+ * and the stream is not the null stream. */
+int jc_iterate(jc_ctx* ctx, int64_t n);
+
+/* |r|_2 of the current iterate into *host_l2 (exchanges first if the
+ * halo is stale).  Waits for the stream.  JC_ERR_NONFINITE on NaN/Inf. */
+int jc_residual(jc_ctx* ctx, double* host_l2);
+
+/* Iterate until |r_k|/|r_0| <= rtol at a check (every check_every sweeps)
+ * or max_iter sweeps; rtol <= 0 runs exactly max_iter sweeps and checks at
+ * the end (and at every check when history is given).  The residual of a
+ * check is computed inside the sweep that follows it, so a converged solve
+ * returns iterate k with no extra pass.  Returns JC_OK or JC_MAXITER (also
+ * in info->status), or an error. */
+int jc_solve(jc_ctx* ctx, double rtol, int64_t max_iter, int64_t check_every,
+             jc_solve_info* info);
+
+/* ---- introspection (host only) -------------------------------------- */
+
+int64_t jc_num_blocks(const jc_ctx* ctx);
+int64_t jc_num_pairs(const jc_ctx* ctx);
+int64_t jc_num_items(const jc_ctx* ctx);
+/* out[0..2] interior n, out[3..5] global offset (block cell x is global
+ * cell offset + x), out[6..11] neighbour block per face (-x,+x,-y,+y,-z,+z;
+ * -1 = global boundary), out[12] row pitch in elements, out[13] plane
+ * stride in elements, out[14..15] byte offset in the arena of element
+ * (0,0,0) of ping-pong copy 0 and 1 (cell (x,y,z) is element
+ * z*plane + y*pitch + x), out[16] current copy (0/1, valid once bound). */
+int jc_block_info(const jc_ctx* ctx, int64_t i, int64_t out[17]);
+/* out = {src_block, src_face, dst_block, dst_face, count, slow, fast,
+ *        buffer byte offset in the arena}. */
+int jc_pair_info(const jc_ctx* ctx, int64_t i, int64_t out[8]);
+/* Iterations performed since the last jc_load_field(U). */
+int64_t jc_iterations(const jc_ctx* ctx);
+/* Current tile shape and launch parameters: {tile_x, tile_y, z_chunk, items}. */
+int jc_tile_info(const jc_ctx* ctx, int64_t out[4]);
+
+/* ---- measurement ----------------------------------------------------- */
+
+/* enable != 0: bracket every kernel launch of this context with HIP events
+ * on its stream; jc_kernel_time returns the summed milliseconds and launch
+ * count per kind (JC_K_*) since enabling, after waiting for the stream. */
+int jc_set_timing(jc_ctx* ctx, int enable);
+int jc_kernel_time(jc_ctx* ctx, int kind, double* ms_total, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JC_H */

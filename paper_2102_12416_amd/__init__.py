@@ -1,0 +1,11 @@
+"""MI355X-native Jacobi3D hot path (arXiv 2102.12416, section 4.3, one GPU).
+
+libjc.so (HIP kernels + host runtime, C-ABI in include/jc.h) does the work;
+this package binds it with ctypes and supplies torch device memory and
+streams.  Importing it fails if libjc.so has not been built.
+"""
+from . import _lib
+from ._lib import JcError
+from .solver import Solver, footprint, min_surface_parts
+
+__all__ = ["Solver", "JcError", "footprint", "min_surface_parts", "_lib"]

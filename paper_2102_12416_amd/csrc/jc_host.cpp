@@ -1,0 +1,1085 @@
+// Host runtime of libjc: decomposition, face pairing, work lists, arena
+// layout, the state machine of the staged exchange, graph-captured
+// iteration windows and the solve driver.  Implements include/jc.h.
+//
+// Paper section 4.3 (Jacobi3D): the domain is split into equal cuboid
+// blocks with minimal surface area; each iteration exchanges block halos
+// with up to six neighbours and then applies the stencil; a fixed number
+// of iterations is run.  The pairing table built here is created once per
+// context, like the channels of section 3.2.2: afterwards every transfer
+// knows its source and destination buffers without any host message.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "jc.h"
+#include "jc_kernels.h"
+#include "jc_types.h"
+
+using jc::BlockDesc;
+using jc::Item;
+using jc::PairDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define JC_HIP(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(JC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxEdge = (int64_t)1 << 30;    // per-axis limit (int32 cell indices)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+enum GhostState { GHOST_CURRENT = 0, GHOST_PACKED = 1, GHOST_EXCHANGED = 2, GHOST_STALE = 3 };
+
+struct HostBlock {
+    int64_t n[3];
+    int64_t off[3];
+    int nbr[6];
+    int pair_out[6];        // pair index whose source is this face, or -1
+    int pair_in[6];         // pair index whose destination is this face, or -1
+    int64_t pitch, plane;   // binary64 arrays
+    size_t u_off[2], b_off; // byte offsets of element (0,0,0)'s line base
+};
+
+struct HostPair {
+    int src_block, src_face, dst_block, dst_face;
+    int64_t slow, fast, count;
+    size_t buf_off[2];
+};
+
+const int kTileYCandidates[] = {1, 2, 4, 8, 16};
+constexpr int kMinZChunk = 16;
+
+}  // namespace
+
+struct jc_ctx {
+    int64_t grid[3] = {0, 0, 0};
+    std::vector<int64_t> cuts[3];
+    jc_options opt{};
+    std::vector<HostBlock> blocks;
+    std::vector<HostPair> pairs;
+    int64_t max_slow = 0, max_fast = 0, max_count = 0;
+    int tile_y = 4;
+    int z_chunk = 0;
+    std::vector<Item> items;
+    int64_t max_items = 0;
+    // arena layout
+    size_t off_blocks = 0, off_pairs = 0, off_items = 0, off_partials = 0, off_ranges = 0,
+           off_result = 0, footprint = 0;
+    // binding
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    std::vector<BlockDesc> hdesc;
+    std::vector<PairDesc> hpairs;
+    int32_t hranges[2] = {0, 0};
+    double* h_result = nullptr;     // pinned
+    // state
+    bool loaded_u = false, loaded_b = false;
+    int parity = 0;
+    int64_t iters = 0;
+    int ghost = GHOST_CURRENT;
+    bool fused_primed = false;
+    // graphs keyed by (iterations, start parity, residual-last)
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    // timing
+    bool timing = false;
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[JC_K_COUNT] = {0};
+    int64_t kernel_launches[JC_K_COUNT] = {0};
+
+    BlockDesc* d_blocks() const { return reinterpret_cast<BlockDesc*>(arena + off_blocks); }
+    PairDesc* d_pairs() const { return reinterpret_cast<PairDesc*>(arena + off_pairs); }
+    Item* d_items() const { return reinterpret_cast<Item*>(arena + off_items); }
+    double* d_partials() const { return reinterpret_cast<double*>(arena + off_partials); }
+    int32_t* d_ranges() const { return reinterpret_cast<int32_t*>(arena + off_ranges); }
+    double* d_result() const { return reinterpret_cast<double*>(arena + off_result); }
+    int nb() const { return (int)blocks.size(); }
+    int np() const { return (int)pairs.size(); }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ geometry
+
+int64_t items_for(const jc_ctx* c, int ty, int zc)
+{
+    int64_t total = 0;
+    for (const HostBlock& b : c->blocks) {
+        const int64_t tx = (b.n[0] + jc::kTileX - 1) / jc::kTileX;
+        const int64_t tyn = (b.n[1] + ty - 1) / ty;
+        const int64_t tz = (b.n[2] + zc - 1) / zc;
+        total += tx * tyn * tz;
+    }
+    return total;
+}
+
+// Default tile: 4 rows; z chunks halved from the full depth until the
+// launch has at least 4096 tiles (16 per compute unit) or chunks reach 16.
+void default_tiles(const jc_ctx* c, int* ty, int* zc)
+{
+    int64_t maxz = 1;
+    for (const HostBlock& b : c->blocks)
+        maxz = std::max(maxz, b.n[2]);
+    int t = c->opt.tile_y > 0 ? c->opt.tile_y : 4;
+    int z = c->opt.z_chunk > 0 ? c->opt.z_chunk : (int)std::min<int64_t>(maxz, 1 << 20);
+    if (c->opt.z_chunk <= 0) {
+        while (z > kMinZChunk && items_for(c, t, z) < 4096)
+            z = (z + 1) / 2;
+    }
+    *ty = t;
+    *zc = z;
+}
+
+void build_items(jc_ctx* c)
+{
+    c->items.clear();
+    for (int bi = 0; bi < c->nb(); ++bi) {
+        const HostBlock& b = c->blocks[bi];
+        for (int64_t z0 = 0; z0 < b.n[2]; z0 += c->z_chunk)
+            for (int64_t y0 = 0; y0 < b.n[1]; y0 += c->tile_y)
+                for (int64_t x0 = 0; x0 < b.n[0]; x0 += jc::kTileX) {
+                    Item it{};
+                    it.block = bi;
+                    it.x0 = (int32_t)x0;
+                    it.y0 = (int32_t)y0;
+                    it.z0 = (int32_t)z0;
+                    it.zlen = (int32_t)std::min<int64_t>(c->z_chunk, b.n[2] - z0);
+                    it.flip = 0;
+                    it.owner = 0;
+                    c->items.push_back(it);
+                }
+    }
+}
+
+int validate_options(const jc_options* opt)
+{
+    if (!opt)
+        return JC_OK;
+    if (opt->mode != JC_MODE_STAGED && opt->mode != JC_MODE_FUSED)
+        return fail(JC_ERR_INVALID, "options.mode must be JC_MODE_STAGED or JC_MODE_FUSED");
+    if (opt->tile_y != 0) {
+        bool ok = false;
+        for (int t : kTileYCandidates)
+            ok = ok || t == opt->tile_y;
+        if (!ok)
+            return fail(JC_ERR_INVALID, "options.tile_y must be 0, 1, 2, 4, 8 or 16");
+    }
+    if (opt->z_chunk < 0)
+        return fail(JC_ERR_INVALID, "options.z_chunk must be >= 0");
+    if (opt->ir_enable)
+        return fail(JC_ERR_INVALID, "iterative refinement buffers are not available in this build");
+    return JC_OK;
+}
+
+int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> cuts[3],
+                   const jc_options* opt)
+{
+    int st = validate_options(opt);
+    if (st != JC_OK)
+        return st;
+    if (opt)
+        c->opt = *opt;
+    for (int a = 0; a < 3; ++a) {
+        if (grid[a] < 1 || grid[a] > kMaxEdge)
+            return fail(JC_ERR_INVALID, "grid sizes must be in [1, 2^30]");
+        int64_t sum = 0;
+        for (int64_t v : cuts[a]) {
+            if (v < 1)
+                return fail(JC_ERR_INVALID, "block edges must be >= 1");
+            sum += v;
+        }
+        if (cuts[a].empty() || sum != grid[a])
+            return fail(JC_ERR_INVALID, "block edges along an axis must sum to the grid size");
+        c->grid[a] = grid[a];
+        c->cuts[a] = cuts[a];
+    }
+    const int64_t px = (int64_t)cuts[0].size(), py = (int64_t)cuts[1].size(), pz = (int64_t)cuts[2].size();
+    if (px * py * pz > (1 << 24))
+        return fail(JC_ERR_INVALID, "too many blocks");
+    std::vector<int64_t> start[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t s = 0;
+        for (int64_t v : cuts[a]) {
+            start[a].push_back(s);
+            s += v;
+        }
+    }
+    auto bidx = [&](int64_t i, int64_t j, int64_t k) { return (int)((k * py + j) * px + i); };
+    c->blocks.clear();
+    c->pairs.clear();
+    for (int64_t k = 0; k < pz; ++k)
+        for (int64_t j = 0; j < py; ++j)
+            for (int64_t i = 0; i < px; ++i) {
+                HostBlock b{};
+                b.n[0] = cuts[0][i]; b.n[1] = cuts[1][j]; b.n[2] = cuts[2][k];
+                b.off[0] = start[0][i]; b.off[1] = start[1][j]; b.off[2] = start[2][k];
+                b.nbr[jc::XM] = i > 0 ? bidx(i - 1, j, k) : -1;
+                b.nbr[jc::XP] = i + 1 < px ? bidx(i + 1, j, k) : -1;
+                b.nbr[jc::YM] = j > 0 ? bidx(i, j - 1, k) : -1;
+                b.nbr[jc::YP] = j + 1 < py ? bidx(i, j + 1, k) : -1;
+                b.nbr[jc::ZM] = k > 0 ? bidx(i, j, k - 1) : -1;
+                b.nbr[jc::ZP] = k + 1 < pz ? bidx(i, j, k + 1) : -1;
+                for (int f = 0; f < 6; ++f)
+                    b.pair_out[f] = b.pair_in[f] = -1;
+                b.pitch = round_up(b.n[0] + 2, jc::line_elems<double>());
+                b.plane = b.pitch * (b.n[1] + 2);
+                c->blocks.push_back(b);
+            }
+    // pairing table: one directed pair per touching face, in block order
+    for (int bi = 0; bi < c->nb(); ++bi) {
+        HostBlock& b = c->blocks[bi];
+        for (int f = 0; f < 6; ++f) {
+            if (b.nbr[f] < 0)
+                continue;
+            HostPair p{};
+            p.src_block = bi;
+            p.src_face = f;
+            p.dst_block = b.nbr[f];
+            p.dst_face = jc::opposite(f);
+            if (f == jc::XM || f == jc::XP) { p.slow = b.n[2]; p.fast = b.n[1]; }
+            else if (f == jc::YM || f == jc::YP) { p.slow = b.n[2]; p.fast = b.n[0]; }
+            else { p.slow = b.n[1]; p.fast = b.n[0]; }
+            p.count = p.slow * p.fast;
+            b.pair_out[f] = (int)c->pairs.size();
+            c->pairs.push_back(p);
+        }
+    }
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& p = c->pairs[q];
+        c->blocks[p.dst_block].pair_in[p.dst_face] = q;
+        c->max_slow = std::max(c->max_slow, p.slow);
+        c->max_fast = std::max(c->max_fast, p.fast);
+        c->max_count = std::max(c->max_count, p.count);
+    }
+    if (c->max_slow > 65535)
+        return fail(JC_ERR_INVALID, "a shared block face is longer than 65535 along its slow axis");
+    if (c->np() > 65535)
+        return fail(JC_ERR_INVALID, "too many face pairs for one launch");
+    if (c->nb() > 65535)
+        return fail(JC_ERR_INVALID, "too many blocks for one launch");
+    default_tiles(c, &c->tile_y, &c->z_chunk);
+    build_items(c);
+    // the work-list region is sized for the finest tiling the tuner may pick
+    c->max_items = std::max<int64_t>((int64_t)c->items.size(), items_for(c, 1, kMinZChunk));
+    if (c->max_items > (int64_t)1 << 30)
+        return fail(JC_ERR_INVALID, "work list too long");
+    // arena layout
+    size_t off = 0;
+    c->off_blocks = off; off = align_up(off + sizeof(BlockDesc) * c->blocks.size(), kAlign);
+    c->off_pairs = off; off = align_up(off + sizeof(PairDesc) * std::max<size_t>(1, c->pairs.size()), kAlign);
+    c->off_items = off; off = align_up(off + sizeof(Item) * (size_t)c->max_items, kAlign);
+    c->off_partials = off; off = align_up(off + sizeof(double) * (size_t)c->max_items, kAlign);
+    c->off_ranges = off; off = align_up(off + sizeof(int32_t) * 2, kAlign);
+    c->off_result = off; off = align_up(off + sizeof(double) * 4, kAlign);
+    for (HostBlock& b : c->blocks) {
+        // element (0,0,0) sits 15 elements into a 128-byte line so that
+        // cell x = 1 of every row starts a line; 16 elements of slack
+        const size_t bytes = align_up(sizeof(double) * (size_t)(b.plane * (b.n[2] + 2) + 16), kAlign);
+        b.u_off[0] = off; off += bytes;
+        b.u_off[1] = off; off += bytes;
+        if (c->opt.with_source) { b.b_off = off; off += bytes; }
+    }
+    for (HostPair& p : c->pairs) {
+        const size_t bytes = align_up(sizeof(double) * (size_t)p.count, kAlign);
+        p.buf_off[0] = off; off += bytes;
+        p.buf_off[1] = off; off += bytes;
+    }
+    c->footprint = off;
+    return JC_OK;
+}
+
+std::vector<int64_t> uniform_cuts(int64_t n, int64_t bd)
+{
+    std::vector<int64_t> v;
+    for (int64_t s = 0; s < n; s += bd)
+        v.push_back(std::min(bd, n - s));
+    return v;
+}
+
+int uniform_geometry(jc_ctx* c, const int64_t grid[3], const int64_t block_dims[3], const jc_options* opt)
+{
+    if (!grid || !block_dims)
+        return fail(JC_ERR_INVALID, "grid and block_dims must not be NULL");
+    std::vector<int64_t> cuts[3];
+    for (int a = 0; a < 3; ++a) {
+        if (grid[a] < 1 || grid[a] > kMaxEdge)
+            return fail(JC_ERR_INVALID, "grid sizes must be in [1, 2^30]");
+        if (block_dims[a] < 1 || block_dims[a] > grid[a])
+            return fail(JC_ERR_INVALID, "block_dims must satisfy 1 <= block_dims[i] <= grid[i]");
+        if ((grid[a] + block_dims[a] - 1) / block_dims[a] > 65535)
+            return fail(JC_ERR_INVALID, "too many blocks along an axis");
+        cuts[a] = uniform_cuts(grid[a], block_dims[a]);
+    }
+    return build_geometry(c, grid, cuts, opt);
+}
+
+int rect_geometry(jc_ctx* c, const int64_t grid[3], const int64_t* const cuts[3], const int64_t ncuts[3],
+                  const jc_options* opt)
+{
+    if (!grid || !cuts || !ncuts)
+        return fail(JC_ERR_INVALID, "grid, cuts and ncuts must not be NULL");
+    std::vector<int64_t> v[3];
+    for (int a = 0; a < 3; ++a) {
+        if (ncuts[a] < 1 || ncuts[a] > 65535 || !cuts[a])
+            return fail(JC_ERR_INVALID, "each axis needs 1..65535 block edges");
+        v[a].assign(cuts[a], cuts[a] + ncuts[a]);
+    }
+    return build_geometry(c, grid, v, opt);
+}
+
+// ------------------------------------------------------------------ timing
+
+hipEvent_t take_event(jc_ctx* c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Runs `launch` bracketed by events when timing is on.
+template <typename F>
+int timed(jc_ctx* c, int kind, F&& launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        a = take_event(c);
+        b = take_event(c);
+        if (!a || !b)
+            return fail(JC_ERR_DEVICE, "hipEventCreate failed");
+        JC_HIP(hipEventRecord(a, c->stream));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess)
+        return fail(JC_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (c->timing) {
+        JC_HIP(hipEventRecord(b, c->stream));
+        c->pending.push_back({kind, a, b});
+    }
+    return JC_OK;
+}
+
+int drain_timing(jc_ctx* c)
+{
+    if (c->pending.empty())
+        return JC_OK;
+    JC_HIP(hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        JC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        c->kernel_ms[p.kind] += ms;
+        c->kernel_launches[p.kind] += 1;
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return JC_OK;
+}
+
+// ------------------------------------------------------------------ steps
+
+int check_ready(jc_ctx* c)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (!c->bound)
+        return fail(JC_ERR_STATE, "context is not bound to an arena (jc_bind)");
+    if (!c->loaded_u)
+        return fail(JC_ERR_STATE, "the iterate has not been loaded (jc_load_field U)");
+    if (c->opt.with_source && !c->loaded_b)
+        return fail(JC_ERR_STATE, "the source has not been loaded (jc_load_field B)");
+    return JC_OK;
+}
+
+int do_pack(jc_ctx* c, int slot)
+{
+    return timed(c, JC_K_PACK, [&] {
+        return jc::launch_pack(c->d_blocks(), c->d_pairs(), c->np(), (int)c->max_slow, (int)c->max_fast,
+                               c->parity, slot, c->stream);
+    });
+}
+
+int do_exchange(jc_ctx* c)
+{
+    return timed(c, JC_K_EXCHANGE, [&] {
+        return jc::launch_exchange(c->d_pairs(), c->np(), c->max_count, c->stream);
+    });
+}
+
+int do_unpack(jc_ctx* c)
+{
+    return timed(c, JC_K_UNPACK, [&] {
+        return jc::launch_unpack(c->d_blocks(), c->d_pairs(), c->np(), (int)c->max_slow, (int)c->max_fast,
+                                 c->parity, c->stream);
+    });
+}
+
+int do_sweep(jc_ctx* c, bool fused, bool resid)
+{
+    int st = timed(c, fused ? JC_K_FUSED : JC_K_SWEEP, [&] {
+        return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_y,
+                                fused, resid, true, c->d_partials(), c->stream);
+    });
+    if (st != JC_OK)
+        return st;
+    c->parity ^= 1;
+    c->iters += 1;
+    if (fused) {
+        c->fused_primed = true;
+        c->ghost = c->np() ? GHOST_STALE : GHOST_CURRENT;
+    } else {
+        c->ghost = c->np() ? GHOST_STALE : GHOST_CURRENT;
+        c->fused_primed = false;
+    }
+    return JC_OK;
+}
+
+int do_halo(jc_ctx* c)
+{
+    if (c->np() == 0) {
+        c->ghost = GHOST_CURRENT;
+        return JC_OK;
+    }
+    int st = do_pack(c, 0);
+    if (st == JC_OK) st = do_exchange(c);
+    if (st == JC_OK) st = do_unpack(c);
+    if (st == JC_OK) {
+        c->ghost = GHOST_CURRENT;
+        c->fused_primed = false;
+    }
+    return st;
+}
+
+// One full iteration of the context's mode; resid: the sweep also sums
+// r^2 of its input iterate into the partials.
+int one_iteration(jc_ctx* c, bool resid)
+{
+    if (c->opt.mode == JC_MODE_FUSED) {
+        if (!c->fused_primed && c->np()) {
+            int st = do_pack(c, c->parity);
+            if (st != JC_OK)
+                return st;
+            c->fused_primed = true;
+        }
+        return do_sweep(c, c->np() > 0, resid);
+    }
+    int st = do_halo(c);
+    if (st != JC_OK)
+        return st;
+    return do_sweep(c, false, resid);
+}
+
+int reduce_to_host(jc_ctx* c, double* sumsq)
+{
+    JC_HIP(jc::launch_reduce(c->d_partials(), c->d_ranges(), 1, c->d_result(), c->stream));
+    JC_HIP(hipMemcpyAsync(c->h_result, c->d_result(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    JC_HIP(hipStreamSynchronize(c->stream));
+    int st = drain_timing(c);
+    if (st != JC_OK)
+        return st;
+    *sumsq = c->h_result[0];
+    return JC_OK;
+}
+
+// Residual of the current iterate by a standalone pass.
+int residual_now(jc_ctx* c, double* l2)
+{
+    bool fused = false;
+    if (c->opt.mode == JC_MODE_FUSED && c->np()) {
+        if (!c->fused_primed) {
+            int st = do_pack(c, c->parity);
+            if (st != JC_OK)
+                return st;
+            c->fused_primed = true;
+        }
+        fused = true;
+    } else if (c->ghost != GHOST_CURRENT) {
+        int st = do_halo(c);
+        if (st != JC_OK)
+            return st;
+    }
+    int st = timed(c, JC_K_RESIDUAL, [&] {
+        return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_y, fused,
+                                true, false, c->d_partials(), c->stream);
+    });
+    if (st != JC_OK)
+        return st;
+    double s = 0;
+    st = reduce_to_host(c, &s);
+    if (st != JC_OK)
+        return st;
+    *l2 = std::sqrt(s);
+    if (!std::isfinite(*l2))
+        return fail(JC_ERR_NONFINITE, "residual is not finite");
+    return JC_OK;
+}
+
+// n plain iterations, as one graph replay when graphs are enabled.
+int iterate_window(jc_ctx* c, int64_t n)
+{
+    if (n <= 0)
+        return JC_OK;
+    const bool graphs = c->opt.use_graphs && c->stream != nullptr && !c->timing;
+    if (!graphs) {
+        for (int64_t i = 0; i < n; ++i) {
+            int st = one_iteration(c, false);
+            if (st != JC_OK)
+                return st;
+        }
+        return JC_OK;
+    }
+    // the priming pack of fused mode stays outside the graph
+    if (c->opt.mode == JC_MODE_FUSED && !c->fused_primed && c->np()) {
+        int st = do_pack(c, c->parity);
+        if (st != JC_OK)
+            return st;
+        c->fused_primed = true;
+    }
+    const auto key = std::make_pair(n, c->parity);
+    auto found = c->graphs.find(key);
+    if (found == c->graphs.end()) {
+        const int parity0 = c->parity;
+        const int64_t iters0 = c->iters;
+        const int ghost0 = c->ghost;
+        const bool primed0 = c->fused_primed;
+        JC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int st = JC_OK;
+        for (int64_t i = 0; i < n && st == JC_OK; ++i)
+            st = one_iteration(c, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        // capture only recorded the launches: restore the state and replay
+        c->parity = parity0;
+        c->iters = iters0;
+        c->ghost = ghost0;
+        c->fused_primed = primed0;
+        if (st != JC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess)
+            return fail(JC_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return fail(JC_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        found = c->graphs.emplace(key, exec).first;
+    }
+    JC_HIP(hipGraphLaunch(found->second, c->stream));
+    // the state after n iterations, as the eager path would leave it
+    c->parity ^= (int)(n & 1);
+    c->iters += n;
+    if (c->np()) {
+        c->ghost = GHOST_STALE;
+        c->fused_primed = c->opt.mode == JC_MODE_FUSED;
+    }
+    return JC_OK;
+}
+
+void free_graphs(jc_ctx* c)
+{
+    for (auto& kv : c->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* jc_last_error(void) { return g_err.c_str(); }
+
+int jc_min_surface_parts(const int64_t grid[3], int64_t nblocks, int64_t parts[3])
+{
+    if (!grid || !parts || nblocks < 1)
+        return fail(JC_ERR_INVALID, "grid and parts must not be NULL and nblocks >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (grid[a] < 1)
+            return fail(JC_ERR_INVALID, "grid sizes must be >= 1");
+    double best = -1;
+    int64_t bp[3] = {0, 0, 0};
+    for (int64_t px = 1; px <= nblocks; ++px) {
+        if (nblocks % px || px > grid[0])
+            continue;
+        for (int64_t py = 1; py <= nblocks / px; ++py) {
+            if ((nblocks / px) % py || py > grid[1])
+                continue;
+            const int64_t pz = nblocks / px / py;
+            if (pz > grid[2])
+                continue;
+            // both sides of every cut plane, plus the outer surface
+            const double gx = (double)grid[0], gy = (double)grid[1], gz = (double)grid[2];
+            const double area = 2.0 * (gy * gz * (double)px + gx * gz * (double)py + gx * gy * (double)pz);
+            const bool better = best < 0 || area < best ||
+                                (area == best && (pz > bp[2] || (pz == bp[2] && py > bp[1])));
+            if (better) {
+                best = area;
+                bp[0] = px; bp[1] = py; bp[2] = pz;
+            }
+        }
+    }
+    if (best < 0)
+        return fail(JC_ERR_INVALID, "no decomposition of the grid into that many blocks");
+    parts[0] = bp[0]; parts[1] = bp[1]; parts[2] = bp[2];
+    return JC_OK;
+}
+
+int jc_footprint(const int64_t grid[3], const int64_t block_dims[3], const jc_options* opt, size_t* bytes)
+{
+    if (!bytes)
+        return fail(JC_ERR_INVALID, "bytes must not be NULL");
+    jc_ctx tmp;
+    int st = uniform_geometry(&tmp, grid, block_dims, opt);
+    if (st != JC_OK)
+        return st;
+    *bytes = tmp.footprint;
+    return JC_OK;
+}
+
+int jc_footprint_rectilinear(const int64_t grid[3], const int64_t* const cuts[3], const int64_t ncuts[3],
+                             const jc_options* opt, size_t* bytes)
+{
+    if (!bytes)
+        return fail(JC_ERR_INVALID, "bytes must not be NULL");
+    jc_ctx tmp;
+    int st = rect_geometry(&tmp, grid, cuts, ncuts, opt);
+    if (st != JC_OK)
+        return st;
+    *bytes = tmp.footprint;
+    return JC_OK;
+}
+
+int jc_create(const int64_t grid[3], const int64_t block_dims[3], const jc_options* opt, jc_ctx** out)
+{
+    if (!out)
+        return fail(JC_ERR_INVALID, "out must not be NULL");
+    *out = nullptr;
+    jc_ctx* c = new (std::nothrow) jc_ctx();
+    if (!c)
+        return fail(JC_ERR_NOMEM, "host allocation failed");
+    int st = uniform_geometry(c, grid, block_dims, opt);
+    if (st != JC_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return JC_OK;
+}
+
+int jc_create_rectilinear(const int64_t grid[3], const int64_t* const cuts[3], const int64_t ncuts[3],
+                          const jc_options* opt, jc_ctx** out)
+{
+    if (!out)
+        return fail(JC_ERR_INVALID, "out must not be NULL");
+    *out = nullptr;
+    jc_ctx* c = new (std::nothrow) jc_ctx();
+    if (!c)
+        return fail(JC_ERR_NOMEM, "host allocation failed");
+    int st = rect_geometry(c, grid, cuts, ncuts, opt);
+    if (st != JC_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return JC_OK;
+}
+
+void jc_destroy(jc_ctx* c)
+{
+    if (!c)
+        return;
+    if (c->bound) {
+        (void)hipStreamSynchronize(c->stream);
+        free_graphs(c);
+        for (auto& p : c->pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (hipEvent_t e : c->event_pool)
+            (void)hipEventDestroy(e);
+        if (c->h_result)
+            (void)hipHostFree(c->h_result);
+    }
+    delete c;
+}
+
+int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (c->bound)
+        return fail(JC_ERR_STATE, "context is already bound");
+    if (!dev_arena)
+        return fail(JC_ERR_INVALID, "arena must not be NULL");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign)
+        return fail(JC_ERR_INVALID, "arena must be 256-byte aligned");
+    if (bytes < c->footprint)
+        return fail(JC_ERR_NOMEM, "arena smaller than jc_footprint (" + std::to_string(bytes) + " < " +
+                                       std::to_string(c->footprint) + ")");
+    c->arena = static_cast<char*>(dev_arena);
+    c->arena_bytes = bytes;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    JC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(double) * 4, hipHostMallocDefault));
+    c->hdesc.assign(c->blocks.size(), BlockDesc{});
+    for (int bi = 0; bi < c->nb(); ++bi) {
+        const HostBlock& hb = c->blocks[bi];
+        BlockDesc& d = c->hdesc[bi];
+        const int64_t lead = jc::line_elems<double>() - 1;
+        d.u[0] = reinterpret_cast<double*>(c->arena + hb.u_off[0]) + lead;
+        d.u[1] = reinterpret_cast<double*>(c->arena + hb.u_off[1]) + lead;
+        d.b = c->opt.with_source ? reinterpret_cast<double*>(c->arena + hb.b_off) + lead : nullptr;
+        for (int f = 0; f < 6; ++f)
+            for (int s = 0; s < 2; ++s) {
+                d.gin[f][s] = hb.pair_in[f] >= 0
+                                  ? reinterpret_cast<double*>(c->arena + c->pairs[hb.pair_in[f]].buf_off[s])
+                                  : nullptr;
+                d.gout[f][s] = hb.pair_out[f] >= 0
+                                   ? reinterpret_cast<double*>(c->arena + c->pairs[hb.pair_out[f]].buf_off[s])
+                                   : nullptr;
+            }
+        for (int a = 0; a < 3; ++a) {
+            d.n[a] = (int32_t)hb.n[a];
+            d.off[a] = (int32_t)hb.off[a];
+        }
+        d.pitch = (int32_t)hb.pitch;
+        d.plane = hb.plane;
+    }
+    c->hpairs.assign(c->pairs.size(), PairDesc{});
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& hp = c->pairs[q];
+        PairDesc& d = c->hpairs[q];
+        d.src_block = hp.src_block; d.src_face = hp.src_face;
+        d.dst_block = hp.dst_block; d.dst_face = hp.dst_face;
+        d.slow = (int32_t)hp.slow; d.fast = (int32_t)hp.fast; d.count = hp.count;
+        d.buf[0] = reinterpret_cast<double*>(c->arena + hp.buf_off[0]);
+        d.buf[1] = reinterpret_cast<double*>(c->arena + hp.buf_off[1]);
+    }
+    c->hranges[0] = 0;
+    c->hranges[1] = (int32_t)c->items.size();
+    JC_HIP(hipMemcpyAsync(c->d_blocks(), c->hdesc.data(), sizeof(BlockDesc) * c->hdesc.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    if (c->np())
+        JC_HIP(hipMemcpyAsync(c->d_pairs(), c->hpairs.data(), sizeof(PairDesc) * c->hpairs.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    JC_HIP(hipMemcpyAsync(c->d_items(), c->items.data(), sizeof(Item) * c->items.size(), hipMemcpyHostToDevice,
+                          c->stream));
+    JC_HIP(hipMemcpyAsync(c->d_ranges(), c->hranges, sizeof(c->hranges), hipMemcpyHostToDevice, c->stream));
+    JC_HIP(hipStreamSynchronize(c->stream));   // host tables may change after this call
+    c->bound = true;
+    return JC_OK;
+}
+
+int jc_load_field(jc_ctx* c, int which, const void* src)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (!c->bound)
+        return fail(JC_ERR_STATE, "context is not bound (jc_bind)");
+    if (!src)
+        return fail(JC_ERR_INVALID, "source array must not be NULL");
+    if (which == JC_FIELD_B && !c->opt.with_source)
+        return fail(JC_ERR_INVALID, "context was created without a source field");
+    if (which != JC_FIELD_U && which != JC_FIELD_B)
+        return fail(JC_ERR_INVALID, "which must be JC_FIELD_U or JC_FIELD_B");
+    JC_HIP(jc::launch_scatter(c->d_blocks(), c->nb(), static_cast<const double*>(src), c->grid[0], c->grid[1],
+                              which, c->stream));
+    if (which == JC_FIELD_U) {
+        c->loaded_u = true;
+        c->parity = 0;
+        c->iters = 0;
+        c->ghost = GHOST_CURRENT;     // the scatter filled every ghost with iterate 0
+        c->fused_primed = false;
+    } else {
+        c->loaded_b = true;
+    }
+    return JC_OK;
+}
+
+int jc_store_field(jc_ctx* c, int which, void* dst)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (!c->bound)
+        return fail(JC_ERR_STATE, "context is not bound (jc_bind)");
+    if (!dst)
+        return fail(JC_ERR_INVALID, "destination array must not be NULL");
+    if (which == JC_FIELD_B && !c->opt.with_source)
+        return fail(JC_ERR_INVALID, "context was created without a source field");
+    if (which != JC_FIELD_U && which != JC_FIELD_B)
+        return fail(JC_ERR_INVALID, "which must be JC_FIELD_U or JC_FIELD_B");
+    if ((which == JC_FIELD_U && !c->loaded_u) || (which == JC_FIELD_B && !c->loaded_b))
+        return fail(JC_ERR_STATE, "field was never loaded");
+    JC_HIP(jc::launch_gather(c->d_blocks(), c->nb(), static_cast<double*>(dst), c->grid[0], c->grid[1],
+                             c->grid[2], which, c->parity, c->stream));
+    return JC_OK;
+}
+
+int jc_pack_faces(jc_ctx* c)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    st = do_pack(c, 0);
+    if (st == JC_OK) {
+        c->ghost = GHOST_PACKED;
+        c->fused_primed = false;
+    }
+    return st;
+}
+
+int jc_exchange(jc_ctx* c)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (c->ghost != GHOST_PACKED)
+        return fail(JC_ERR_STATE, "jc_exchange needs jc_pack_faces first");
+    st = do_exchange(c);
+    if (st == JC_OK)
+        c->ghost = GHOST_EXCHANGED;
+    return st;
+}
+
+int jc_unpack_faces(jc_ctx* c)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (c->ghost != GHOST_EXCHANGED)
+        return fail(JC_ERR_STATE, "jc_unpack_faces needs jc_exchange first");
+    st = do_unpack(c);
+    if (st == JC_OK)
+        c->ghost = GHOST_CURRENT;
+    return st;
+}
+
+int jc_sweep(jc_ctx* c)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (c->np() && c->ghost != GHOST_CURRENT)
+        return fail(JC_ERR_STATE, "halo is stale: jc_pack_faces, jc_exchange, jc_unpack_faces first");
+    return do_sweep(c, false, false);
+}
+
+int jc_iterate(jc_ctx* c, int64_t n)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (n < 0)
+        return fail(JC_ERR_INVALID, "n must be >= 0");
+    return iterate_window(c, n);
+}
+
+int jc_residual(jc_ctx* c, double* host_l2)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (!host_l2)
+        return fail(JC_ERR_INVALID, "host_l2 must not be NULL");
+    return residual_now(c, host_l2);
+}
+
+int jc_solve(jc_ctx* c, double rtol, int64_t max_iter, int64_t check_every, jc_solve_info* info)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (!info)
+        return fail(JC_ERR_INVALID, "info must not be NULL");
+    if (max_iter < 0 || check_every < 1)
+        return fail(JC_ERR_INVALID, "max_iter must be >= 0 and check_every >= 1");
+    if (!std::isfinite(rtol))
+        return fail(JC_ERR_INVALID, "rtol must be finite");
+    info->history_len = 0;
+    info->outer = 0;
+    const bool checks = rtol > 0 || (info->history && info->history_cap > 0);
+    auto record = [&](double r) {
+        if (info->history && info->history_len < info->history_cap)
+            info->history[info->history_len++] = r;
+        info->outer += 1;
+    };
+    const int64_t start = c->iters;
+    double r0 = -1.0, r = 0.0;
+    int64_t k = 0;
+    int status = JC_MAXITER;
+    while (true) {
+        if (k == max_iter) {
+            st = residual_now(c, &r);
+            if (st != JC_OK)
+                return st;
+            if (r0 < 0)
+                r0 = r;
+            record(r);
+            const double rel = r0 > 0 ? r / r0 : 0.0;
+            status = (rtol > 0 && rel <= rtol) ? JC_OK : JC_MAXITER;
+            break;
+        }
+        if (checks && k % check_every == 0) {
+            // the sweep out of iterate k also sums r_k^2
+            st = one_iteration(c, true);
+            if (st != JC_OK)
+                return st;
+            double s = 0;
+            st = reduce_to_host(c, &s);
+            if (st != JC_OK)
+                return st;
+            r = std::sqrt(s);
+            if (!std::isfinite(r))
+                return fail(JC_ERR_NONFINITE, "residual is not finite at iteration " + std::to_string(start + k));
+            if (r0 < 0)
+                r0 = r;
+            record(r);
+            const double rel = r0 > 0 ? r / r0 : 0.0;
+            if (rtol > 0 && rel <= rtol) {
+                // return iterate k: it is still intact in the other copy
+                c->parity ^= 1;
+                c->iters -= 1;
+                if (c->opt.mode == JC_MODE_FUSED) {
+                    // slot `parity` of every face buffer still holds iterate k's faces
+                    c->fused_primed = true;
+                    c->ghost = c->np() ? GHOST_STALE : GHOST_CURRENT;
+                } else {
+                    // the halo of iterate k was unpacked into its copy before the sweep
+                    c->ghost = GHOST_CURRENT;
+                    c->fused_primed = false;
+                }
+                status = JC_OK;
+                break;
+            }
+            k += 1;
+            const int64_t n = std::min(check_every - 1, max_iter - k);
+            st = iterate_window(c, n);
+            if (st != JC_OK)
+                return st;
+            k += n;
+        } else {
+            const int64_t n = checks ? std::min(check_every - (k % check_every), max_iter - k) : max_iter - k;
+            st = iterate_window(c, n);
+            if (st != JC_OK)
+                return st;
+            k += n;
+        }
+    }
+    info->iters = c->iters - start;
+    info->abs_resid = r;
+    info->r0 = r0;
+    info->rel_resid = r0 > 0 ? r / r0 : 0.0;
+    info->status = status;
+    return status;
+}
+
+int64_t jc_num_blocks(const jc_ctx* c) { return c ? (int64_t)c->blocks.size() : 0; }
+int64_t jc_num_pairs(const jc_ctx* c) { return c ? (int64_t)c->pairs.size() : 0; }
+int64_t jc_num_items(const jc_ctx* c) { return c ? (int64_t)c->items.size() : 0; }
+int64_t jc_iterations(const jc_ctx* c) { return c ? c->iters : 0; }
+
+int jc_block_info(const jc_ctx* c, int64_t i, int64_t out[17])
+{
+    if (!c || !out || i < 0 || i >= (int64_t)c->blocks.size())
+        return fail(JC_ERR_INVALID, "bad context or block index");
+    const HostBlock& b = c->blocks[i];
+    for (int a = 0; a < 3; ++a) {
+        out[a] = b.n[a];
+        out[3 + a] = b.off[a];
+    }
+    for (int f = 0; f < 6; ++f)
+        out[6 + f] = b.nbr[f];
+    out[12] = b.pitch;
+    out[13] = b.plane;
+    const int64_t lead = (jc::line_elems<double>() - 1) * (int64_t)sizeof(double);
+    out[14] = (int64_t)b.u_off[0] + lead;
+    out[15] = (int64_t)b.u_off[1] + lead;
+    out[16] = c->parity;
+    return JC_OK;
+}
+
+int jc_pair_info(const jc_ctx* c, int64_t i, int64_t out[8])
+{
+    if (!c || !out || i < 0 || i >= (int64_t)c->pairs.size())
+        return fail(JC_ERR_INVALID, "bad context or pair index");
+    const HostPair& p = c->pairs[i];
+    out[0] = p.src_block; out[1] = p.src_face; out[2] = p.dst_block; out[3] = p.dst_face;
+    out[4] = p.count; out[5] = p.slow; out[6] = p.fast; out[7] = (int64_t)p.buf_off[0];
+    return JC_OK;
+}
+
+int jc_tile_info(const jc_ctx* c, int64_t out[4])
+{
+    if (!c || !out)
+        return fail(JC_ERR_INVALID, "bad context or output");
+    out[0] = jc::kTileX;
+    out[1] = c->tile_y;
+    out[2] = c->z_chunk;
+    out[3] = (int64_t)c->items.size();
+    return JC_OK;
+}
+
+int jc_set_timing(jc_ctx* c, int enable)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (!c->bound)
+        return fail(JC_ERR_STATE, "context is not bound (jc_bind)");
+    int st = drain_timing(c);
+    if (st != JC_OK)
+        return st;
+    c->timing = enable != 0;
+    for (int k = 0; k < JC_K_COUNT; ++k) {
+        c->kernel_ms[k] = 0;
+        c->kernel_launches[k] = 0;
+    }
+    return JC_OK;
+}
+
+int jc_kernel_time(jc_ctx* c, int kind, double* ms_total, int64_t* launches)
+{
+    if (!c || kind < 0 || kind >= JC_K_COUNT || !ms_total || !launches)
+        return fail(JC_ERR_INVALID, "bad arguments");
+    int st = drain_timing(c);
+    if (st != JC_OK)
+        return st;
+    *ms_total = c->kernel_ms[kind];
+    *launches = c->kernel_launches[kind];
+    return JC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,41 @@
+// Launchers of the libjc HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "jc_types.h"
+
+namespace jc {
+
+// Tile widths: one 64-lane wavefront covers 64 consecutive x cells of one row.
+constexpr int kTileX = 64;
+
+// Sweep / residual over a work list.  parity selects the input copy of
+// each item's block (xor the item's flip).  fused: read paired ghosts from
+// the face buffers of the input slot and write face values to the output
+// slot.  resid: write one partial sum of r^2 per item into partials.
+// store: write the new iterate (false = residual only).
+hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
+                        int tile_y, bool fused, bool resid, bool store, double* partials,
+                        hipStream_t s);
+
+// Sum partials[ranges[m] .. ranges[m+1]) in a fixed order into out[m], m < nmembers.
+hipError_t launch_reduce(const double* partials, const int32_t* ranges, int nmembers, double* out,
+                         hipStream_t s);
+
+// Face pack (interior face plane of u[parity] -> pair buffer slot),
+// exchange (slot 0 -> slot 1), unpack (slot 1 -> ghost plane of u[parity]).
+hipError_t launch_pack(const BlockDesc* blocks, const PairDesc* pairs, int npairs, int max_slow,
+                       int max_fast, int parity, int slot, hipStream_t s);
+hipError_t launch_exchange(const PairDesc* pairs, int npairs, int64_t max_count, hipStream_t s);
+hipError_t launch_unpack(const BlockDesc* blocks, const PairDesc* pairs, int npairs, int max_slow,
+                         int max_fast, int parity, hipStream_t s);
+
+// Global padded array <-> blocks.  which: 0 = iterate (both copies on
+// scatter; copy `parity` on gather), 1 = source.
+hipError_t launch_scatter(const BlockDesc* blocks, int nblocks, const double* global,
+                          int64_t gnx, int64_t gny, int which, hipStream_t s);
+hipError_t launch_gather(const BlockDesc* blocks, int nblocks, double* global, int64_t gnx,
+                         int64_t gny, int64_t gnz, int which, int parity, hipStream_t s);
+
+}  // namespace jc

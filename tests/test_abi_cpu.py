@@ -1,0 +1,226 @@
+"""libjc host logic without a GPU: exports, validation, decomposition,
+pairing geometry, footprint and state errors.  No device call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2102_12416_amd import _lib as L
+from paper_2102_12416_amd._lib import check
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(jc_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares a signature for every one of them
+    assert names <= set(L.SIGNATURES), sorted(names - set(L.SIGNATURES))
+
+
+def create(grid, bd, **kw):
+    opt = L.Options()
+    opt.mode = kw.get("mode", 0)
+    opt.with_source = kw.get("with_source", 0)
+    opt.ir_dtype = L.JC_NONE
+    opt.tile_y = kw.get("tile_y", 0)
+    opt.z_chunk = kw.get("z_chunk", 0)
+    ctx = ctypes.c_void_p()
+    st = L.lib.jc_create(L.i64(grid), L.i64(bd), ctypes.byref(opt), ctypes.byref(ctx))
+    return st, ctx
+
+
+def create_rect(grid, cuts):
+    opt = L.Options()
+    opt.ir_dtype = L.JC_NONE
+    arrs = [L.i64(c) for c in cuts]
+    ptrs = (ctypes.POINTER(ctypes.c_int64) * 3)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_int64)) for a in arrs])
+    ctx = ctypes.c_void_p()
+    st = L.lib.jc_create_rectilinear(L.i64(grid), ptrs, L.i64([len(c) for c in cuts]), ctypes.byref(opt),
+                                     ctypes.byref(ctx))
+    return st, ctx
+
+
+def blocks_of(ctx):
+    out = []
+    for i in range(L.lib.jc_num_blocks(ctx)):
+        v = (ctypes.c_int64 * 17)()
+        check(L.lib.jc_block_info(ctx, i, v))
+        out.append(list(v))
+    return out
+
+
+def pairs_of(ctx):
+    out = []
+    for i in range(L.lib.jc_num_pairs(ctx)):
+        v = (ctypes.c_int64 * 8)()
+        check(L.lib.jc_pair_info(ctx, i, v))
+        out.append(list(v))
+    return out
+
+
+@pytest.mark.parametrize("grid,bd,nb,npairs", [
+    ((512, 512, 512), (256, 256, 256), 8, 24),     # 12 interfaces, both directions
+    ((768, 768, 768), (96, 96, 96), 512, 2688),    # 3 * 7 * 64 interfaces
+    ((64, 64, 64), (64, 64, 64), 1, 0),
+    ((37, 29, 23), (16, 8, 10), 3 * 4 * 3, 2 * (2 * 4 * 3 + 3 * 3 * 3 + 3 * 4 * 2)),
+])
+def test_uniform_decomposition_and_pairing(grid, bd, nb, npairs):
+    st, ctx = create(grid, bd)
+    assert st == 0, L.last_error()
+    try:
+        blocks = blocks_of(ctx)
+        pairs = pairs_of(ctx)
+        assert len(blocks) == nb and len(pairs) == npairs
+        # blocks tile the grid exactly
+        assert sum(b[0] * b[1] * b[2] for b in blocks) == grid[0] * grid[1] * grid[2]
+        for b in blocks:
+            for a in range(3):
+                assert 0 <= b[3 + a] and b[3 + a] + b[a] <= grid[a]
+            # pitch: a multiple of 16 doubles with room for both x ghosts
+            assert b[12] % 16 == 0 and b[12] >= b[0] + 2
+            assert b[13] == b[12] * (b[1] + 2)
+        # every directed pair has its reverse, with opposite faces and equal counts
+        table = {(p[0], p[1]): p for p in pairs}
+        for p in pairs:
+            src, f, dst, g, count, slow, fast, _ = p
+            assert g == f ^ 1
+            rev = table[(dst, g)]
+            assert rev[2] == src and rev[3] == f and rev[4] == count
+            assert slow * fast == count
+            # neighbours touch: offsets differ by the source edge along the face normal
+            a = f // 2
+            bs, bd_ = blocks[src], blocks[dst]
+            if f % 2 == 1:
+                assert bs[3 + a] + bs[a] == bd_[3 + a]
+            else:
+                assert bd_[3 + a] + bd_[a] == bs[3 + a]
+            assert blocks[src][6 + f] == dst
+        # faces on the global boundary have no neighbour
+        for i, b in enumerate(blocks):
+            for f in range(6):
+                a = f // 2
+                on_boundary = (b[3 + a] == 0) if f % 2 == 0 else (b[3 + a] + b[a] == grid[a])
+                assert (b[6 + f] == -1) == on_boundary
+    finally:
+        L.lib.jc_destroy(ctx)
+
+
+def test_remainder_block_is_last():
+    st, ctx = create((10, 7, 5), (4, 7, 2))
+    assert st == 0
+    xs = sorted({(b[3], b[0]) for b in blocks_of(ctx)})
+    zs = sorted({(b[5], b[2]) for b in blocks_of(ctx)})
+    assert xs == [(0, 4), (4, 4), (8, 2)]
+    assert zs == [(0, 2), (2, 2), (4, 1)]
+    L.lib.jc_destroy(ctx)
+
+
+def test_rectilinear_uneven_cuts():
+    import synth
+    cuts = [synth.uneven_cuts(768, 32, 160, seed=12416, axis=a) for a in range(3)]
+    st, ctx = create_rect((768, 768, 768), cuts)
+    assert st == 0, L.last_error()
+    nb = len(cuts[0]) * len(cuts[1]) * len(cuts[2])
+    assert L.lib.jc_num_blocks(ctx) == nb
+    blocks = blocks_of(ctx)
+    assert sum(b[0] * b[1] * b[2] for b in blocks) == 768 ** 3
+    L.lib.jc_destroy(ctx)
+
+
+@pytest.mark.parametrize("grid,bd", [((0, 4, 4), (1, 1, 1)), ((8, 8, 8), (9, 8, 8)), ((8, 8, 8), (0, 8, 8)),
+                                     ((8, -1, 8), (8, 8, 8))])
+def test_invalid_geometry(grid, bd):
+    st, ctx = create(grid, bd)
+    assert st == L.JC_ERR_INVALID
+    assert not ctx.value
+    assert L.last_error()
+    fp = ctypes.c_size_t()
+    assert L.lib.jc_footprint(L.i64(grid), L.i64(bd), None, ctypes.byref(fp)) == L.JC_ERR_INVALID
+
+
+def test_invalid_rectilinear_sum():
+    st, ctx = create_rect((10, 10, 10), [[5, 4], [10], [10]])
+    assert st == L.JC_ERR_INVALID and "sum" in L.last_error()
+
+
+def test_invalid_options():
+    st, _ = create((8, 8, 8), (8, 8, 8), tile_y=3)
+    assert st == L.JC_ERR_INVALID
+    st, _ = create((8, 8, 8), (8, 8, 8), mode=7)
+    assert st == L.JC_ERR_INVALID
+
+
+def test_footprint_covers_arrays_and_buffers():
+    grid, bd = (512, 512, 512), (256, 256, 256)
+    fp = ctypes.c_size_t()
+    check(L.lib.jc_footprint(L.i64(grid), L.i64(bd), None, ctypes.byref(fp)))
+    pitch = 272                                  # 256 + 2 rounded up to 16 doubles
+    arrays = 8 * 2 * pitch * 258 * 258 * 8       # 8 blocks, ping-pong
+    bufs = 24 * 2 * 256 * 256 * 8                # 24 pairs, send + receive
+    assert arrays + bufs <= fp.value <= (arrays + bufs) * 1.05
+    fps = ctypes.c_size_t()
+    opt = L.Options()
+    opt.with_source = 1
+    opt.ir_dtype = L.JC_NONE
+    check(L.lib.jc_footprint(L.i64(grid), L.i64(bd), ctypes.byref(opt), ctypes.byref(fps)))
+    assert fps.value - fp.value >= 8 * pitch * 258 * 258 * 8
+
+
+def test_min_surface_parts():
+    out = (ctypes.c_int64 * 3)()
+    check(L.lib.jc_min_surface_parts(L.i64((512, 512, 512)), 8, out))
+    assert tuple(out) == (2, 2, 2)
+    check(L.lib.jc_min_surface_parts(L.i64((768, 768, 768)), 512, out))
+    assert tuple(out) == (8, 8, 8)
+    # a long x axis is cut along x first
+    check(L.lib.jc_min_surface_parts(L.i64((4096, 256, 256)), 4, out))
+    assert tuple(out) == (4, 1, 1)
+    # 1536^3 over 6 devices: any permutation of (1, 2, 3) has minimal area; ties prefer z cuts
+    check(L.lib.jc_min_surface_parts(L.i64((1536, 1536, 1536)), 6, out))
+    assert tuple(out) == (1, 2, 3)
+    assert L.lib.jc_min_surface_parts(L.i64((2, 2, 2)), 27, out) == L.JC_ERR_INVALID
+
+
+def test_unbound_context_state_errors():
+    st, ctx = create((16, 16, 16), (8, 8, 8))
+    assert st == 0
+    for fn in (L.lib.jc_pack_faces, L.lib.jc_exchange, L.lib.jc_unpack_faces, L.lib.jc_sweep):
+        assert fn(ctx) == L.JC_ERR_STATE
+    assert L.lib.jc_iterate(ctx, 1) == L.JC_ERR_STATE
+    r = ctypes.c_double()
+    assert L.lib.jc_residual(ctx, ctypes.byref(r)) == L.JC_ERR_STATE
+    assert "bound" in L.last_error()
+    # arena checks happen before any device call
+    assert L.lib.jc_bind(ctx, None, 0, None) == L.JC_ERR_INVALID
+    assert L.lib.jc_bind(ctx, ctypes.c_void_p(4096), 1024, None) == L.JC_ERR_NOMEM
+    assert L.lib.jc_bind(ctx, ctypes.c_void_p(4097), 1 << 40, None) == L.JC_ERR_INVALID
+    L.lib.jc_destroy(ctx)
+
+
+def test_destroy_null_is_noop():
+    L.lib.jc_destroy(None)
+
+
+def test_tile_info_and_items():
+    st, ctx = create((512, 512, 512), (256, 256, 256), tile_y=4, z_chunk=64)
+    assert st == 0
+    out = (ctypes.c_int64 * 4)()
+    check(L.lib.jc_tile_info(ctx, out))
+    assert tuple(out) == (64, 4, 64, 8 * 4 * 64 * 4)
+    assert L.lib.jc_num_items(ctx) == out[3]
+    L.lib.jc_destroy(ctx)

@@ -1,0 +1,305 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+FP64 results are expected bitwise equal to the oracle (same summation
+order, IEEE division, no contraction on either side); the pass bar stated
+for the method is 1e-12 relative, and residual norms (whose reduction
+order differs) are compared at 1e-12 relative.  Decomposed vs single-block,
+fused vs staged, graph vs eager and tile shapes are compared bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+from paper_2102_12416_amd import JcError, Solver, _lib as L  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def run_gpu(n, iters, b=None, seed=12416, **kw):
+    u0 = synth.boundary_field(n, seed=seed)
+    with Solver(n, with_source=b is not None, **kw) as s:
+        s.load(u0, b)
+        s.iterate(iters)
+        return s.store().cpu().numpy()
+
+
+def local_oracle(u0, b, cell, k):
+    """Iterate k of the oracle at one cell, from a box of radius k + 1 (the
+    box edge is frozen; information moves one cell per sweep)."""
+    P = u0.shape
+    lo = [max(0, c - k - 1) for c in cell]
+    hi = [min(P[a] - 1, cell[a] + k + 1) for a in range(3)]
+    box = u0[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1].copy()
+    bb = None if b is None else b[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1].copy()
+    for _ in range(k):
+        box = oracle.sweep(box, bb)
+    return box[cell[0] - lo[0], cell[1] - lo[1], cell[2] - lo[2]]
+
+
+# ------------------------------------------------------------ the 64^3 case
+
+@pytest.mark.parametrize("seed", [12416, 1, 2])
+def test_single_block_64_vs_oracle(seed):
+    """64^3, one block, U[0,1) boundary, 100 iterations, residual every 10."""
+    say("64^3 single block, seed", seed)
+    n = (64, 64, 64)
+    u0 = synth.boundary_field(n, seed=seed)
+    ref, hist = oracle.c_jacobi(u0, 100, None, every=10)
+    with Solver(n) as s:
+        s.load(u0)
+        info = s.solve(rtol=0.0, max_iter=100, check_every=10, history=True)
+        got = s.store().cpu().numpy()
+    assert info["iters"] == 100
+    assert np.array_equal(got, ref)
+    assert len(info["history"]) == 11
+    np.testing.assert_allclose(info["history"], hist, rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------- decompositions, modes
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+@pytest.mark.parametrize("n,bd", [((37, 29, 23), (16, 8, 10)), ((64, 48, 40), (32, 24, 20)),
+                                  ((130, 17, 9), (65, 17, 9)), ((5, 70, 3), (5, 7, 1))])
+def test_decomposed_vs_oracle(mode, n, bd):
+    say("decomposed", n, bd, mode)
+    u0 = synth.boundary_field(n, seed=3)
+    b = synth.source_field(n, seed=3)
+    ref, _ = oracle.c_jacobi(u0, 17, b)
+    with Solver(n, block_dims=bd, mode=mode, with_source=True) as s:
+        s.load(u0, b)
+        s.iterate(17)
+        got = s.store().cpu().numpy()
+    assert np.array_equal(got, ref)
+    rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert rel <= 1e-12
+
+
+def test_rectilinear_uneven_vs_oracle():
+    say("rectilinear uneven 70x50x44")
+    n = (70, 50, 44)
+    cuts = [[20, 33, 17], [9, 41], [44]]
+    u0 = synth.boundary_field(n, seed=4)
+    ref, _ = oracle.c_jacobi(u0, 12, None)
+    for mode in ("staged", "fused"):
+        with Solver(n, cuts=cuts, mode=mode) as s:
+            s.load(u0)
+            s.iterate(12)
+            assert np.array_equal(s.store().cpu().numpy(), ref), mode
+
+
+def test_pack_exchange_unpack_bitwise():
+    """Send buffers hold the face planes, receive buffers their copies, and
+    unpacked ghost planes equal the neighbour's face plane, bit for bit."""
+    n = (40, 36, 33)
+    say("pack/exchange/unpack", n)
+    u0 = synth.boundary_field(n, seed=5)
+    u0[1:-1, 1:-1, 1:-1] = np.random.default_rng(5).random((n[2], n[1], n[0]))
+    with Solver(n, block_dims=(20, 18, 17)) as s:
+        s.load(u0)
+        s.pack_faces()
+        s.exchange()
+        s.unpack_faces()
+        s.synchronize()
+        g = torch.from_numpy(u0)
+        for q in range(s.num_pairs):
+            p = s.pair_info(q)
+            src = s.block_info(p["src_block"])
+            ox, oy, oz = src["off"]
+            nx, ny, nz = src["n"]
+            f = p["src_face"]
+            # the face plane of the source block in global padded coordinates
+            if f in (0, 1):
+                x = ox + (1 if f == 0 else nx)
+                plane = g[oz + 1:oz + nz + 1, oy + 1:oy + ny + 1, x]
+            elif f in (2, 3):
+                y = oy + (1 if f == 2 else ny)
+                plane = g[oz + 1:oz + nz + 1, y, ox + 1:ox + nx + 1]
+            else:
+                z = oz + (1 if f == 4 else nz)
+                plane = g[z, oy + 1:oy + ny + 1, ox + 1:ox + nx + 1]
+            count = p["count"]
+            send = s.arena_view(p["buf_off"], count).cpu()
+            assert torch.equal(send, plane.reshape(-1)), ("send", q)
+            # the receive buffer immediately follows (256-byte aligned)
+            recv_off = p["buf_off"] + ((count * 8 + 255) // 256) * 256
+            assert torch.equal(s.arena_view(recv_off, count).cpu(), send), ("recv", q)
+            dst = s.block_info(p["dst_block"])
+            arr = s.block_array(p["dst_block"]).cpu()
+            dnx, dny, dnz = dst["n"]
+            df = p["dst_face"]
+            if df in (0, 1):
+                ghost = arr[1:dnz + 1, 1:dny + 1, 0 if df == 0 else dnx + 1]
+            elif df in (2, 3):
+                ghost = arr[1:dnz + 1, 0 if df == 2 else dny + 1, 1:dnx + 1]
+            else:
+                ghost = arr[0 if df == 4 else dnz + 1, 1:dny + 1, 1:dnx + 1]
+            assert torch.equal(ghost.reshape(-1), send), ("unpack", q)
+
+
+def test_staged_state_machine():
+    say("state machine")
+    n = (32, 32, 32)
+    with Solver(n, block_dims=(16, 32, 32)) as s:
+        s.load(synth.boundary_field(n))
+        with pytest.raises(JcError) as e:
+            s.exchange()
+        assert e.value.code == L.JC_ERR_STATE
+        s.sweep()                                   # halo of iterate 0 came with the load
+        with pytest.raises(JcError) as e:
+            s.sweep()                               # halo now stale
+        assert e.value.code == L.JC_ERR_STATE
+        s.pack_faces()
+        with pytest.raises(JcError) as e:
+            s.unpack_faces()
+        assert e.value.code == L.JC_ERR_STATE
+        s.exchange()
+        s.unpack_faces()
+        s.sweep()
+        assert s.iterations == 2
+
+
+@pytest.mark.parametrize("tile_y,z_chunk", [(1, 16), (2, 0), (4, 7), (8, 0), (16, 33)])
+def test_tile_shapes_bitwise(tile_y, z_chunk):
+    say("tile", tile_y, z_chunk)
+    n = (100, 70, 66)
+    ref = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=4, z_chunk=0, mode="fused")
+    got = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=tile_y, z_chunk=z_chunk, mode="fused")
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_graph_replays_match_eager(mode):
+    """Each window replay, interleaved with eager work and synchronisation,
+    matches the eager run."""
+    say("graphs", mode)
+    n = (48, 40, 36)
+    u0 = synth.boundary_field(n, seed=6)
+    with Solver(n, block_dims=(24, 20, 18), mode=mode, use_graphs=False) as e, \
+            Solver(n, block_dims=(24, 20, 18), mode=mode, use_graphs=True) as g:
+        e.load(u0)
+        g.load(u0)
+        for rep in range(4):
+            e.iterate(5)
+            g.iterate(5)
+            torch.cuda.synchronize()
+            junk = torch.ones(1000, device="cuda") * rep      # unrelated eager work
+            assert np.array_equal(g.store().cpu().numpy(), e.store().cpu().numpy()), rep
+            del junk
+        g.iterate(3)          # odd window: the other start parity
+        e.iterate(3)
+        assert np.array_equal(g.store().cpu().numpy(), e.store().cpu().numpy())
+
+
+# -------------------------------------------------------------- solving
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_solve_to_tolerance_certified(mode):
+    n = (20, 18, 16)
+    say("solve to 1e-10", n, mode)
+    u0 = synth.boundary_field(n, seed=8)
+    b = synth.source_field(n, seed=8)
+    with Solver(n, block_dims=(10, 9, 16), mode=mode, with_source=True) as s:
+        s.load(u0, b)
+        info = s.solve(rtol=1e-10, max_iter=20000, check_every=10)
+        u = s.store().cpu().numpy()
+    assert info["converged"] and info["rel_resid"] <= 1e-10
+    # oracle certificate on the returned iterate
+    r0 = oracle.c_residual_norm(u0, b)
+    assert oracle.c_residual_norm(u, b) / r0 <= 1e-10 * (1 + 1e-9)
+    # same stopping iteration as the oracle's own checks, and the same iterate
+    ref, hist = oracle.c_jacobi(u0, info["iters"], b, every=10)
+    rel = [h / hist[0] for h in hist]
+    first = next(i for i, r in enumerate(rel) if r <= 1e-10) * 10
+    assert first == info["iters"]
+    assert np.array_equal(u, ref)
+
+
+def test_nonfinite_detected():
+    say("nonfinite")
+    n = (16, 16, 16)
+    u0 = synth.boundary_field(n)
+    u0[0, 5, 5] = np.nan
+    with Solver(n) as s:
+        s.load(u0)
+        with pytest.raises(JcError) as e:
+            s.solve(rtol=1e-10, max_iter=100, check_every=10)
+        assert e.value.code == L.JC_ERR_NONFINITE
+
+
+def test_maxiter_status():
+    say("maxiter")
+    n = (24, 24, 24)
+    with Solver(n, block_dims=(12, 12, 12)) as s:
+        s.load(synth.boundary_field(n))
+        info = s.solve(rtol=1e-10, max_iter=50, check_every=10)
+    assert info["status"] == L.JC_MAXITER and info["iters"] == 50 and info["rel_resid"] > 1e-10
+
+
+def test_kernel_timing_counts():
+    say("timing")
+    n = (64, 64, 64)
+    with Solver(n, block_dims=(32, 32, 32)) as s:
+        s.load(synth.boundary_field(n))
+        s.set_timing(True)
+        s.iterate(7)
+        ms, k = s.kernel_time(L.JC_K_SWEEP)
+        assert k == 7 and ms > 0
+        assert s.kernel_time(L.JC_K_PACK)[1] == 7
+        assert s.kernel_time(L.JC_K_EXCHANGE)[1] == 7
+
+
+# --------------------------------------------------------- full-size cases
+
+def test_512_decomposed_full_size():
+    """512^3 as 2x2x2 blocks of 256^3, the benchmarked launch configuration:
+    sampled cells after 6 iterations equal the oracle's local computation;
+    1000 iterations equal the single-block run bit for bit and obey the
+    maximum principle."""
+    n = (512, 512, 512)
+    say("512^3 2x2x2 sampled + bitwise vs single block")
+    u0 = synth.boundary_field(n, seed=12416)
+    with Solver(n, block_dims=(256, 256, 256), mode="staged") as s:
+        s.load(u0)
+        s.iterate(6)
+        got = s.store().cpu().numpy()
+        rng = np.random.default_rng(0)
+        cells = [tuple(int(v) for v in rng.integers(1, 513, 3)) for _ in range(40)]
+        cells += [(256, 256, 256), (257, 256, 256), (256, 257, 257), (1, 1, 1), (512, 512, 512),
+                  (1, 256, 257), (257, 1, 512), (256, 512, 1)]
+        for c in cells:
+            assert got[c] == local_oracle(u0, None, c, 6), c
+        s.iterate(994)
+        dec = s.store().cpu().numpy()
+    assert dec.max() <= u0.max() and dec[1:-1, 1:-1, 1:-1].min() >= 0.0
+    with Solver(n, mode="staged") as one:
+        one.load(u0)
+        one.iterate(1000)
+        single = one.store().cpu().numpy()
+    assert np.array_equal(dec, single)
+
+
+@pytest.mark.parametrize("variant", ["uniform", "uneven"])
+def test_768_overdecomposed_full_size(variant):
+    """768^3 in 512 blocks of 96^3 (or the seeded uneven rectilinear cuts),
+    fused, 500 iterations: bitwise equal to one block of the same grid."""
+    n = (768, 768, 768)
+    say("768^3", variant)
+    u0 = synth.boundary_field(n, seed=12416)
+    kw = dict(block_dims=(96, 96, 96)) if variant == "uniform" else \
+        dict(cuts=[synth.uneven_cuts(768, 32, 160, seed=12416, axis=a) for a in range(3)])
+    with Solver(n, mode="fused", **kw) as s:
+        s.load(u0)
+        s.iterate(500)
+        dec = s.store().cpu().numpy()
+    with Solver(n, mode="staged") as one:
+        one.load(u0)
+        one.iterate(500)
+        single = one.store().cpu().numpy()
+    assert np.array_equal(dec, single)
