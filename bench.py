@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--workload", default="512_2x2x2", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
     ap.add_argument("--seed", type=int, default=12416)
+    ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")
+    ap.add_argument("--z-chunk", type=int, default=0, help="planes per tile (0: library default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -50,14 +52,27 @@ def parse():
 
 
 def copy_probe():
+    """A plain device copy of known size: its HBM counters calibrate the
+    sweep's, and its rate is the practical streaming ceiling."""
     import torch
     n = 1 << 28                                   # 2 GiB of float64
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(5):
+    for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "launches": 3 + reps, "ms_per_copy": round(ms, 4),
+                      "copy_gbs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}))
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -115,7 +130,7 @@ def main():
         kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
     print("[bench] workload %s mode %s: building inputs" % (args.workload, mode), file=sys.stderr, flush=True)
     u0 = synth.boundary_field(grid, seed=args.seed)
-    s = Solver(grid, mode=mode, use_graphs=False, **kw)
+    s = Solver(grid, mode=mode, use_graphs=False, tile_y=args.tile_y, z_chunk=args.z_chunk, **kw)
     s.load(u0)
     del u0
     nb = s.num_blocks

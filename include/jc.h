@@ -208,8 +208,10 @@ int64_t jc_num_items(const jc_ctx* ctx);
  * z*plane + y*pitch + x), out[16] current copy (0/1, valid once bound). */
 int jc_block_info(const jc_ctx* ctx, int64_t i, int64_t out[17]);
 /* out = {src_block, src_face, dst_block, dst_face, count, slow, fast,
- *        buffer byte offset in the arena}. */
-int jc_pair_info(const jc_ctx* ctx, int64_t i, int64_t out[8]);
+ *        byte offset in the arena of the send buffer, of the receive
+ *        buffer, row length ld}.  A buffer holds value (s, f) of the
+ *        shared plane at element s * ld + f (ld = fast rounded up to even). */
+int jc_pair_info(const jc_ctx* ctx, int64_t i, int64_t out[10]);
 /* Iterations performed since the last jc_load_field(U). */
 int64_t jc_iterations(const jc_ctx* ctx);
 /* Current tile shape and launch parameters: {tile_x, tile_y, z_chunk, items}. */

@@ -90,6 +90,9 @@ SIGNATURES = {
 
 
 def _load():
+    # torch ships its own HIP runtime; load it first so that libjc binds to
+    # that same runtime (one runtime per process: shared memory and streams)
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libjc.so is not built (%s); run `python -m paper_2102_12416_amd.build`"
                           % LIB_PATH)

@@ -66,11 +66,11 @@ struct HostBlock {
 
 struct HostPair {
     int src_block, src_face, dst_block, dst_face;
-    int64_t slow, fast, count;
+    int64_t slow, fast, count, span;
     size_t buf_off[2];
 };
 
-const int kTileYCandidates[] = {1, 2, 4, 8, 16};
+const int kTileYCandidates[] = {4, 8, 16, 32};
 constexpr int kMinZChunk = 16;
 
 }  // namespace
@@ -82,7 +82,7 @@ struct jc_ctx {
     std::vector<HostBlock> blocks;
     std::vector<HostPair> pairs;
     int64_t max_slow = 0, max_fast = 0, max_count = 0;
-    int tile_y = 4;
+    int tile_y = 8;
     int z_chunk = 0;
     std::vector<Item> items;
     int64_t max_items = 0;
@@ -140,14 +140,14 @@ int64_t items_for(const jc_ctx* c, int ty, int zc)
     return total;
 }
 
-// Default tile: 4 rows; z chunks halved from the full depth until the
+// Default tile: 8 rows; z chunks halved from the full depth until the
 // launch has at least 4096 tiles (16 per compute unit) or chunks reach 16.
 void default_tiles(const jc_ctx* c, int* ty, int* zc)
 {
     int64_t maxz = 1;
     for (const HostBlock& b : c->blocks)
         maxz = std::max(maxz, b.n[2]);
-    int t = c->opt.tile_y > 0 ? c->opt.tile_y : 4;
+    int t = c->opt.tile_y > 0 ? c->opt.tile_y : 8;
     int z = c->opt.z_chunk > 0 ? c->opt.z_chunk : (int)std::min<int64_t>(maxz, 1 << 20);
     if (c->opt.z_chunk <= 0) {
         while (z > kMinZChunk && items_for(c, t, z) < 4096)
@@ -189,7 +189,7 @@ int validate_options(const jc_options* opt)
         for (int t : kTileYCandidates)
             ok = ok || t == opt->tile_y;
         if (!ok)
-            return fail(JC_ERR_INVALID, "options.tile_y must be 0, 1, 2, 4, 8 or 16");
+            return fail(JC_ERR_INVALID, "options.tile_y must be 0, 4, 8, 16 or 32");
     }
     if (opt->z_chunk < 0)
         return fail(JC_ERR_INVALID, "options.z_chunk must be >= 0");
@@ -267,6 +267,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
             else if (f == jc::YM || f == jc::YP) { p.slow = b.n[2]; p.fast = b.n[0]; }
             else { p.slow = b.n[1]; p.fast = b.n[0]; }
             p.count = p.slow * p.fast;
+            p.span = p.slow * jc::face_ld(p.fast);
             b.pair_out[f] = (int)c->pairs.size();
             c->pairs.push_back(p);
         }
@@ -276,7 +277,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         c->blocks[p.dst_block].pair_in[p.dst_face] = q;
         c->max_slow = std::max(c->max_slow, p.slow);
         c->max_fast = std::max(c->max_fast, p.fast);
-        c->max_count = std::max(c->max_count, p.count);
+        c->max_count = std::max(c->max_count, p.span);
     }
     if (c->max_slow > 65535)
         return fail(JC_ERR_INVALID, "a shared block face is longer than 65535 along its slow axis");
@@ -287,7 +288,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
     default_tiles(c, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
-    c->max_items = std::max<int64_t>((int64_t)c->items.size(), items_for(c, 1, kMinZChunk));
+    c->max_items = std::max<int64_t>((int64_t)c->items.size(), items_for(c, 4, kMinZChunk));
     if (c->max_items > (int64_t)1 << 30)
         return fail(JC_ERR_INVALID, "work list too long");
     // arena layout
@@ -307,7 +308,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         if (c->opt.with_source) { b.b_off = off; off += bytes; }
     }
     for (HostPair& p : c->pairs) {
-        const size_t bytes = align_up(sizeof(double) * (size_t)p.count, kAlign);
+        const size_t bytes = align_up(sizeof(double) * (size_t)p.span, kAlign);
         p.buf_off[0] = off; off += bytes;
         p.buf_off[1] = off; off += bytes;
     }
@@ -450,7 +451,7 @@ int do_sweep(jc_ctx* c, bool fused, bool resid)
 {
     int st = timed(c, fused ? JC_K_FUSED : JC_K_SWEEP, [&] {
         return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_y,
-                                fused, resid, true, c->d_partials(), c->stream);
+                                fused, resid, true, c->opt.with_source != 0, c->d_partials(), c->stream);
     });
     if (st != JC_OK)
         return st;
@@ -532,7 +533,7 @@ int residual_now(jc_ctx* c, double* l2)
     }
     int st = timed(c, JC_K_RESIDUAL, [&] {
         return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_y, fused,
-                                true, false, c->d_partials(), c->stream);
+                                true, false, c->opt.with_source != 0, c->d_partials(), c->stream);
     });
     if (st != JC_OK)
         return st;
@@ -785,7 +786,7 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
         PairDesc& d = c->hpairs[q];
         d.src_block = hp.src_block; d.src_face = hp.src_face;
         d.dst_block = hp.dst_block; d.dst_face = hp.dst_face;
-        d.slow = (int32_t)hp.slow; d.fast = (int32_t)hp.fast; d.count = hp.count;
+        d.slow = (int32_t)hp.slow; d.fast = (int32_t)hp.fast; d.count = hp.count; d.span = hp.span;
         d.buf[0] = reinterpret_cast<double*>(c->arena + hp.buf_off[0]);
         d.buf[1] = reinterpret_cast<double*>(c->arena + hp.buf_off[1]);
     }
@@ -1032,13 +1033,14 @@ int jc_block_info(const jc_ctx* c, int64_t i, int64_t out[17])
     return JC_OK;
 }
 
-int jc_pair_info(const jc_ctx* c, int64_t i, int64_t out[8])
+int jc_pair_info(const jc_ctx* c, int64_t i, int64_t out[10])
 {
     if (!c || !out || i < 0 || i >= (int64_t)c->pairs.size())
         return fail(JC_ERR_INVALID, "bad context or pair index");
     const HostPair& p = c->pairs[i];
     out[0] = p.src_block; out[1] = p.src_face; out[2] = p.dst_block; out[3] = p.dst_face;
     out[4] = p.count; out[5] = p.slow; out[6] = p.fast; out[7] = (int64_t)p.buf_off[0];
+    out[8] = (int64_t)p.buf_off[1]; out[9] = jc::face_ld(p.fast);
     return JC_OK;
 }
 

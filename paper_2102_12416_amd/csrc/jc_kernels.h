@@ -7,7 +7,7 @@
 
 namespace jc {
 
-// Tile widths: one 64-lane wavefront covers 64 consecutive x cells of one row.
+// Tiles are 64 x cells wide (32 threads, two cells each, per row).
 constexpr int kTileX = 64;
 
 // Sweep / residual over a work list.  parity selects the input copy of
@@ -16,7 +16,7 @@ constexpr int kTileX = 64;
 // slot.  resid: write one partial sum of r^2 per item into partials.
 // store: write the new iterate (false = residual only).
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
-                        int tile_y, bool fused, bool resid, bool store, double* partials,
+                        int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
                         hipStream_t s);
 
 // Sum partials[ranges[m] .. ranges[m+1]) in a fixed order into out[m], m < nmembers.

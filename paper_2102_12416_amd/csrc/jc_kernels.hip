@@ -3,12 +3,11 @@
 // Jacobi3D, paper section 4.3: each block of the decomposition is swept
 // with the 7-point stencil after its halo has been exchanged with up to
 // six neighbours.  The sweep marches along z through a tile of 64 x cells
-// (one wavefront per row) and tile_y rows, keeping the z-1, z and z+1
-// values of its own column in registers, so that every interior value is
-// fetched from HBM once per sweep; the x and y neighbours of a plane are
-// re-read from the L1/L2 lines the neighbouring lanes and rows just
-// brought in.  The stencil is not a contraction, so no matrix cores are
-// used: the kernel is bound by HBM bandwidth (16 bytes per cell update).
+// by tile_y rows, staging each plane in LDS and keeping the z-1, z and z+1
+// values of its own cells in registers, so that every interior value is
+// fetched from HBM once per sweep.  The stencil is not a contraction, so
+// no matrix cores are used: the kernel is bound by HBM bandwidth (16 bytes
+// per cell update in FP64).
 //
 // Bit-exactness: the neighbour sum is formed in one fixed order and
 // divided by 6 with an IEEE division; the library is built with
@@ -32,6 +31,35 @@ __device__ __forceinline__ int logical_block(int bid, int nblocks)
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Global-memory views of the generic pointers held in the tables: loads
+// and stores through them are global (not flat) instructions, which count
+// only against the vector-memory counter, so waiting for an LDS write does
+// not also wait for every load still in flight.
+#define JC_GLOBAL __attribute__((address_space(1)))
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// 16-byte load of the aligned pair at p
+__device__ __forceinline__ double2 ld2(const double* p)
+{
+    const v2d v = *(const v2d JC_GLOBAL*)(p);
+    return make_double2(v.x, v.y);
+}
+
+// 16-byte store of (a, b) to the aligned pair at p
+__device__ __forceinline__ void st2(double* p, double a, double b)
+{
+    v2d v;
+    v.x = a;
+    v.y = b;
+    *(v2d JC_GLOBAL*)(p) = v;
+}
+
+__device__ __forceinline__ void st1(double* p, double a)
+{
+    *(double JC_GLOBAL*)(p) = a;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int o = 32; o > 0; o >>= 1)
@@ -39,120 +67,247 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int TY, bool FUSED, bool RES, bool STORE>
-__global__ void __launch_bounds__(64 * TY)
+// One work-group sweeps a tile of 64 x cells by TY rows of one block,
+// marching along z.  Each thread owns two adjacent x cells of one row
+// (one 16-byte load per plane: cell x = 1 of every row starts a 128-byte
+// line).  Per plane the work-group writes the plane -- its cells plus a
+// one-cell halo ring -- into an LDS tile, synchronises once (the tile is
+// double-buffered by plane parity) and reads its x and y neighbours from
+// LDS; the z-1 / z / z+1 values of its own cells stay in registers.
+//
+// Every thread issues the same global loads in every iteration, with
+// clamped addresses where it has nothing to fetch, so that the loads of
+// the next two planes stay in flight while the current one is computed
+// (no divergent branch around a load).  The halo ring is fetched by
+// threads with a halo role: threads 0-31 the row above the tile, 32-63
+// the row below, the next TY threads the column left of it and the next
+// TY the column right of it; the rest re-load their own cells.
+//
+// FUSED: ghost cells of faces that have a neighbour block are read from
+// the neighbour's face buffer of the input slot (the pairing's pre-posted
+// receive side), and every face cell written is also written to this
+// block's face buffer of the output slot -- pack, exchange and unpack
+// folded into the sweep.  RES: accumulate r^2 of the input iterate,
+// r = (b + s) - 6u, into one partial per work-group.  STORE: write the
+// new iterate (off: residual only).  SRC: the block has a source b.
+template <int TY, bool FUSED, bool RES, bool STORE, bool SRC>
+__global__ void __launch_bounds__(32 * TY)
 k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int nitems,
         int parity, double* __restrict__ partials)
 {
+    static_assert(TY >= 4 && 32 * TY >= 64 + 2 * TY, "halo roles need 64 + 2 TY threads");
+    constexpr int NT = 32 * TY;
+    constexpr int LW = 68;   // LDS row: col 1 = x0, cols 2..65 = x0+1..x0+64, up to col 66
+    __shared__ double S[2][TY + 2][LW];
+    __shared__ double wsum[NT / 64];
+
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= nitems)
-        return;                              // uniform over the work-group
+        return;                                   // uniform over the work-group
     const Item it = items[id];
     const BlockDesc* B = blocks + it.block;
     const int p = parity ^ it.flip;
     const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
-    const int lx = threadIdx.x & 63;
-    const int ly = threadIdx.x >> 6;
-    const int x = it.x0 + lx + 1;
-    const int y = it.y0 + ly + 1;
+    const int t = threadIdx.x;
+    const int lx = t & 31;
+    const int ly = t >> 5;
+    const int x0 = it.x0, y0 = it.y0;
+    const int x_end = min(x0 + 64, nx);           // last x cell of the tile
+    const int y_end = min(y0 + TY, ny);           // last row of the tile
+    const int ly_last = y_end - y0 - 1;
+    const int xa = x0 + 2 * lx + 1;               // this thread's cells: xa, xa + 1
+    const int y = y0 + ly + 1;
+    const bool row_ok = y <= ny;
+    const bool a_ok = row_ok && xa <= nx;
+    const bool b_ok = row_ok && xa + 1 <= nx;
+    const int xlast = (nx - 1) | 1;               // start of the last aligned pair of a row
+    const int xa_c = min(xa, xlast);
+    const int y_c = min(y, ny);
     const int64_t pitch = B->pitch;
     const int64_t plane = B->plane;
+    const int64_t ldx = face_ld(ny);              // x-face buffers: (z, y) rows
+    const int64_t ldy = face_ld(nx);              // y- and z-face buffers: (z, x) / (y, x) rows
     const double* __restrict__ src = B->u[p];
     double* __restrict__ dst = B->u[p ^ 1];
-    const double* __restrict__ bsrc = B->b;
+
+    // own pair (xa_c, y_c) at plane zz
+    const double* own = src + (int64_t)y_c * pitch + xa_c;
+    const double* own_lo = own;                                   // plane 0
+    const double* own_hi = own + (int64_t)(nz + 1) * plane;       // plane nz + 1
+    if (FUSED) {
+        const int64_t zi = (int64_t)(y_c - 1) * ldy + (xa_c - 1);
+        if (B->gin[ZM][p]) own_lo = B->gin[ZM][p] + zi;
+        if (B->gin[ZP][p]) own_hi = B->gin[ZP][p] + zi;
+    }
+    auto own_at = [&](int zz) -> double2 {
+        const double* a = own + (int64_t)zz * plane;
+        if (FUSED) {
+            a = (zz == 0) ? own_lo : a;
+            a = (zz == nz + 1) ? own_hi : a;
+        }
+        return ld2(a);
+    };
+    const double* bown = SRC ? B->b + (int64_t)y_c * pitch + xa_c : nullptr;
+
+    // halo role: the pair at hbase + zz * hstride (16-byte aligned)
+    const int role = t < 32 ? 0 : t < 64 ? 1 : t < 64 + TY ? 2 : t < 64 + 2 * TY ? 3 : 4;
+    const double* hbase = own;
+    int64_t hstride = plane;
+    int hrow = 0, hcol = 0, hcomp = 0;
+    bool hv0 = false, hv1 = false;
+    if (role <= 1) {
+        const int hl = t & 31;
+        const int hx = x0 + 2 * hl + 1;
+        const int hx_c = min(hx, xlast);
+        const int hy = role == 0 ? y0 : y_end + 1;
+        hv0 = hx <= x_end;
+        hv1 = hx + 1 <= x_end;
+        hbase = src + (int64_t)hy * pitch + hx_c;
+        if (FUSED) {
+            const double* g = (hy == 0) ? B->gin[YM][p] : (hy == ny + 1) ? B->gin[YP][p] : nullptr;
+            if (g) {
+                hbase = g - ldy + (hx_c - 1);     // value (z - 1, x - 1)
+                hstride = ldy;
+            }
+        }
+        hrow = role == 0 ? 0 : ly_last + 2;
+        hcol = 2 * hl + 2;
+    } else if (role <= 3) {
+        const int r = t - 64 - (role == 3 ? TY : 0);
+        const int hy = y0 + r + 1;
+        hv0 = hy <= y_end;
+        const int hy_c = min(hy, ny);
+        const int hx = role == 2 ? x0 : x_end + 1;
+        const int ps = (hx & 1) ? hx : hx - 1;    // aligned pair holding hx
+        hcomp = (hx & 1) ? 0 : 1;
+        hbase = src + (int64_t)hy_c * pitch + ps;
+        if (FUSED) {
+            const double* g = (hx == 0) ? B->gin[XM][p] : (hx == nx + 1) ? B->gin[XP][p] : nullptr;
+            if (g) {
+                const int fi = hy_c - 1;          // value (z - 1, y - 1)
+                hbase = g - ldx + (fi & ~1);
+                hcomp = fi & 1;
+                hstride = ldx;
+            }
+        }
+        hrow = r + 1;
+        hcol = role == 2 ? 1 : x_end - x0 + 2;
+    }
+    auto halo_at = [&](int zz) -> double2 {
+        return ld2(hbase + (int64_t)zz * hstride);
+    };
+
+    const int zf = it.z0 + 1;                     // first plane of the tile
+    const int zl = it.z0 + it.zlen;               // last plane of the tile
+    double2 zm = own_at(zf - 1);
+    double2 c = own_at(zf);
+    double2 zp = own_at(zf + 1);
+    double2 h = halo_at(zf);
+    double2 bc = make_double2(0.0, 0.0);
+    if (SRC)
+        bc = ld2(bown + (int64_t)zf * plane);
 
     double acc = 0.0;
-    if (x <= nx && y <= ny) {
-        const double* gxm = nullptr; const double* gxp = nullptr;
-        const double* gym = nullptr; const double* gyp = nullptr;
-        const double* gzm = nullptr; const double* gzp = nullptr;
-        double* oxm = nullptr; double* oxp = nullptr;
-        double* oym = nullptr; double* oyp = nullptr;
-        double* ozm = nullptr; double* ozp = nullptr;
-        if (FUSED) {
-            gxm = B->gin[XM][p]; gxp = B->gin[XP][p];
-            gym = B->gin[YM][p]; gyp = B->gin[YP][p];
-            gzm = B->gin[ZM][p]; gzp = B->gin[ZP][p];
-            oxm = B->gout[XM][p ^ 1]; oxp = B->gout[XP][p ^ 1];
-            oym = B->gout[YM][p ^ 1]; oyp = B->gout[YP][p ^ 1];
-            ozm = B->gout[ZM][p ^ 1]; ozp = B->gout[ZP][p ^ 1];
+    for (int z = zf; z <= zl; ++z) {
+        // the next planes go in flight first; the last iteration re-reads
+        // planes it already holds (cache hits) instead of branching
+        const int zn = min(z + 1, zl);
+        const double2 zq = own_at(min(z + 2, zl + 1));
+        const double2 hn = halo_at(zn);
+        double2 bn = make_double2(0.0, 0.0);
+        if (SRC)
+            bn = ld2(bown + (int64_t)zn * plane);
+
+        double (*T)[LW] = S[z & 1];
+        if (a_ok) {
+            T[ly + 1][2 * lx + 2] = c.x;
+            if (b_ok)
+                T[ly + 1][2 * lx + 3] = c.y;
         }
-        int z = it.z0 + 1;
-        const int64_t col = (int64_t)y * pitch + x;
-        const int64_t zf = (int64_t)(y - 1) * nx + (x - 1);     // index in a z-face buffer
-        const double* pc = src + (int64_t)z * plane + col;
-        const double* azm = (FUSED && z == 1 && gzm) ? gzm + zf : pc - plane;
-        double zm = *azm;
-        double c = pc[0];
-        const int zend = z + it.zlen;
-        for (; z < zend; ++z, pc += plane) {
-            const int64_t xf = (int64_t)(z - 1) * ny + (y - 1);  // x-face buffer index
-            const int64_t yf = (int64_t)(z - 1) * nx + (x - 1);  // y-face buffer index
-            const double* azp = (FUSED && z == nz && gzp) ? gzp + zf : pc + plane;
-            const double* axm = (FUSED && x == 1 && gxm) ? gxm + xf : pc - 1;
-            const double* axp = (FUSED && x == nx && gxp) ? gxp + xf : pc + 1;
-            const double* aym = (FUSED && y == 1 && gym) ? gym + yf : pc - pitch;
-            const double* ayp = (FUSED && y == ny && gyp) ? gyp + yf : pc + pitch;
-            const double zp = *azp;
-            const double xm = *axm;
-            const double xp = *axp;
-            const double ym = *aym;
-            const double yp = *ayp;
-            double s = xm + xp;
-            s = s + ym;
-            s = s + yp;
-            s = s + zm;
-            s = s + zp;
-            const int64_t at = (int64_t)z * plane + col;
-            double bb = 0.0;
-            if (bsrc)
-                bb = bsrc[at];
-            if (RES) {
-                const double r = bsrc ? (bb + s) - 6.0 * c : s - 6.0 * c;
-                acc = acc + r * r;
-            }
-            if (STORE) {
-                const double v = bsrc ? (s + bb) / 6.0 : s / 6.0;
-                dst[at] = v;
-                if (FUSED) {
-                    if (x == 1 && oxm) oxm[xf] = v;
-                    if (x == nx && oxp) oxp[xf] = v;
-                    if (y == 1 && oym) oym[yf] = v;
-                    if (y == ny && oyp) oyp[yf] = v;
-                    if (z == 1 && ozm) ozm[zf] = v;
-                    if (z == nz && ozp) ozp[zf] = v;
-                }
-            }
-            zm = c;
-            c = zp;
+        if (role <= 1) {
+            if (hv0) T[hrow][hcol] = h.x;
+            if (hv1) T[hrow][hcol + 1] = h.y;
+        } else if (role <= 3 && hv0) {
+            T[hrow][hcol] = hcomp ? h.y : h.x;
         }
+        __syncthreads();
+        const double xm_a = T[ly + 1][2 * lx + 1];
+        const double xp_a = b_ok ? c.y : T[ly + 1][2 * lx + 3];
+        double sa = xm_a + xp_a;
+        sa = sa + T[ly][2 * lx + 2];
+        sa = sa + T[ly + 2][2 * lx + 2];
+        sa = sa + zm.x;
+        sa = sa + zp.x;
+        double sb = c.x + T[ly + 1][2 * lx + 4];
+        sb = sb + T[ly][2 * lx + 3];
+        sb = sb + T[ly + 2][2 * lx + 3];
+        sb = sb + zm.y;
+        sb = sb + zp.y;
+        if (RES) {
+            const double ra = SRC ? (bc.x + sa) - 6.0 * c.x : sa - 6.0 * c.x;
+            const double rb = SRC ? (bc.y + sb) - 6.0 * c.y : sb - 6.0 * c.y;
+            acc = acc + (a_ok ? ra * ra : 0.0);
+            acc = acc + (b_ok ? rb * rb : 0.0);
+        }
+        if (STORE) {
+            const double va = SRC ? (sa + bc.x) / 6.0 : sa / 6.0;
+            // past the last cell of a row the pair's second slot is the
+            // x = nx + 1 ghost: write back the value it already holds
+            const double vb = b_ok ? (SRC ? (sb + bc.y) / 6.0 : sb / 6.0) : c.y;
+            if (a_ok)
+                st2(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
+            if (FUSED) {
+                const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
+                const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
+                const int64_t zfi = (int64_t)(y - 1) * ldy + (xa - 1);
+                double* oxm = B->gout[XM][p ^ 1];
+                double* oxp = B->gout[XP][p ^ 1];
+                double* oym = B->gout[YM][p ^ 1];
+                double* oyp = B->gout[YP][p ^ 1];
+                double* ozm = B->gout[ZM][p ^ 1];
+                double* ozp = B->gout[ZP][p ^ 1];
+                // a face row's padding slot takes the second value of a
+                // pair that ends past the face (ld is even)
+                if (a_ok && xa == 1 && oxm) st1(oxm + xfi, va);
+                if (a_ok && xa == nx && oxp) st1(oxp + xfi, va);
+                if (b_ok && xa + 1 == nx && oxp) st1(oxp + xfi, vb);
+                if (a_ok && y == 1 && oym) st2(oym + yfi, va, vb);
+                if (a_ok && y == ny && oyp) st2(oyp + yfi, va, vb);
+                if (a_ok && z == 1 && ozm) st2(ozm + zfi, va, vb);
+                if (a_ok && z == nz && ozp) st2(ozp + zfi, va, vb);
+            }
+        }
+        zm = c;
+        c = zp;
+        zp = zq;
+        h = hn;
+        bc = bn;
     }
     if (RES) {
-        __shared__ double wsum[TY];
         const double w = wave_sum(acc);
-        if ((threadIdx.x & 63) == 0)
-            wsum[threadIdx.x >> 6] = w;
+        if ((t & 63) == 0)
+            wsum[t >> 6] = w;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int i = 0; i < TY; ++i)
-                t = t + wsum[i];
-            partials[id] = t;
+        if (t == 0) {
+            double sum = 0.0;
+            for (int i = 0; i < NT / 64; ++i)
+                sum = sum + wsum[i];
+            partials[id] = sum;
         }
     }
 }
 
-template <int TY>
+template <int TY, bool SRC>
 hipError_t sweep_ty(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
                     bool resid, bool store, double* partials, hipStream_t s)
 {
     const int grid = ((nitems + 7) / 8) * 8;
-    const dim3 bs(64 * TY);
-#define JC_SWEEP_CASE(F, R, S)                                                         \
-    if (fused == F && resid == R && store == S) {                                     \
-        hipLaunchKernelGGL((k_sweep<TY, F, R, S>), dim3(grid), bs, 0, s, blocks, items, \
-                           nitems, parity, partials);                                 \
-        return hipGetLastError();                                                     \
+    const dim3 bs(32 * TY);
+#define JC_SWEEP_CASE(F, R, S)                                                                \
+    if (fused == F && resid == R && store == S) {                                            \
+        hipLaunchKernelGGL((k_sweep<TY, F, R, S, SRC>), dim3(grid), bs, 0, s, blocks, items,  \
+                           nitems, parity, partials);                                        \
+        return hipGetLastError();                                                            \
     }
     JC_SWEEP_CASE(false, false, true)
     JC_SWEEP_CASE(false, true, true)
@@ -162,6 +317,14 @@ hipError_t sweep_ty(const BlockDesc* blocks, const Item* items, int nitems, int 
     JC_SWEEP_CASE(true, true, false)
 #undef JC_SWEEP_CASE
     return hipErrorInvalidValue;
+}
+
+template <int TY>
+hipError_t sweep_src(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
+                     bool resid, bool store, bool src, double* partials, hipStream_t s)
+{
+    return src ? sweep_ty<TY, true>(blocks, items, nitems, parity, fused, resid, store, partials, s)
+               : sweep_ty<TY, false>(blocks, items, nitems, parity, fused, resid, store, partials, s);
 }
 
 // Fixed-order sum of one member's partials: each thread adds a strided
@@ -210,7 +373,7 @@ k_pack(const BlockDesc* __restrict__ blocks, const PairDesc* __restrict__ pairs,
     if (slow >= P.slow || fast >= P.fast)
         return;
     const BlockDesc& B = blocks[P.src_block];
-    P.buf[slot][(int64_t)slow * P.fast + fast] = B.u[parity][face_cell(B, P.src_face, slow, fast, 0)];
+    P.buf[slot][(int64_t)slow * face_ld(P.fast) + fast] = B.u[parity][face_cell(B, P.src_face, slow, fast, 0)];
 }
 
 __global__ void __launch_bounds__(256)
@@ -222,22 +385,21 @@ k_unpack(const BlockDesc* __restrict__ blocks, const PairDesc* __restrict__ pair
     if (slow >= P.slow || fast >= P.fast)
         return;
     const BlockDesc& B = blocks[P.dst_block];
-    B.u[parity][face_cell(B, P.dst_face, slow, fast, 1)] = P.buf[1][(int64_t)slow * P.fast + fast];
+    B.u[parity][face_cell(B, P.dst_face, slow, fast, 1)] = P.buf[1][(int64_t)slow * face_ld(P.fast) + fast];
 }
 
 // The pairing's transfer: every send buffer into the receive buffer
-// pre-posted for it.  Buffers are 256-byte aligned; 16-byte vectors.
+// pre-posted for it.  Buffers are 256-byte aligned with an even number of
+// elements: 16-byte vectors.
 __global__ void __launch_bounds__(256)
 k_exchange(const PairDesc* __restrict__ pairs)
 {
     const PairDesc& P = pairs[blockIdx.y];
-    const int64_t n2 = P.count >> 1;
+    const int64_t n2 = P.span >> 1;
     const double2* __restrict__ a = reinterpret_cast<const double2*>(P.buf[0]);
     double2* __restrict__ b = reinterpret_cast<double2*>(P.buf[1]);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (int64_t)gridDim.x * 256)
         b[i] = a[i];
-    if ((P.count & 1) && blockIdx.x == 0 && threadIdx.x == 0)
-        P.buf[1][P.count - 1] = P.buf[0][P.count - 1];
 }
 
 // Rows of every block's padded array: blockIdx.y = block; the work-group
@@ -298,17 +460,16 @@ k_gather(const BlockDesc* __restrict__ blocks, double* __restrict__ g, int64_t g
 }  // namespace
 
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
-                        int tile_y, bool fused, bool resid, bool store, double* partials,
+                        int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
                         hipStream_t s)
 {
     if (nitems <= 0)
         return hipSuccess;
     switch (tile_y) {
-    case 1: return sweep_ty<1>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 2: return sweep_ty<2>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 4: return sweep_ty<4>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 8: return sweep_ty<8>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 16: return sweep_ty<16>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 4: return sweep_src<4>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
+    case 8: return sweep_src<8>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
+    case 16: return sweep_src<16>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
+    case 32: return sweep_src<32>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

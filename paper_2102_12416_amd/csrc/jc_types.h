@@ -47,13 +47,20 @@ struct BlockDesc {
 // receive side pre-posted for it (dst block, opposite face).  buf[0] is
 // the send buffer, buf[1] the receive buffer; in fused mode the two are
 // the two parity slots the producer and consumer alternate between.
+// Buffers hold the shared plane slow-major with rows padded to an even
+// length ld = fast rounded up to 2 (so every pair of cells starting at an
+// even index is a 16-byte aligned vector): value (s, f) at s * ld + f.
 struct PairDesc {
     int32_t src_block, src_face, dst_block, dst_face;
     int32_t slow, fast;      // extents of the shared plane, slow-major
-    int64_t count;           // slow * fast
+    int64_t count;           // slow * fast values
+    int64_t span;            // slow * ld elements per buffer
     double* buf[2];
     void* lbuf[2];           // low-precision buffers for the correction
 };
+
+// Row length of a face buffer whose fast extent is `fast`.
+inline constexpr int64_t face_ld(int64_t fast) { return (fast + 1) & ~(int64_t)1; }
 
 // A tile of the work list: block, origin (0-based interior offsets), the
 // z range, and the ping-pong flip of its owner relative to the launch.

@@ -178,11 +178,17 @@ class Solver:
                     u_off=(v[14], v[15]), parity=v[16])
 
     def pair_info(self, i):
-        out = (ctypes.c_int64 * 8)()
+        out = (ctypes.c_int64 * 10)()
         check(L.lib.jc_pair_info(self._ctx, int(i), out))
         v = list(out)
         return dict(src_block=v[0], src_face=v[1], dst_block=v[2], dst_face=v[3], count=v[4], slow=v[5],
-                    fast=v[6], buf_off=v[7])
+                    fast=v[6], buf_off=v[7], recv_off=v[8], ld=v[9])
+
+    def face_buffer(self, q, slot):
+        """Values of pair q's send (slot 0) or receive (slot 1) buffer, (slow, fast)."""
+        p = self.pair_info(q)
+        flat = self.arena_view(p["buf_off"] if slot == 0 else p["recv_off"], p["slow"] * p["ld"])
+        return flat.view(p["slow"], p["ld"])[:, :p["fast"]]
 
     def tile_info(self):
         out = (ctypes.c_int64 * 4)()

@@ -67,7 +67,7 @@ def blocks_of(ctx):
 def pairs_of(ctx):
     out = []
     for i in range(L.lib.jc_num_pairs(ctx)):
-        v = (ctypes.c_int64 * 8)()
+        v = (ctypes.c_int64 * 10)()
         check(L.lib.jc_pair_info(ctx, i, v))
         out.append(list(v))
     return out
@@ -97,7 +97,9 @@ def test_uniform_decomposition_and_pairing(grid, bd, nb, npairs):
         # every directed pair has its reverse, with opposite faces and equal counts
         table = {(p[0], p[1]): p for p in pairs}
         for p in pairs:
-            src, f, dst, g, count, slow, fast, _ = p
+            src, f, dst, g, count, slow, fast, off0, off1, ld = p
+            assert ld % 2 == 0 and fast <= ld <= fast + 1
+            assert off0 % 256 == 0 and off1 % 256 == 0 and off1 >= off0 + slow * ld * 8
             assert g == f ^ 1
             rev = table[(dst, g)]
             assert rev[2] == src and rev[3] == f and rev[4] == count

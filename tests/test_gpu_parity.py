@@ -124,12 +124,9 @@ def test_pack_exchange_unpack_bitwise():
             else:
                 z = oz + (1 if f == 4 else nz)
                 plane = g[z, oy + 1:oy + ny + 1, ox + 1:ox + nx + 1]
-            count = p["count"]
-            send = s.arena_view(p["buf_off"], count).cpu()
+            send = s.face_buffer(q, 0).cpu().reshape(-1)
             assert torch.equal(send, plane.reshape(-1)), ("send", q)
-            # the receive buffer immediately follows (256-byte aligned)
-            recv_off = p["buf_off"] + ((count * 8 + 255) // 256) * 256
-            assert torch.equal(s.arena_view(recv_off, count).cpu(), send), ("recv", q)
+            assert torch.equal(s.face_buffer(q, 1).cpu().reshape(-1), send), ("recv", q)
             dst = s.block_info(p["dst_block"])
             arr = s.block_array(p["dst_block"]).cpu()
             dnx, dny, dnz = dst["n"]
@@ -165,11 +162,11 @@ def test_staged_state_machine():
         assert s.iterations == 2
 
 
-@pytest.mark.parametrize("tile_y,z_chunk", [(1, 16), (2, 0), (4, 7), (8, 0), (16, 33)])
+@pytest.mark.parametrize("tile_y,z_chunk", [(4, 16), (8, 0), (16, 7), (32, 0), (4, 33)])
 def test_tile_shapes_bitwise(tile_y, z_chunk):
     say("tile", tile_y, z_chunk)
     n = (100, 70, 66)
-    ref = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=4, z_chunk=0, mode="fused")
+    ref = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=8, z_chunk=0, mode="fused")
     got = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=tile_y, z_chunk=z_chunk, mode="fused")
     assert np.array_equal(got, ref)
 
