@@ -76,9 +76,9 @@ typedef struct jc_group jc_group;
 typedef struct jc_options {
     int mode;            /* JC_MODE_STAGED or JC_MODE_FUSED */
     int with_source;     /* 1: the context holds a source field b */
-    int ir_dtype;        /* JC_NONE (0 is treated as none too) or JC_F32/JC_BF16 with
-                            ir_enable = 1: allocate refinement buffers (d, r_lo) */
-    int ir_enable;
+    int ir_dtype;        /* storage of the refinement correction d and residual r_lo:
+                            JC_F64, JC_F32 or JC_BF16 (read only when ir_enable = 1) */
+    int ir_enable;       /* 1: allocate refinement buffers (d x 2, r_lo, face buffers) */
     int tile_y;          /* rows per tile; 0 = auto */
     int z_chunk;         /* planes per tile; 0 = auto */
     int use_graphs;      /* 1: capture jc_iterate windows as HIP graphs */
@@ -194,6 +194,53 @@ int jc_residual(jc_ctx* ctx, double* host_l2);
  * in info->status), or an error. */
 int jc_solve(jc_ctx* ctx, double rtol, int64_t max_iter, int64_t check_every,
              jc_solve_info* info);
+
+/* Mixed-precision iterative refinement with Jacobi inner sweeps.
+ * Outer step, in binary64: r = (b + s(u)) - 6u over every block, its
+ * norm (a fixed-order reduction), the stop test |r|/|r_0| <= rtol, and
+ * r_lo = r rounded to the context's ir_dtype (through binary32 for
+ * bfloat16, round to nearest even).  Inner: d_0 = 0 with zero ghosts, then
+ * inner_sweeps sweeps d' = lo((((((d(x-1)+d(x+1))+d(y-1))+d(y+1))+d(z-1))+d(z+1) + r_lo) / 6)
+ * in binary32 arithmetic (binary64 for JC_F64), with the halo of d moved
+ * through the face pairing.  Update, binary64: u += d.  Repeats until the
+ * test passes or max_inner inner sweeps were run (info->iters counts inner
+ * sweeps, info->outer residual checks, history gets |r| of every check).
+ * Needs ir_enable at creation.  Waits for the stream.  Returns JC_OK or
+ * JC_MAXITER, or an error (JC_ERR_NONFINITE on a NaN/Inf residual). */
+int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
+                jc_solve_info* info);
+
+/* ---- groups: many contexts in shared launches (batching, serving) ----- */
+
+/* A group sweeps the blocks of several bound, loaded contexts together:
+ * one launch per iteration and kernel class (binary64 with / without a
+ * source; refinement per storage format), over a joint work list with a
+ * tile shape fixed for all groups, so that each member's iterates and
+ * residual norms are bitwise the same alone and in any mix.  Members stay
+ * independent (own fields, pairing, iteration counts); paired faces move
+ * through the face buffers (fused).  Refining members (ir_enable) advance
+ * by inner sweeps: jc_group_residuals performs their outer step (update
+ * u += d if sweeps ran, binary64 residual, r_lo), jc_group_iterate their
+ * inner sweeps; a refining member must hold its iterate in copy 0.
+ * ctxs is read during the call; the contexts must outlive the group and
+ * must not be used on their own streams while the group exists.
+ * flags: bit 0 = capture jc_group_iterate windows as HIP graphs (needs a
+ * non-null stream).  Host only until jc_group_bind. */
+int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_group** out);
+/* Device scratch the group needs (joint tables, partial sums). */
+int jc_group_footprint(const jc_group* g, size_t* bytes);
+/* Attach caller-owned scratch (>= footprint, 256-byte aligned); orders the
+ * group stream after every member's queued work; uploads the tables. */
+int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes);
+/* n sweeps of every member (inner sweeps for refining members). */
+int jc_group_iterate(jc_group* g, int64_t n);
+/* |r|_2 of every member's current iterate into host_l2[members], after the
+ * outer step of refining members; waits for the stream.  JC_ERR_NONFINITE
+ * if any norm is NaN/Inf (all norms are still written). */
+int jc_group_residuals(jc_group* g, double* host_l2);
+/* Frees the group's host data, graphs and events (waits for its stream).
+ * NULL-safe.  The scratch stays the caller's. */
+void jc_group_destroy(jc_group* g);
 
 /* ---- introspection (host only) -------------------------------------- */
 

@@ -6,6 +6,6 @@ streams.  Importing it fails if libjc.so has not been built.
 """
 from . import _lib
 from ._lib import JcError
-from .solver import Solver, footprint, min_surface_parts
+from .solver import Group, Solver, footprint, min_surface_parts
 
-__all__ = ["Solver", "JcError", "footprint", "min_surface_parts", "_lib"]
+__all__ = ["Group", "Solver", "JcError", "footprint", "min_surface_parts", "_lib"]

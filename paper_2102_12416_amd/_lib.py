@@ -77,6 +77,13 @@ SIGNATURES = {
     "jc_iterate": (ctypes.c_int, [CTX, I64]),
     "jc_residual": (ctypes.c_int, [CTX, ctypes.POINTER(ctypes.c_double)]),
     "jc_solve": (ctypes.c_int, [CTX, ctypes.c_double, I64, I64, ctypes.POINTER(SolveInfo)]),
+    "jc_solve_ir": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.c_double, I64, ctypes.POINTER(SolveInfo)]),
+    "jc_group_create": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, VP, ctypes.c_int, ctypes.POINTER(VP)]),
+    "jc_group_footprint": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "jc_group_bind": (ctypes.c_int, [VP, VP, ctypes.c_size_t]),
+    "jc_group_iterate": (ctypes.c_int, [VP, I64]),
+    "jc_group_residuals": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
+    "jc_group_destroy": (None, [VP]),
     "jc_num_blocks": (I64, [CTX]),
     "jc_num_pairs": (I64, [CTX]),
     "jc_num_items": (I64, [CTX]),
@@ -94,7 +101,7 @@ def _load():
     # that same runtime (one runtime per process: shared memory and streams)
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libjc.so is not built (%s); run `python -m paper_2102_12416_amd.build`"
+        raise ImportError("libjc.so is not built (%s); run `python paper_2102_12416_amd/build.py`"
                           % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():

@@ -1,6 +1,7 @@
 """Builds libjc.so in-tree with hipcc for gfx950.
 
-Usage: python -m paper_2102_12416_amd.build
+Usage: python paper_2102_12416_amd/build.py [-v]
+(run as a file: importing the package would load the library being built)
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libjc.so")
 
-SOURCES = ["jc_kernels.hip", "jc_host.cpp"]
+SOURCES = ["jc_kernels.hip", "jc_host.cpp", "jc_group.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,161 @@
+// Internal state of a libjc context, shared by the host runtime files
+// (jc_host.cpp: one context; jc_group.cpp: several contexts per launch).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "jc.h"
+#include "jc_kernels.h"
+#include "jc_types.h"
+
+using jc::BlockDesc;
+using jc::Item;
+using jc::PairDesc;
+
+namespace jc_rt {
+
+// Record msg as this thread's last error and return code.
+int fail(int code, const std::string& msg);
+
+#define JC_HIP(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(JC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxEdge = (int64_t)1 << 30;    // per-axis limit (int32 cell indices)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+enum GhostState { GHOST_CURRENT = 0, GHOST_PACKED = 1, GHOST_EXCHANGED = 2, GHOST_STALE = 3 };
+
+struct HostBlock {
+    int64_t n[3];
+    int64_t off[3];
+    int nbr[6];
+    int pair_out[6];        // pair index whose source is this face, or -1
+    int pair_in[6];         // pair index whose destination is this face, or -1
+    int64_t pitch, plane;   // binary64 arrays
+    size_t u_off[2], b_off; // byte offsets of element (0,0,0)'s line base
+    int64_t lpitch, lplane; // refinement arrays (d, r_lo)
+    size_t d_off[2], rlo_off;
+};
+
+struct HostPair {
+    int src_block, src_face, dst_block, dst_face;
+    int64_t slow, fast, count, span;
+    size_t buf_off[2];
+    size_t lbuf_off[2];     // refinement face buffers
+};
+
+// Bytes of one element of the refinement storage format.
+inline size_t lo_size(int dtype) { return dtype == JC_F64 ? 8 : dtype == JC_F32 ? 4 : 2; }
+
+constexpr int kTileYCandidates[] = {4, 8, 16, 32};
+constexpr int kMinZChunk = 16;
+
+}  // namespace jc_rt
+
+using jc_rt::GHOST_CURRENT;
+using jc_rt::GHOST_EXCHANGED;
+using jc_rt::GHOST_PACKED;
+using jc_rt::GHOST_STALE;
+using jc_rt::HostBlock;
+using jc_rt::HostPair;
+
+struct jc_ctx {
+    int64_t grid[3] = {0, 0, 0};
+    std::vector<int64_t> cuts[3];
+    jc_options opt{};
+    std::vector<HostBlock> blocks;
+    std::vector<HostPair> pairs;
+    int64_t max_slow = 0, max_fast = 0, max_count = 0;
+    int tile_y = 8;
+    int z_chunk = 0;
+    std::vector<Item> items;
+    int64_t max_items = 0;
+    // arena layout
+    size_t off_blocks = 0, off_pairs = 0, off_items = 0, off_partials = 0, off_ranges = 0,
+           off_result = 0, footprint = 0;
+    size_t lo_begin = 0, lo_end = 0;   // refinement arrays and buffers
+    // binding
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    std::vector<BlockDesc> hdesc;
+    std::vector<PairDesc> hpairs;
+    int32_t hranges[2] = {0, 0};
+    double* h_result = nullptr;     // pinned
+    // state
+    bool loaded_u = false, loaded_b = false;
+    int parity = 0;
+    int64_t iters = 0;
+    int ghost = GHOST_CURRENT;
+    bool fused_primed = false;
+    // refinement state used by groups: d arrays zeroed, phase
+    // (0: residual due, 1: r_lo current, 2: inner sweeps ran since the
+    // last residual), copy q holding the latest correction
+    bool ir_zeroed = false;
+    int ir_phase = 0;
+    int ir_q = 0;
+    // graphs keyed by (iterations, start parity, residual-last)
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    // timing
+    bool timing = false;
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[JC_K_COUNT] = {0};
+    int64_t kernel_launches[JC_K_COUNT] = {0};
+
+    BlockDesc* d_blocks() const { return reinterpret_cast<BlockDesc*>(arena + off_blocks); }
+    PairDesc* d_pairs() const { return reinterpret_cast<PairDesc*>(arena + off_pairs); }
+    Item* d_items() const { return reinterpret_cast<Item*>(arena + off_items); }
+    double* d_partials() const { return reinterpret_cast<double*>(arena + off_partials); }
+    int32_t* d_ranges() const { return reinterpret_cast<int32_t*>(arena + off_ranges); }
+    double* d_result() const { return reinterpret_cast<double*>(arena + off_result); }
+    int nb() const { return (int)blocks.size(); }
+    int np() const { return (int)pairs.size(); }
+};
+
+
+namespace jc_rt {
+
+hipEvent_t take_event(jc_ctx* c);
+int drain_timing(jc_ctx* c);
+int check_ready(jc_ctx* c);
+int do_pack(jc_ctx* c, int slot);
+
+// Runs `launch` on the context's stream, bracketed by timing events of
+// kind `kind` when timing is on.
+template <typename F>
+int timed(jc_ctx* c, int kind, F&& launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        a = take_event(c);
+        b = take_event(c);
+        if (!a || !b)
+            return fail(JC_ERR_DEVICE, "hipEventCreate failed");
+        JC_HIP(hipEventRecord(a, c->stream));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess)
+        return fail(JC_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (c->timing) {
+        JC_HIP(hipEventRecord(b, c->stream));
+        c->pending.push_back({kind, a, b});
+    }
+    return JC_OK;
+}
+
+}  // namespace jc_rt

@@ -1,0 +1,482 @@
+// Groups: the blocks of several independent contexts swept by shared
+// launches (batching many grids, continuous batching of a solve server).
+//
+// A group owns a joint block table and joint work lists, one list per
+// kernel class (plain binary64 with or without a source; refinement by
+// storage format and source).  Every launch covers all members of a
+// class; each work item carries its member's ping-pong flip, so members
+// admitted at different times stay independent.  The tile shape is fixed
+// for a group (it never depends on who else is in it), so a member's
+// results and residual norms are bitwise the same alone and in any mix.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "jc_ctx.h"
+
+using namespace jc_rt;
+
+namespace {
+
+constexpr int kGroupTileY = 8;
+constexpr int kGroupZChunk = 32;
+
+struct Class {
+    bool ir = false;     // refinement members
+    bool src = false;    // members with a source
+    int lo = JC_F64;     // refinement storage
+    int bstart = 0, bend = 0;        // joint block range
+    size_t item0 = 0;                // first joint item
+    std::vector<Item> items;
+    std::vector<int> members;
+};
+
+}  // namespace
+
+struct jc_group {
+    std::vector<jc_ctx*> members;
+    hipStream_t stream = nullptr;
+    bool use_graphs = false;
+    std::vector<Class> classes;
+    std::vector<BlockDesc> desc;        // joint block table, class-major
+    std::vector<Item> items;            // joint work list, class-major
+    std::vector<int32_t> lohi;          // per member: joint item range
+    std::vector<int> member_bstart;     // per member: first joint block
+    size_t off_desc = 0, off_items = 0, off_partials = 0, off_lohi = 0, off_out = 0, footprint = 0;
+    char* scratch = nullptr;
+    bool bound = false;
+    double* h_out = nullptr;            // pinned, one per member
+    int parity = 0;                     // launch parity; items hold member flips
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    std::vector<hipEvent_t> events;
+
+    BlockDesc* d_desc() const { return reinterpret_cast<BlockDesc*>(scratch + off_desc); }
+    Item* d_items() const { return reinterpret_cast<Item*>(scratch + off_items); }
+    double* d_partials() const { return reinterpret_cast<double*>(scratch + off_partials); }
+    int32_t* d_lohi() const { return reinterpret_cast<int32_t*>(scratch + off_lohi); }
+    double* d_out() const { return reinterpret_cast<double*>(scratch + off_out); }
+};
+
+namespace {
+
+int ghip(hipError_t e, const char* what)
+{
+    if (e != hipSuccess)
+        return fail(JC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return JC_OK;
+}
+
+// Items of one member's blocks with the group's fixed tile shape.
+void member_items(const jc_ctx* c, int bbase, int member, std::vector<Item>& out)
+{
+    for (int bi = 0; bi < (int)c->blocks.size(); ++bi) {
+        const HostBlock& b = c->blocks[bi];
+        for (int64_t z0 = 0; z0 < b.n[2]; z0 += kGroupZChunk)
+            for (int64_t y0 = 0; y0 < b.n[1]; y0 += kGroupTileY)
+                for (int64_t x0 = 0; x0 < b.n[0]; x0 += jc::kTileX) {
+                    Item it{};
+                    it.block = bbase + bi;
+                    it.x0 = (int32_t)x0;
+                    it.y0 = (int32_t)y0;
+                    it.z0 = (int32_t)z0;
+                    it.zlen = (int32_t)std::min<int64_t>(kGroupZChunk, b.n[2] - z0);
+                    it.flip = c->parity;
+                    it.owner = member;
+                    out.push_back(it);
+                }
+    }
+}
+
+// The faces of every member's current iterate into its slot `parity`.
+int prime_faces(jc_group* g)
+{
+    for (jc_ctx* c : g->members) {
+        if (c->np() && !c->fused_primed) {
+            const hipError_t e = jc::launch_pack(c->d_blocks(), c->d_pairs(), c->np(), (int)c->max_slow,
+                                                 (int)c->max_fast, c->parity, c->parity, g->stream);
+            if (e != hipSuccess)
+                return ghip(e, "pack");
+            c->fused_primed = true;
+        }
+    }
+    return JC_OK;
+}
+
+// One sweep of every member.
+int group_sweep(jc_group* g)
+{
+    for (const Class& k : g->classes) {
+        const int n = (int)k.items.size();
+        if (!k.ir) {
+            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, kGroupTileY,
+                                                  true, false, true, k.src, nullptr, g->stream);
+            if (e != hipSuccess)
+                return ghip(e, "group sweep");
+        } else {
+            // refinement members: the first inner sweep after a residual
+            // starts from d = 0; later ones sweep d
+            const jc_ctx* c0 = g->members[k.members[0]];
+            hipError_t e;
+            if (c0->ir_phase == 1)
+                e = jc::launch_ir_first(g->d_desc() + k.bstart, k.bend - k.bstart, k.lo, g->stream);
+            else
+                e = jc::launch_ir_inner(g->d_desc(), g->d_items() + k.item0, n, c0->ir_q, kGroupTileY, k.lo,
+                                        g->stream);
+            if (e != hipSuccess)
+                return ghip(e, "group inner sweep");
+        }
+    }
+    return JC_OK;
+}
+
+// Bookkeeping after n sweeps of every member.
+void advance(jc_group* g, int64_t n)
+{
+    if (n <= 0)
+        return;
+    g->parity ^= (int)(n & 1);
+    for (const Class& k : g->classes) {
+        for (int m : k.members) {
+            jc_ctx* c = g->members[m];
+            c->iters += n;
+            if (!k.ir) {
+                c->parity ^= (int)(n & 1);
+                c->ghost = c->np() ? GHOST_STALE : GHOST_CURRENT;
+                c->fused_primed = c->np() > 0;
+            } else {
+                // first sweep writes copy 1; each later one flips it
+                const int q = c->ir_phase == 1 ? 1 : c->ir_q;
+                const int64_t later = c->ir_phase == 1 ? n - 1 : n;
+                c->ir_q = q ^ (int)(later & 1);
+                c->ir_phase = 2;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_group** out)
+{
+    if (!out)
+        return fail(JC_ERR_INVALID, "out must not be NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1)
+        return fail(JC_ERR_INVALID, "a group needs at least one context");
+    if (flags & ~1)
+        return fail(JC_ERR_INVALID, "unknown group flags");
+    std::set<const jc_ctx*> seen;
+    for (int i = 0; i < n; ++i) {
+        jc_ctx* c = ctxs[i];
+        int st = check_ready(c);
+        if (st != JC_OK)
+            return st;
+        if (!seen.insert(c).second)
+            return fail(JC_ERR_INVALID, "a context appears twice in the group");
+        if (c->opt.ir_enable && c->parity != 0)
+            return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
+    }
+    jc_group* g = new (std::nothrow) jc_group();
+    if (!g)
+        return fail(JC_ERR_NOMEM, "host allocation failed");
+    g->members.assign(ctxs, ctxs + n);
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    g->use_graphs = (flags & 1) && g->stream != nullptr;
+    // classes, in a fixed order
+    std::map<std::tuple<int, int, int>, int> cls;
+    for (int i = 0; i < n; ++i) {
+        const jc_ctx* c = ctxs[i];
+        const auto key = std::make_tuple(c->opt.ir_enable ? 1 : 0, c->opt.with_source ? 1 : 0,
+                                         c->opt.ir_enable ? c->opt.ir_dtype : JC_F64);
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            Class k;
+            k.ir = std::get<0>(key) != 0;
+            k.src = std::get<1>(key) != 0;
+            k.lo = std::get<2>(key);
+            it = cls.emplace(key, 0).first;
+            g->classes.push_back(k);
+            it->second = (int)g->classes.size() - 1;
+        }
+        g->classes[it->second].members.push_back(i);
+    }
+    g->member_bstart.assign(n, 0);
+    g->lohi.assign(2 * n, 0);
+    for (Class& k : g->classes) {
+        k.bstart = (int)g->desc.size();
+        k.item0 = g->items.size();
+        for (int m : k.members) {
+            const jc_ctx* c = ctxs[m];
+            g->member_bstart[m] = (int)g->desc.size();
+            const size_t i0 = g->items.size();
+            const size_t first = k.items.size();
+            member_items(c, (int)g->desc.size(), m, k.items);
+            g->desc.insert(g->desc.end(), c->hdesc.begin(), c->hdesc.end());
+            g->items.insert(g->items.end(), k.items.begin() + first, k.items.end());
+            g->lohi[2 * m] = (int32_t)i0;
+            g->lohi[2 * m + 1] = (int32_t)g->items.size();
+        }
+        k.bend = (int)g->desc.size();
+    }
+    if (g->desc.size() > 65535 || g->items.size() > ((size_t)1 << 30)) {
+        delete g;
+        return fail(JC_ERR_INVALID, "group too large for one launch");
+    }
+    size_t off = 0;
+    g->off_desc = off; off = align_up(off + sizeof(BlockDesc) * g->desc.size(), kAlign);
+    g->off_items = off; off = align_up(off + sizeof(Item) * g->items.size(), kAlign);
+    g->off_partials = off; off = align_up(off + sizeof(double) * g->items.size(), kAlign);
+    g->off_lohi = off; off = align_up(off + sizeof(int32_t) * g->lohi.size(), kAlign);
+    g->off_out = off; off = align_up(off + sizeof(double) * n, kAlign);
+    g->footprint = off;
+    *out = g;
+    return JC_OK;
+}
+
+int jc_group_footprint(const jc_group* g, size_t* bytes)
+{
+    if (!g || !bytes)
+        return fail(JC_ERR_INVALID, "bad group or output");
+    *bytes = g->footprint;
+    return JC_OK;
+}
+
+int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes)
+{
+    if (!g)
+        return fail(JC_ERR_INVALID, "NULL group");
+    if (g->bound)
+        return fail(JC_ERR_STATE, "group is already bound");
+    if (!dev_scratch || reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
+        return fail(JC_ERR_INVALID, "scratch must be a 256-byte aligned device pointer");
+    if (bytes < g->footprint)
+        return fail(JC_ERR_NOMEM, "scratch smaller than jc_group_footprint");
+    g->scratch = static_cast<char*>(dev_scratch);
+    int st = ghip(hipHostMalloc(reinterpret_cast<void**>(&g->h_out), sizeof(double) * g->members.size(),
+                                hipHostMallocDefault), "hipHostMalloc");
+    if (st != JC_OK)
+        return st;
+    // order the group stream after every member's queued work
+    for (jc_ctx* c : g->members) {
+        if (c->stream == g->stream)
+            continue;
+        hipEvent_t e = nullptr;
+        st = ghip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        if (st != JC_OK)
+            return st;
+        g->events.push_back(e);
+        st = ghip(hipEventRecord(e, c->stream), "hipEventRecord");
+        if (st == JC_OK)
+            st = ghip(hipStreamWaitEvent(g->stream, e, 0), "hipStreamWaitEvent");
+        if (st != JC_OK)
+            return st;
+    }
+    st = ghip(hipMemcpyAsync(g->d_desc(), g->desc.data(), sizeof(BlockDesc) * g->desc.size(),
+                             hipMemcpyHostToDevice, g->stream), "upload blocks");
+    if (st == JC_OK)
+        st = ghip(hipMemcpyAsync(g->d_items(), g->items.data(), sizeof(Item) * g->items.size(),
+                                 hipMemcpyHostToDevice, g->stream), "upload items");
+    if (st == JC_OK)
+        st = ghip(hipMemcpyAsync(g->d_lohi(), g->lohi.data(), sizeof(int32_t) * g->lohi.size(),
+                                 hipMemcpyHostToDevice, g->stream), "upload ranges");
+    if (st == JC_OK)
+        st = ghip(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    if (st != JC_OK)
+        return st;
+    g->bound = true;
+    return JC_OK;
+}
+
+int jc_group_iterate(jc_group* g, int64_t n)
+{
+    if (!g || !g->bound)
+        return fail(!g ? JC_ERR_INVALID : JC_ERR_STATE, "group is not bound (jc_group_bind)");
+    if (n < 0)
+        return fail(JC_ERR_INVALID, "n must be >= 0");
+    for (const Class& k : g->classes)
+        if (k.ir)
+            for (int m : k.members)
+                if (g->members[m]->ir_phase == 0)
+                    return fail(JC_ERR_STATE, "a refining member needs jc_group_residuals before sweeping");
+    if (n == 0)
+        return JC_OK;
+    int st = prime_faces(g);
+    if (st != JC_OK)
+        return st;
+    // the first window sweep of refinement members differs from the rest
+    int64_t done = 0;
+    bool ir_first = false;
+    for (const Class& k : g->classes)
+        if (k.ir && g->members[k.members[0]]->ir_phase == 1)
+            ir_first = true;
+    if (ir_first) {
+        st = group_sweep(g);
+        if (st != JC_OK)
+            return st;
+        advance(g, 1);
+        done = 1;
+    }
+    const int64_t rest = n - done;
+    if (rest <= 0)
+        return JC_OK;
+    if (!g->use_graphs) {
+        for (int64_t i = 0; i < rest; ++i) {
+            st = group_sweep(g);
+            if (st != JC_OK)
+                return st;
+            advance(g, 1);
+        }
+        return JC_OK;
+    }
+    // graph of `rest` sweeps from the current launch parity; the d copy
+    // of refinement members alternates with the launch parity
+    int irq = 0;
+    for (const Class& k : g->classes)
+        if (k.ir)
+            irq = g->members[k.members[0]]->ir_q;
+    const auto key = std::make_pair(rest, g->parity | (irq << 1));
+    auto found = g->graphs.find(key);
+    if (found == g->graphs.end()) {
+        // record the sweeps on a scratch copy of the member states
+        std::vector<int> saved_q, saved_par, saved_phase;
+        std::vector<int64_t> saved_it;
+        std::vector<int> saved_ghost;
+        std::vector<bool> saved_primed;
+        for (jc_ctx* c : g->members) {
+            saved_q.push_back(c->ir_q);
+            saved_par.push_back(c->parity);
+            saved_phase.push_back(c->ir_phase);
+            saved_it.push_back(c->iters);
+            saved_ghost.push_back(c->ghost);
+            saved_primed.push_back(c->fused_primed);
+        }
+        const int gpar = g->parity;
+        st = ghip(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (st != JC_OK)
+            return st;
+        for (int64_t i = 0; i < rest && st == JC_OK; ++i) {
+            st = group_sweep(g);
+            advance(g, 1);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+        g->parity = gpar;
+        for (size_t i = 0; i < g->members.size(); ++i) {
+            jc_ctx* c = g->members[i];
+            c->ir_q = saved_q[i];
+            c->parity = saved_par[i];
+            c->ir_phase = saved_phase[i];
+            c->iters = saved_it[i];
+            c->ghost = saved_ghost[i];
+            c->fused_primed = saved_primed[i];
+        }
+        if (st != JC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        st = ghip(e, "hipStreamEndCapture");
+        if (st != JC_OK)
+            return st;
+        hipGraphExec_t exec = nullptr;
+        st = ghip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        (void)hipGraphDestroy(graph);
+        if (st != JC_OK)
+            return st;
+        found = g->graphs.emplace(key, exec).first;
+    }
+    st = ghip(hipGraphLaunch(found->second, g->stream), "hipGraphLaunch");
+    if (st != JC_OK)
+        return st;
+    advance(g, rest);
+    return JC_OK;
+}
+
+int jc_group_residuals(jc_group* g, double* host_l2)
+{
+    if (!g || !host_l2)
+        return fail(JC_ERR_INVALID, "bad group or output");
+    if (!g->bound)
+        return fail(JC_ERR_STATE, "group is not bound (jc_group_bind)");
+    int st = prime_faces(g);
+    if (st != JC_OK)
+        return st;
+    for (const Class& k : g->classes) {
+        const int n = (int)k.items.size();
+        if (!k.ir) {
+            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, kGroupTileY,
+                                                  true, true, false, k.src, g->d_partials() + k.item0, g->stream);
+            if (e != hipSuccess)
+                return ghip(e, "group residual");
+            continue;
+        }
+        for (int m : k.members) {
+            jc_ctx* c = g->members[m];
+            const int nb = (int)c->blocks.size();
+            BlockDesc* bd = g->d_desc() + g->member_bstart[m];
+            if (!c->ir_zeroed) {
+                st = ghip(jc::launch_zero(c->arena + c->lo_begin, c->lo_end - c->lo_begin, g->stream), "zero");
+                if (st != JC_OK)
+                    return st;
+                c->ir_zeroed = true;
+            }
+            if (c->ir_phase == 2) {
+                // outer update with the correction of the sweeps just run
+                st = ghip(jc::launch_ir_update(bd, nb, c->parity, c->ir_q, k.lo, g->stream), "update");
+                if (st != JC_OK)
+                    return st;
+            }
+        }
+        // refining members keep their iterate in copy 0 (their items' flip is 0)
+        const hipError_t e = jc::launch_ir_residual(g->d_desc(), g->d_items() + k.item0, n, 0, kGroupTileY,
+                                                    k.src, k.lo, g->d_partials() + k.item0, g->stream);
+        if (e != hipSuccess)
+            return ghip(e, "group refinement residual");
+        for (int m : k.members)
+            g->members[m]->ir_phase = 1;
+    }
+    const int nm = (int)g->members.size();
+    st = ghip(jc::launch_reduce(g->d_partials(), g->d_lohi(), nm, g->d_out(), g->stream), "reduce");
+    if (st == JC_OK)
+        st = ghip(hipMemcpyAsync(g->h_out, g->d_out(), sizeof(double) * nm, hipMemcpyDeviceToHost, g->stream),
+                  "copy residuals");
+    if (st == JC_OK)
+        st = ghip(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    if (st != JC_OK)
+        return st;
+    int bad = -1;
+    for (int m = 0; m < nm; ++m) {
+        host_l2[m] = std::sqrt(g->h_out[m]);
+        if (!std::isfinite(host_l2[m]) && bad < 0)
+            bad = m;
+    }
+    if (bad >= 0)
+        return fail(JC_ERR_NONFINITE, "residual of group member " + std::to_string(bad) + " is not finite");
+    return JC_OK;
+}
+
+void jc_group_destroy(jc_group* g)
+{
+    if (!g)
+        return;
+    if (g->bound) {
+        (void)hipStreamSynchronize(g->stream);
+        for (auto& kv : g->graphs)
+            (void)hipGraphExecDestroy(kv.second);
+        for (hipEvent_t e : g->events)
+            (void)hipEventDestroy(e);
+        if (g->h_out)
+            (void)hipHostFree(g->h_out);
+    }
+    delete g;
+}
+
+}  // extern "C"

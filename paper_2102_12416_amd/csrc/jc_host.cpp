@@ -21,15 +21,11 @@
 #include <utility>
 #include <vector>
 
-#include "jc.h"
-#include "jc_kernels.h"
-#include "jc_types.h"
+#include "jc_ctx.h"
 
-using jc::BlockDesc;
-using jc::Item;
-using jc::PairDesc;
+using namespace jc_rt;
 
-namespace {
+namespace jc_rt {
 
 thread_local std::string g_err;
 
@@ -39,90 +35,7 @@ int fail(int code, const std::string& msg)
     return code;
 }
 
-#define JC_HIP(expr)                                                                       \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(JC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int64_t kMaxEdge = (int64_t)1 << 30;    // per-axis limit (int32 cell indices)
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-enum GhostState { GHOST_CURRENT = 0, GHOST_PACKED = 1, GHOST_EXCHANGED = 2, GHOST_STALE = 3 };
-
-struct HostBlock {
-    int64_t n[3];
-    int64_t off[3];
-    int nbr[6];
-    int pair_out[6];        // pair index whose source is this face, or -1
-    int pair_in[6];         // pair index whose destination is this face, or -1
-    int64_t pitch, plane;   // binary64 arrays
-    size_t u_off[2], b_off; // byte offsets of element (0,0,0)'s line base
-};
-
-struct HostPair {
-    int src_block, src_face, dst_block, dst_face;
-    int64_t slow, fast, count, span;
-    size_t buf_off[2];
-};
-
-const int kTileYCandidates[] = {4, 8, 16, 32};
-constexpr int kMinZChunk = 16;
-
-}  // namespace
-
-struct jc_ctx {
-    int64_t grid[3] = {0, 0, 0};
-    std::vector<int64_t> cuts[3];
-    jc_options opt{};
-    std::vector<HostBlock> blocks;
-    std::vector<HostPair> pairs;
-    int64_t max_slow = 0, max_fast = 0, max_count = 0;
-    int tile_y = 8;
-    int z_chunk = 0;
-    std::vector<Item> items;
-    int64_t max_items = 0;
-    // arena layout
-    size_t off_blocks = 0, off_pairs = 0, off_items = 0, off_partials = 0, off_ranges = 0,
-           off_result = 0, footprint = 0;
-    // binding
-    char* arena = nullptr;
-    size_t arena_bytes = 0;
-    hipStream_t stream = nullptr;
-    bool bound = false;
-    std::vector<BlockDesc> hdesc;
-    std::vector<PairDesc> hpairs;
-    int32_t hranges[2] = {0, 0};
-    double* h_result = nullptr;     // pinned
-    // state
-    bool loaded_u = false, loaded_b = false;
-    int parity = 0;
-    int64_t iters = 0;
-    int ghost = GHOST_CURRENT;
-    bool fused_primed = false;
-    // graphs keyed by (iterations, start parity, residual-last)
-    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
-    // timing
-    bool timing = false;
-    struct Pending { int kind; hipEvent_t a, b; };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> event_pool;
-    double kernel_ms[JC_K_COUNT] = {0};
-    int64_t kernel_launches[JC_K_COUNT] = {0};
-
-    BlockDesc* d_blocks() const { return reinterpret_cast<BlockDesc*>(arena + off_blocks); }
-    PairDesc* d_pairs() const { return reinterpret_cast<PairDesc*>(arena + off_pairs); }
-    Item* d_items() const { return reinterpret_cast<Item*>(arena + off_items); }
-    double* d_partials() const { return reinterpret_cast<double*>(arena + off_partials); }
-    int32_t* d_ranges() const { return reinterpret_cast<int32_t*>(arena + off_ranges); }
-    double* d_result() const { return reinterpret_cast<double*>(arena + off_result); }
-    int nb() const { return (int)blocks.size(); }
-    int np() const { return (int)pairs.size(); }
-};
+}  // namespace jc_rt
 
 namespace {
 
@@ -193,8 +106,8 @@ int validate_options(const jc_options* opt)
     }
     if (opt->z_chunk < 0)
         return fail(JC_ERR_INVALID, "options.z_chunk must be >= 0");
-    if (opt->ir_enable)
-        return fail(JC_ERR_INVALID, "iterative refinement buffers are not available in this build");
+    if (opt->ir_enable && opt->ir_dtype != JC_F64 && opt->ir_dtype != JC_F32 && opt->ir_dtype != JC_BF16)
+        return fail(JC_ERR_INVALID, "options.ir_dtype must be JC_F64, JC_F32 or JC_BF16 when ir_enable is set");
     return JC_OK;
 }
 
@@ -312,6 +225,25 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         p.buf_off[0] = off; off += bytes;
         p.buf_off[1] = off; off += bytes;
     }
+    c->lo_begin = c->lo_end = off;
+    if (c->opt.ir_enable) {
+        const size_t es = lo_size(c->opt.ir_dtype);
+        const int64_t le = 128 / (int64_t)es;
+        for (HostBlock& b : c->blocks) {
+            b.lpitch = round_up(b.n[0] + 2, le);
+            b.lplane = b.lpitch * (b.n[1] + 2);
+            const size_t bytes = align_up(es * (size_t)(b.lplane * (b.n[2] + 2) + le), kAlign);
+            b.d_off[0] = off; off += bytes;
+            b.d_off[1] = off; off += bytes;
+            b.rlo_off = off; off += bytes;
+        }
+        for (HostPair& p : c->pairs) {
+            const size_t bytes = align_up(es * (size_t)p.span, kAlign);
+            p.lbuf_off[0] = off; off += bytes;
+            p.lbuf_off[1] = off; off += bytes;
+        }
+        c->lo_end = off;
+    }
     c->footprint = off;
     return JC_OK;
 }
@@ -355,6 +287,10 @@ int rect_geometry(jc_ctx* c, const int64_t grid[3], const int64_t* const cuts[3]
     return build_geometry(c, grid, v, opt);
 }
 
+}  // namespace
+
+namespace jc_rt {
+
 // ------------------------------------------------------------------ timing
 
 hipEvent_t take_event(jc_ctx* c)
@@ -368,28 +304,6 @@ hipEvent_t take_event(jc_ctx* c)
     if (hipEventCreate(&e) != hipSuccess)
         return nullptr;
     return e;
-}
-
-// Runs `launch` bracketed by events when timing is on.
-template <typename F>
-int timed(jc_ctx* c, int kind, F&& launch)
-{
-    hipEvent_t a = nullptr, b = nullptr;
-    if (c->timing) {
-        a = take_event(c);
-        b = take_event(c);
-        if (!a || !b)
-            return fail(JC_ERR_DEVICE, "hipEventCreate failed");
-        JC_HIP(hipEventRecord(a, c->stream));
-    }
-    hipError_t e = launch();
-    if (e != hipSuccess)
-        return fail(JC_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
-    if (c->timing) {
-        JC_HIP(hipEventRecord(b, c->stream));
-        c->pending.push_back({kind, a, b});
-    }
-    return JC_OK;
 }
 
 int drain_timing(jc_ctx* c)
@@ -431,6 +345,10 @@ int do_pack(jc_ctx* c, int slot)
                                c->parity, slot, c->stream);
     });
 }
+
+}  // namespace jc_rt
+
+namespace {
 
 int do_exchange(jc_ctx* c)
 {
@@ -623,7 +541,7 @@ void free_graphs(jc_ctx* c)
 
 extern "C" {
 
-const char* jc_last_error(void) { return g_err.c_str(); }
+const char* jc_last_error(void) { return jc_rt::g_err.c_str(); }
 
 int jc_min_surface_parts(const int64_t grid[3], int64_t nblocks, int64_t parts[3])
 {
@@ -779,6 +697,20 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
         }
         d.pitch = (int32_t)hb.pitch;
         d.plane = hb.plane;
+        if (c->opt.ir_enable) {
+            const size_t es = lo_size(c->opt.ir_dtype);
+            const size_t llead = (128 / es - 1) * es;
+            d.d[0] = c->arena + hb.d_off[0] + llead;
+            d.d[1] = c->arena + hb.d_off[1] + llead;
+            d.rlo = c->arena + hb.rlo_off + llead;
+            d.lpitch = (int32_t)hb.lpitch;
+            d.lplane = hb.lplane;
+            for (int f = 0; f < 6; ++f)
+                for (int s = 0; s < 2; ++s) {
+                    d.lgin[f][s] = hb.pair_in[f] >= 0 ? c->arena + c->pairs[hb.pair_in[f]].lbuf_off[s] : nullptr;
+                    d.lgout[f][s] = hb.pair_out[f] >= 0 ? c->arena + c->pairs[hb.pair_out[f]].lbuf_off[s] : nullptr;
+                }
+        }
     }
     c->hpairs.assign(c->pairs.size(), PairDesc{});
     for (int q = 0; q < c->np(); ++q) {
@@ -789,6 +721,10 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
         d.slow = (int32_t)hp.slow; d.fast = (int32_t)hp.fast; d.count = hp.count; d.span = hp.span;
         d.buf[0] = reinterpret_cast<double*>(c->arena + hp.buf_off[0]);
         d.buf[1] = reinterpret_cast<double*>(c->arena + hp.buf_off[1]);
+        if (c->opt.ir_enable) {
+            d.lbuf[0] = c->arena + hp.lbuf_off[0];
+            d.lbuf[1] = c->arena + hp.lbuf_off[1];
+        }
     }
     c->hranges[0] = 0;
     c->hranges[1] = (int32_t)c->items.size();
@@ -1000,6 +936,98 @@ int jc_solve(jc_ctx* c, double rtol, int64_t max_iter, int64_t check_every, jc_s
             k += n;
         }
     }
+    info->iters = c->iters - start;
+    info->abs_resid = r;
+    info->r0 = r0;
+    info->rel_resid = r0 > 0 ? r / r0 : 0.0;
+    info->status = status;
+    return status;
+}
+
+int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_solve_info* info)
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (!info)
+        return fail(JC_ERR_INVALID, "info must not be NULL");
+    if (!c->opt.ir_enable)
+        return fail(JC_ERR_STATE, "context was created without refinement buffers (options.ir_enable)");
+    if (inner_sweeps < 1 || max_inner < 0 || !std::isfinite(rtol))
+        return fail(JC_ERR_INVALID, "inner_sweeps must be >= 1, max_inner >= 0 and rtol finite");
+    const int lo = c->opt.ir_dtype;
+    const bool src = c->opt.with_source != 0;
+    info->history_len = 0;
+    info->outer = 0;
+    // d = 0 with zero ghosts, once: sweeps never write a ghost
+    st = timed(c, JC_K_IR_OUTER, [&] {
+        return jc::launch_zero(c->arena + c->lo_begin, c->lo_end - c->lo_begin, c->stream);
+    });
+    if (st != JC_OK)
+        return st;
+    // faces of the current iterate into slot `parity` of the u buffers
+    if (c->np()) {
+        st = do_pack(c, c->parity);
+        if (st != JC_OK)
+            return st;
+    }
+    const int64_t start = c->iters;
+    double r0 = -1.0, r = 0.0;
+    int64_t done = 0;
+    int status = JC_MAXITER;
+    while (true) {
+        st = timed(c, JC_K_IR_OUTER, [&] {
+            return jc::launch_ir_residual(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity,
+                                          c->tile_y, src, lo, c->d_partials(), c->stream);
+        });
+        if (st != JC_OK)
+            return st;
+        double ss = 0;
+        st = reduce_to_host(c, &ss);
+        if (st != JC_OK)
+            return st;
+        r = std::sqrt(ss);
+        if (!std::isfinite(r))
+            return fail(JC_ERR_NONFINITE, "residual is not finite after " + std::to_string(done) + " inner sweeps");
+        if (r0 < 0)
+            r0 = r;
+        if (info->history && info->history_len < info->history_cap)
+            info->history[info->history_len++] = r;
+        info->outer += 1;
+        const double rel = r0 > 0 ? r / r0 : 0.0;
+        if (rel <= rtol) {
+            status = JC_OK;
+            break;
+        }
+        if (done >= max_inner)
+            break;
+        const int64_t m = std::min<int64_t>(inner_sweeps, max_inner - done);
+        st = timed(c, JC_K_IR_INNER, [&] {
+            return jc::launch_ir_first(c->d_blocks(), c->nb(), lo, c->stream);
+        });
+        if (st != JC_OK)
+            return st;
+        int q = 1;
+        for (int64_t j = 1; j < m; ++j) {
+            st = timed(c, JC_K_IR_INNER, [&] {
+                return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), q, c->tile_y, lo,
+                                           c->stream);
+            });
+            if (st != JC_OK)
+                return st;
+            q ^= 1;
+        }
+        st = timed(c, JC_K_IR_OUTER, [&] {
+            return jc::launch_ir_update(c->d_blocks(), c->nb(), c->parity, q, lo, c->stream);
+        });
+        if (st != JC_OK)
+            return st;
+        done += m;
+        c->iters += m;
+    }
+    // u stayed in its copy; its faces of slot `parity` are current
+    c->ghost = c->np() ? GHOST_STALE : GHOST_CURRENT;
+    c->fused_primed = c->np() > 0;
     info->iters = c->iters - start;
     info->abs_resid = r;
     info->r0 = r0;

@@ -19,7 +19,21 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
                         int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
                         hipStream_t s);
 
-// Sum partials[ranges[m] .. ranges[m+1]) in a fixed order into out[m], m < nmembers.
+// Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
+// of d and r_lo).  Residual: r of u[parity] with fused ghosts (face
+// buffers of slot parity), partial sums of r^2, r rounded into r_lo.
+// Inner: one sweep of d (copy qparity -> qparity ^ 1) with source r_lo.
+// First: d_1 = lo(r_lo / 6) into copy 1.  Update: u[p] += d[q] and the
+// updated faces into slot p.
+hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
+                              bool src, int lo_dtype, double* partials, hipStream_t s);
+hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
+                           int lo_dtype, hipStream_t s);
+hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int lo_dtype, hipStream_t s);
+hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int p, int q, int lo_dtype, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Sum partials[ranges[2m] .. ranges[2m+1]) in a fixed order into out[m], m < nmembers.
 hipError_t launch_reduce(const double* partials, const int32_t* ranges, int nmembers, double* out,
                          hipStream_t s);
 

@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "jc_kernels.h"
 
 namespace jc {
@@ -38,27 +40,111 @@ __device__ __forceinline__ int logical_block(int bid, int nblocks)
 #define JC_GLOBAL __attribute__((address_space(1)))
 
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
-// 16-byte load of the aligned pair at p
-__device__ __forceinline__ double2 ld2(const double* p)
+// bfloat16: the upper half of a binary32, rounded to nearest even
+__device__ __forceinline__ float bf16_to_f32(uint32_t h)
 {
-    const v2d v = *(const v2d JC_GLOBAL*)(p);
-    return make_double2(v.x, v.y);
+    return __uint_as_float(h << 16);
 }
 
-// 16-byte store of (a, b) to the aligned pair at p
-__device__ __forceinline__ void st2(double* p, double a, double b)
+__device__ __forceinline__ uint32_t f32_to_bf16(float f)
 {
-    v2d v;
-    v.x = a;
-    v.y = b;
-    *(v2d JC_GLOBAL*)(p) = v;
+    const uint32_t x = __float_as_uint(f);
+    if ((x & 0x7fffffffu) > 0x7f800000u)          // NaN stays a (quiet) NaN
+        return (x >> 16) | 0x40u;
+    const uint32_t lower = x & 0xffffu;
+    uint32_t upper = x >> 16;
+    if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))
+        upper += 1u;
+    return upper & 0xffffu;
 }
 
-__device__ __forceinline__ void st1(double* p, double a)
-{
-    *(double JC_GLOBAL*)(p) = a;
-}
+// Storage formats of a swept field: arithmetic type C, and loads / stores
+// of the 2-element aligned pair (x, x + 1) that one thread owns.
+template <typename T> struct Tr;
+
+template <> struct Tr<double> {
+    using C = double;
+    __device__ static void ld(const double* p, double& a, double& b)
+    {
+        const v2d v = *(const v2d JC_GLOBAL*)(p);
+        a = v.x;
+        b = v.y;
+    }
+    __device__ static void st(double* p, double a, double b)
+    {
+        v2d v;
+        v.x = a;
+        v.y = b;
+        *(v2d JC_GLOBAL*)(p) = v;
+    }
+    __device__ static void st1(double* p, double a) { *(double JC_GLOBAL*)(p) = a; }
+};
+
+template <> struct Tr<float> {
+    using C = float;
+    __device__ static void ld(const float* p, float& a, float& b)
+    {
+        const v2f v = *(const v2f JC_GLOBAL*)(p);
+        a = v.x;
+        b = v.y;
+    }
+    __device__ static void st(float* p, float a, float b)
+    {
+        v2f v;
+        v.x = a;
+        v.y = b;
+        *(v2f JC_GLOBAL*)(p) = v;
+    }
+    __device__ static void st1(float* p, float a) { *(float JC_GLOBAL*)(p) = a; }
+};
+
+template <> struct Tr<bf16> {
+    using C = float;
+    __device__ static void ld(const bf16* p, float& a, float& b)
+    {
+        const uint32_t w = *(const uint32_t JC_GLOBAL*)(p);    // x at the lower address
+        a = bf16_to_f32(w & 0xffffu);
+        b = bf16_to_f32(w >> 16);
+    }
+    __device__ static void st(bf16* p, float a, float b)
+    {
+        *(uint32_t JC_GLOBAL*)(p) = f32_to_bf16(a) | (f32_to_bf16(b) << 16);
+    }
+    __device__ static void st1(bf16* p, float a) { *(uint16_t JC_GLOBAL*)(p) = (uint16_t)f32_to_bf16(a); }
+};
+
+// Which arrays of a block a sweep works on: the iterate u (with source b)
+// or the refinement correction d (with source r_lo).
+enum { FIELD_U = 0, FIELD_D = 1 };
+
+template <typename T, int FIELD> struct Fld;
+
+template <typename T> struct Fld<T, FIELD_U> {
+    __device__ static const T* src(const BlockDesc* B, int p) { return B->u[p]; }
+    __device__ static T* dst(const BlockDesc* B, int p) { return B->u[p ^ 1]; }
+    __device__ static const T* source(const BlockDesc* B) { return B->b; }
+    __device__ static const T* gin(const BlockDesc* B, int f, int s) { return B->gin[f][s]; }
+    __device__ static T* gout(const BlockDesc* B, int f, int s) { return B->gout[f][s]; }
+    __device__ static int64_t pitch(const BlockDesc* B) { return B->pitch; }
+    __device__ static int64_t plane(const BlockDesc* B) { return B->plane; }
+};
+
+template <typename T> struct Fld<T, FIELD_D> {
+    __device__ static const T* src(const BlockDesc* B, int p) { return static_cast<const T*>(B->d[p]); }
+    __device__ static T* dst(const BlockDesc* B, int p) { return static_cast<T*>(B->d[p ^ 1]); }
+    __device__ static const T* source(const BlockDesc* B) { return static_cast<const T*>(B->rlo); }
+    __device__ static const T* gin(const BlockDesc* B, int f, int s)
+    {
+        return static_cast<const T*>(B->lgin[f][s]);
+    }
+    __device__ static T* gout(const BlockDesc* B, int f, int s) { return static_cast<T*>(B->lgout[f][s]); }
+    __device__ static int64_t pitch(const BlockDesc* B) { return B->lpitch; }
+    __device__ static int64_t plane(const BlockDesc* B) { return B->lplane; }
+};
+
+struct NoRlo {};
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -69,11 +155,12 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // One work-group sweeps a tile of 64 x cells by TY rows of one block,
 // marching along z.  Each thread owns two adjacent x cells of one row
-// (one 16-byte load per plane: cell x = 1 of every row starts a 128-byte
-// line).  Per plane the work-group writes the plane -- its cells plus a
-// one-cell halo ring -- into an LDS tile, synchronises once (the tile is
-// double-buffered by plane parity) and reads its x and y neighbours from
-// LDS; the z-1 / z / z+1 values of its own cells stay in registers.
+// (one aligned-pair load per plane: cell x = 1 of every row starts a
+// 128-byte line).  Per plane the work-group writes the plane -- its cells
+// plus a one-cell halo ring -- into an LDS tile, synchronises once (the
+// tile is double-buffered by plane parity) and reads its x and y
+// neighbours from LDS; the z-1 / z / z+1 values of its own cells stay in
+// registers.
 //
 // Every thread issues the same global loads in every iteration, with
 // clamped addresses where it has nothing to fetch, so that the loads of
@@ -83,22 +170,29 @@ __device__ __forceinline__ double wave_sum(double v)
 // the row below, the next TY threads the column left of it and the next
 // TY the column right of it; the rest re-load their own cells.
 //
-// FUSED: ghost cells of faces that have a neighbour block are read from
-// the neighbour's face buffer of the input slot (the pairing's pre-posted
-// receive side), and every face cell written is also written to this
-// block's face buffer of the output slot -- pack, exchange and unpack
-// folded into the sweep.  RES: accumulate r^2 of the input iterate,
-// r = (b + s) - 6u, into one partial per work-group.  STORE: write the
-// new iterate (off: residual only).  SRC: the block has a source b.
-template <int TY, bool FUSED, bool RES, bool STORE, bool SRC>
+// T / FIELD: the swept field and its storage (binary64 iterate u, or the
+// correction d of the refinement stored as binary64, binary32 or
+// bfloat16 with binary32 arithmetic).  FUSED: ghost cells of faces that
+// have a neighbour block are read from the neighbour's face buffer of the
+// input slot (the pairing's pre-posted receive side), and every face cell
+// written is also written to this block's face buffer of the output slot
+// -- pack, exchange and unpack folded into the sweep.  RES: accumulate r^2
+// of the input iterate, r = (b + s) - 6u, into one partial per
+// work-group.  STORE: write the new iterate.  SRC: add the source (b for
+// u, r_lo for d).  R: also store r rounded to R into the block's r_lo
+// array (the outer pass of the refinement).
+template <typename T, int FIELD, int TY, bool FUSED, bool RES, bool STORE, bool SRC, typename R>
 __global__ void __launch_bounds__(32 * TY)
 k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int nitems,
         int parity, double* __restrict__ partials)
 {
     static_assert(TY >= 4 && 32 * TY >= 64 + 2 * TY, "halo roles need 64 + 2 TY threads");
+    using C = typename Tr<T>::C;
+    using F = Fld<T, FIELD>;
+    constexpr bool RLO = !std::is_same<R, NoRlo>::value;
     constexpr int NT = 32 * TY;
     constexpr int LW = 68;   // LDS row: col 1 = x0, cols 2..65 = x0+1..x0+64, up to col 66
-    __shared__ double S[2][TY + 2][LW];
+    __shared__ C S[2][TY + 2][LW];
     __shared__ double wsum[NT / 64];
 
     const int id = logical_block(blockIdx.x, gridDim.x);
@@ -123,35 +217,36 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
     const int xlast = (nx - 1) | 1;               // start of the last aligned pair of a row
     const int xa_c = min(xa, xlast);
     const int y_c = min(y, ny);
-    const int64_t pitch = B->pitch;
-    const int64_t plane = B->plane;
+    const int64_t pitch = F::pitch(B);
+    const int64_t plane = F::plane(B);
     const int64_t ldx = face_ld(ny);              // x-face buffers: (z, y) rows
     const int64_t ldy = face_ld(nx);              // y- and z-face buffers: (z, x) / (y, x) rows
-    const double* __restrict__ src = B->u[p];
-    double* __restrict__ dst = B->u[p ^ 1];
+    const T* __restrict__ src = F::src(B, p);
+    T* __restrict__ dst = F::dst(B, p);
+    const C six = C(6);
 
     // own pair (xa_c, y_c) at plane zz
-    const double* own = src + (int64_t)y_c * pitch + xa_c;
-    const double* own_lo = own;                                   // plane 0
-    const double* own_hi = own + (int64_t)(nz + 1) * plane;       // plane nz + 1
+    const T* own = src + (int64_t)y_c * pitch + xa_c;
+    const T* own_lo = own;                                        // plane 0
+    const T* own_hi = own + (int64_t)(nz + 1) * plane;            // plane nz + 1
     if (FUSED) {
         const int64_t zi = (int64_t)(y_c - 1) * ldy + (xa_c - 1);
-        if (B->gin[ZM][p]) own_lo = B->gin[ZM][p] + zi;
-        if (B->gin[ZP][p]) own_hi = B->gin[ZP][p] + zi;
+        if (F::gin(B, ZM, p)) own_lo = F::gin(B, ZM, p) + zi;
+        if (F::gin(B, ZP, p)) own_hi = F::gin(B, ZP, p) + zi;
     }
-    auto own_at = [&](int zz) -> double2 {
-        const double* a = own + (int64_t)zz * plane;
+    auto own_at = [&](int zz, C& a, C& b) {
+        const T* q = own + (int64_t)zz * plane;
         if (FUSED) {
-            a = (zz == 0) ? own_lo : a;
-            a = (zz == nz + 1) ? own_hi : a;
+            q = (zz == 0) ? own_lo : q;
+            q = (zz == nz + 1) ? own_hi : q;
         }
-        return ld2(a);
+        Tr<T>::ld(q, a, b);
     };
-    const double* bown = SRC ? B->b + (int64_t)y_c * pitch + xa_c : nullptr;
+    const T* sown = SRC ? F::source(B) + (int64_t)y_c * pitch + xa_c : nullptr;
 
-    // halo role: the pair at hbase + zz * hstride (16-byte aligned)
+    // halo role: the pair at hbase + zz * hstride
     const int role = t < 32 ? 0 : t < 64 ? 1 : t < 64 + TY ? 2 : t < 64 + 2 * TY ? 3 : 4;
-    const double* hbase = own;
+    const T* hbase = own;
     int64_t hstride = plane;
     int hrow = 0, hcol = 0, hcomp = 0;
     bool hv0 = false, hv1 = false;
@@ -164,7 +259,7 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hv1 = hx + 1 <= x_end;
         hbase = src + (int64_t)hy * pitch + hx_c;
         if (FUSED) {
-            const double* g = (hy == 0) ? B->gin[YM][p] : (hy == ny + 1) ? B->gin[YP][p] : nullptr;
+            const T* g = (hy == 0) ? F::gin(B, YM, p) : (hy == ny + 1) ? F::gin(B, YP, p) : nullptr;
             if (g) {
                 hbase = g - ldy + (hx_c - 1);     // value (z - 1, x - 1)
                 hstride = ldy;
@@ -182,7 +277,7 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hcomp = (hx & 1) ? 0 : 1;
         hbase = src + (int64_t)hy_c * pitch + ps;
         if (FUSED) {
-            const double* g = (hx == 0) ? B->gin[XM][p] : (hx == nx + 1) ? B->gin[XP][p] : nullptr;
+            const T* g = (hx == 0) ? F::gin(B, XM, p) : (hx == nx + 1) ? F::gin(B, XP, p) : nullptr;
             if (g) {
                 const int fi = hy_c - 1;          // value (z - 1, y - 1)
                 hbase = g - ldx + (fi & ~1);
@@ -193,95 +288,102 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hrow = r + 1;
         hcol = role == 2 ? 1 : x_end - x0 + 2;
     }
-    auto halo_at = [&](int zz) -> double2 {
-        return ld2(hbase + (int64_t)zz * hstride);
-    };
 
     const int zf = it.z0 + 1;                     // first plane of the tile
     const int zl = it.z0 + it.zlen;               // last plane of the tile
-    double2 zm = own_at(zf - 1);
-    double2 c = own_at(zf);
-    double2 zp = own_at(zf + 1);
-    double2 h = halo_at(zf);
-    double2 bc = make_double2(0.0, 0.0);
+    C zm_a, zm_b, c_a, c_b, zp_a, zp_b, h_a, h_b;
+    C s_a = C(0), s_b = C(0);                     // source of the current plane
+    own_at(zf - 1, zm_a, zm_b);
+    own_at(zf, c_a, c_b);
+    own_at(zf + 1, zp_a, zp_b);
+    Tr<T>::ld(hbase + (int64_t)zf * hstride, h_a, h_b);
     if (SRC)
-        bc = ld2(bown + (int64_t)zf * plane);
+        Tr<T>::ld(sown + (int64_t)zf * plane, s_a, s_b);
 
     double acc = 0.0;
     for (int z = zf; z <= zl; ++z) {
         // the next planes go in flight first; the last iteration re-reads
         // planes it already holds (cache hits) instead of branching
         const int zn = min(z + 1, zl);
-        const double2 zq = own_at(min(z + 2, zl + 1));
-        const double2 hn = halo_at(zn);
-        double2 bn = make_double2(0.0, 0.0);
+        C zq_a, zq_b, hn_a, hn_b, sn_a = C(0), sn_b = C(0);
+        own_at(min(z + 2, zl + 1), zq_a, zq_b);
+        Tr<T>::ld(hbase + (int64_t)zn * hstride, hn_a, hn_b);
         if (SRC)
-            bn = ld2(bown + (int64_t)zn * plane);
+            Tr<T>::ld(sown + (int64_t)zn * plane, sn_a, sn_b);
 
-        double (*T)[LW] = S[z & 1];
+        C (*L)[LW] = S[z & 1];
         if (a_ok) {
-            T[ly + 1][2 * lx + 2] = c.x;
+            L[ly + 1][2 * lx + 2] = c_a;
             if (b_ok)
-                T[ly + 1][2 * lx + 3] = c.y;
+                L[ly + 1][2 * lx + 3] = c_b;
         }
         if (role <= 1) {
-            if (hv0) T[hrow][hcol] = h.x;
-            if (hv1) T[hrow][hcol + 1] = h.y;
+            if (hv0) L[hrow][hcol] = h_a;
+            if (hv1) L[hrow][hcol + 1] = h_b;
         } else if (role <= 3 && hv0) {
-            T[hrow][hcol] = hcomp ? h.y : h.x;
+            L[hrow][hcol] = hcomp ? h_b : h_a;
         }
         __syncthreads();
-        const double xm_a = T[ly + 1][2 * lx + 1];
-        const double xp_a = b_ok ? c.y : T[ly + 1][2 * lx + 3];
-        double sa = xm_a + xp_a;
-        sa = sa + T[ly][2 * lx + 2];
-        sa = sa + T[ly + 2][2 * lx + 2];
-        sa = sa + zm.x;
-        sa = sa + zp.x;
-        double sb = c.x + T[ly + 1][2 * lx + 4];
-        sb = sb + T[ly][2 * lx + 3];
-        sb = sb + T[ly + 2][2 * lx + 3];
-        sb = sb + zm.y;
-        sb = sb + zp.y;
+        const C xm_a = L[ly + 1][2 * lx + 1];
+        const C xp_a = b_ok ? c_b : L[ly + 1][2 * lx + 3];
+        C sa = xm_a + xp_a;
+        sa = sa + L[ly][2 * lx + 2];
+        sa = sa + L[ly + 2][2 * lx + 2];
+        sa = sa + zm_a;
+        sa = sa + zp_a;
+        C sb = c_a + L[ly + 1][2 * lx + 4];
+        sb = sb + L[ly][2 * lx + 3];
+        sb = sb + L[ly + 2][2 * lx + 3];
+        sb = sb + zm_b;
+        sb = sb + zp_b;
         if (RES) {
-            const double ra = SRC ? (bc.x + sa) - 6.0 * c.x : sa - 6.0 * c.x;
-            const double rb = SRC ? (bc.y + sb) - 6.0 * c.y : sb - 6.0 * c.y;
-            acc = acc + (a_ok ? ra * ra : 0.0);
-            acc = acc + (b_ok ? rb * rb : 0.0);
+            const C ra = SRC ? (s_a + sa) - six * c_a : sa - six * c_a;
+            const C rb = SRC ? (s_b + sb) - six * c_b : sb - six * c_b;
+            acc = acc + (a_ok ? (double)(ra * ra) : 0.0);
+            acc = acc + (b_ok ? (double)(rb * rb) : 0.0);
+            if constexpr (RLO) {
+                // r rounded to the refinement's storage, through binary32
+                R* o = static_cast<R*>(B->rlo) + (int64_t)z * B->lplane + (int64_t)y * B->lpitch + xa;
+                if constexpr (std::is_same<R, double>::value) {
+                    if (a_ok) Tr<double>::st(o, ra, rb);
+                } else {
+                    if (a_ok) Tr<R>::st(o, (float)ra, (float)rb);
+                }
+            }
         }
         if (STORE) {
-            const double va = SRC ? (sa + bc.x) / 6.0 : sa / 6.0;
+            const C va = SRC ? (sa + s_a) / six : sa / six;
             // past the last cell of a row the pair's second slot is the
             // x = nx + 1 ghost: write back the value it already holds
-            const double vb = b_ok ? (SRC ? (sb + bc.y) / 6.0 : sb / 6.0) : c.y;
+            const C vb = b_ok ? (SRC ? (sb + s_b) / six : sb / six) : c_b;
             if (a_ok)
-                st2(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
+                Tr<T>::st(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
             if (FUSED) {
                 const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
                 const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
                 const int64_t zfi = (int64_t)(y - 1) * ldy + (xa - 1);
-                double* oxm = B->gout[XM][p ^ 1];
-                double* oxp = B->gout[XP][p ^ 1];
-                double* oym = B->gout[YM][p ^ 1];
-                double* oyp = B->gout[YP][p ^ 1];
-                double* ozm = B->gout[ZM][p ^ 1];
-                double* ozp = B->gout[ZP][p ^ 1];
+                T* oxm = F::gout(B, XM, p ^ 1);
+                T* oxp = F::gout(B, XP, p ^ 1);
+                T* oym = F::gout(B, YM, p ^ 1);
+                T* oyp = F::gout(B, YP, p ^ 1);
+                T* ozm = F::gout(B, ZM, p ^ 1);
+                T* ozp = F::gout(B, ZP, p ^ 1);
                 // a face row's padding slot takes the second value of a
                 // pair that ends past the face (ld is even)
-                if (a_ok && xa == 1 && oxm) st1(oxm + xfi, va);
-                if (a_ok && xa == nx && oxp) st1(oxp + xfi, va);
-                if (b_ok && xa + 1 == nx && oxp) st1(oxp + xfi, vb);
-                if (a_ok && y == 1 && oym) st2(oym + yfi, va, vb);
-                if (a_ok && y == ny && oyp) st2(oyp + yfi, va, vb);
-                if (a_ok && z == 1 && ozm) st2(ozm + zfi, va, vb);
-                if (a_ok && z == nz && ozp) st2(ozp + zfi, va, vb);
+                if (a_ok && xa == 1 && oxm) Tr<T>::st1(oxm + xfi, va);
+                if (a_ok && xa == nx && oxp) Tr<T>::st1(oxp + xfi, va);
+                if (b_ok && xa + 1 == nx && oxp) Tr<T>::st1(oxp + xfi, vb);
+                if (a_ok && y == 1 && oym) Tr<T>::st(oym + yfi, va, vb);
+                if (a_ok && y == ny && oyp) Tr<T>::st(oyp + yfi, va, vb);
+                if (a_ok && z == 1 && ozm) Tr<T>::st(ozm + zfi, va, vb);
+                if (a_ok && z == nz && ozp) Tr<T>::st(ozp + zfi, va, vb);
             }
         }
-        zm = c;
-        c = zp;
-        zp = zq;
-        h = hn;
-        bc = bn;
+        zm_a = c_a; zm_b = c_b;
+        c_a = zp_a; c_b = zp_b;
+        zp_a = zq_a; zp_b = zq_b;
+        h_a = hn_a; h_b = hn_b;
+        s_a = sn_a; s_b = sn_b;
     }
     if (RES) {
         const double w = wave_sum(acc);
@@ -297,44 +399,162 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
     }
 }
 
-template <int TY, bool SRC>
-hipError_t sweep_ty(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
-                    bool resid, bool store, double* partials, hipStream_t s)
+template <typename T, int FIELD, int TY, bool SRC, typename R>
+hipError_t sweep_flags(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
+                       bool resid, bool store, double* partials, hipStream_t s)
 {
     const int grid = ((nitems + 7) / 8) * 8;
     const dim3 bs(32 * TY);
-#define JC_SWEEP_CASE(F, R, S)                                                                \
-    if (fused == F && resid == R && store == S) {                                            \
-        hipLaunchKernelGGL((k_sweep<TY, F, R, S, SRC>), dim3(grid), bs, 0, s, blocks, items,  \
-                           nitems, parity, partials);                                        \
-        return hipGetLastError();                                                            \
+#define JC_SWEEP_CASE(FU, RE, ST)                                                                    \
+    if (fused == FU && resid == RE && store == ST) {                                                \
+        hipLaunchKernelGGL((k_sweep<T, FIELD, TY, FU, RE, ST, SRC, R>), dim3(grid), bs, 0, s, blocks, \
+                           items, nitems, parity, partials);                                        \
+        return hipGetLastError();                                                                   \
     }
-    JC_SWEEP_CASE(false, false, true)
-    JC_SWEEP_CASE(false, true, true)
-    JC_SWEEP_CASE(false, true, false)
-    JC_SWEEP_CASE(true, false, true)
-    JC_SWEEP_CASE(true, true, true)
-    JC_SWEEP_CASE(true, true, false)
+    if constexpr (std::is_same<R, NoRlo>::value) {
+        if constexpr (FIELD == FIELD_U) {
+            JC_SWEEP_CASE(false, false, true)
+            JC_SWEEP_CASE(false, true, true)
+            JC_SWEEP_CASE(false, true, false)
+            JC_SWEEP_CASE(true, true, true)
+            JC_SWEEP_CASE(true, true, false)
+        }
+        JC_SWEEP_CASE(true, false, true)
+    } else {
+        JC_SWEEP_CASE(true, true, false)
+    }
 #undef JC_SWEEP_CASE
     return hipErrorInvalidValue;
 }
 
-template <int TY>
-hipError_t sweep_src(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
-                     bool resid, bool store, bool src, double* partials, hipStream_t s)
+template <typename T, int FIELD, bool SRC, typename R>
+hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
+                       bool fused, bool resid, bool store, double* partials, hipStream_t s)
 {
-    return src ? sweep_ty<TY, true>(blocks, items, nitems, parity, fused, resid, store, partials, s)
-               : sweep_ty<TY, false>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    switch (tile_y) {
+    case 4: return sweep_flags<T, FIELD, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 8: return sweep_flags<T, FIELD, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 16: return sweep_flags<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 32: return sweep_flags<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-// Fixed-order sum of one member's partials: each thread adds a strided
-// subsequence in order, then a fixed tree over the work-group.
+// First inner sweep of a refinement step: d_1 = lo((0 + r_lo) / 6)
+// (d_0 = 0, so no neighbour is read); writes copy 1 of d and its faces.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_ir_first(const BlockDesc* __restrict__ blocks)
+{
+    using C = typename Tr<T>::C;
+    const BlockDesc* B = blocks + blockIdx.y;
+    const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+    const int64_t lp = B->lpitch, ll = B->lplane;
+    const int64_t ldx = face_ld(ny), ldy = face_ld(nx);
+    const T* rl = static_cast<const T*>(B->rlo);
+    T* d = static_cast<T*>(B->d[1]);
+    const int npair = (nx + 1) / 2;
+    const int64_t rows = (int64_t)ny * nz;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % ny) + 1;
+        const int z = (int)(r / ny) + 1;
+        for (int k = threadIdx.x; k < npair; k += 256) {
+            const int xa = 2 * k + 1;
+            const bool b_ok = xa + 1 <= nx;
+            const int64_t at = (int64_t)z * ll + (int64_t)y * lp + xa;
+            C sa, sb;
+            Tr<T>::ld(rl + at, sa, sb);
+            const C zero = C(0);
+            const C va = (zero + sa) / C(6);
+            const C vb = (zero + sb) / C(6);
+            C ga, gb;
+            Tr<T>::ld(static_cast<const T*>(B->d[1]) + at, ga, gb);   // keeps the x = nx + 1 ghost
+            Tr<T>::st(d + at, va, b_ok ? vb : gb);
+            T* oxm = static_cast<T*>(B->lgout[XM][1]);
+            T* oxp = static_cast<T*>(B->lgout[XP][1]);
+            T* oym = static_cast<T*>(B->lgout[YM][1]);
+            T* oyp = static_cast<T*>(B->lgout[YP][1]);
+            T* ozm = static_cast<T*>(B->lgout[ZM][1]);
+            T* ozp = static_cast<T*>(B->lgout[ZP][1]);
+            const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
+            const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
+            const int64_t zfi = (int64_t)(y - 1) * ldy + (xa - 1);
+            if (xa == 1 && oxm) Tr<T>::st1(oxm + xfi, va);
+            if (xa == nx && oxp) Tr<T>::st1(oxp + xfi, va);
+            if (b_ok && xa + 1 == nx && oxp) Tr<T>::st1(oxp + xfi, vb);
+            if (y == 1 && oym) Tr<T>::st(oym + yfi, va, vb);
+            if (y == ny && oyp) Tr<T>::st(oyp + yfi, va, vb);
+            if (z == 1 && ozm) Tr<T>::st(ozm + zfi, va, vb);
+            if (z == nz && ozp) Tr<T>::st(ozp + zfi, va, vb);
+        }
+    }
+}
+
+// Outer update of the refinement: u(copy p) += (double) d(copy q) on the
+// interior; the updated face cells go to the u face buffers of slot p.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_ir_update(const BlockDesc* __restrict__ blocks, int p, int q)
+{
+    using C = typename Tr<T>::C;
+    const BlockDesc* B = blocks + blockIdx.y;
+    const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+    const int64_t ldx = face_ld(ny), ldy = face_ld(nx);
+    double* u = B->u[p];
+    const T* d = static_cast<const T*>(B->d[q]);
+    const int npair = (nx + 1) / 2;
+    const int64_t rows = (int64_t)ny * nz;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % ny) + 1;
+        const int z = (int)(r / ny) + 1;
+        for (int k = threadIdx.x; k < npair; k += 256) {
+            const int xa = 2 * k + 1;
+            const bool b_ok = xa + 1 <= nx;
+            double* up = u + (int64_t)z * B->plane + (int64_t)y * B->pitch + xa;
+            double ua, ub;
+            Tr<double>::ld(up, ua, ub);
+            C da, db;
+            Tr<T>::ld(d + (int64_t)z * B->lplane + (int64_t)y * B->lpitch + xa, da, db);
+            const double va = ua + (double)da;
+            const double vb = b_ok ? ub + (double)db : ub;
+            Tr<double>::st(up, va, vb);
+            double* oxm = B->gout[XM][p];
+            double* oxp = B->gout[XP][p];
+            double* oym = B->gout[YM][p];
+            double* oyp = B->gout[YP][p];
+            double* ozm = B->gout[ZM][p];
+            double* ozp = B->gout[ZP][p];
+            const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
+            const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
+            const int64_t zfi = (int64_t)(y - 1) * ldy + (xa - 1);
+            if (xa == 1 && oxm) Tr<double>::st1(oxm + xfi, va);
+            if (xa == nx && oxp) Tr<double>::st1(oxp + xfi, va);
+            if (b_ok && xa + 1 == nx && oxp) Tr<double>::st1(oxp + xfi, vb);
+            if (y == 1 && oym) Tr<double>::st(oym + yfi, va, vb);
+            if (y == ny && oyp) Tr<double>::st(oyp + yfi, va, vb);
+            if (z == 1 && ozm) Tr<double>::st(ozm + zfi, va, vb);
+            if (z == nz && ozp) Tr<double>::st(ozp + zfi, va, vb);
+        }
+    }
+}
+
+// Zero `words` 8-byte words at p (grid-stride).
+__global__ void __launch_bounds__(256)
+k_zero(uint64_t* __restrict__ p, int64_t words)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256)
+        *(uint64_t JC_GLOBAL*)(p + i) = 0;
+}
+
+// Fixed-order sum of one member's partials [ranges[2m], ranges[2m+1]):
+// each thread adds a strided subsequence in order, then a fixed tree over
+// the work-group.
 __global__ void __launch_bounds__(256)
 k_reduce(const double* __restrict__ partials, const int32_t* __restrict__ ranges,
          double* __restrict__ out)
 {
     const int m = blockIdx.x;
-    const int lo = ranges[m], hi = ranges[m + 1];
+    const int lo = ranges[2 * m], hi = ranges[2 * m + 1];
     double t = 0.0;
     for (int i = lo + (int)threadIdx.x; i < hi; i += 256)
         t = t + partials[i];
@@ -465,13 +685,84 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 {
     if (nitems <= 0)
         return hipSuccess;
-    switch (tile_y) {
-    case 4: return sweep_src<4>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
-    case 8: return sweep_src<8>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
-    case 16: return sweep_src<16>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
-    case 32: return sweep_src<32>(blocks, items, nitems, parity, fused, resid, store, src, partials, s);
+    return src ? sweep_tiles<double, FIELD_U, true, NoRlo>(blocks, items, nitems, parity, tile_y, fused, resid,
+                                                             store, partials, s)
+               : sweep_tiles<double, FIELD_U, false, NoRlo>(blocks, items, nitems, parity, tile_y, fused, resid,
+                                                              store, partials, s);
+}
+
+hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
+                              bool src, int lo_dtype, double* partials, hipStream_t s)
+{
+    if (nitems <= 0)
+        return hipSuccess;
+#define JC_IR_RES(RT)                                                                                  \
+    return src ? sweep_tiles<double, FIELD_U, true, RT>(blocks, items, nitems, parity, tile_y, true, true,  \
+                                                        false, partials, s)                                 \
+               : sweep_tiles<double, FIELD_U, false, RT>(blocks, items, nitems, parity, tile_y, true, true, \
+                                                         false, partials, s);
+    switch (lo_dtype) {
+    case 0: JC_IR_RES(double)
+    case 1: JC_IR_RES(float)
+    case 2: JC_IR_RES(bf16)
     default: return hipErrorInvalidValue;
     }
+#undef JC_IR_RES
+}
+
+hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
+                           int lo_dtype, hipStream_t s)
+{
+    if (nitems <= 0)
+        return hipSuccess;
+    switch (lo_dtype) {
+    case 0: return sweep_tiles<double, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_y, true, false,
+                                                             true, nullptr, s);
+    case 1: return sweep_tiles<float, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_y, true, false,
+                                                            true, nullptr, s);
+    case 2: return sweep_tiles<bf16, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_y, true, false,
+                                                           true, nullptr, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int lo_dtype, hipStream_t s)
+{
+    if (nblocks <= 0)
+        return hipSuccess;
+    const dim3 grid(512, nblocks);
+    switch (lo_dtype) {
+    case 0: hipLaunchKernelGGL(k_ir_first<double>, grid, dim3(256), 0, s, blocks); break;
+    case 1: hipLaunchKernelGGL(k_ir_first<float>, grid, dim3(256), 0, s, blocks); break;
+    case 2: hipLaunchKernelGGL(k_ir_first<bf16>, grid, dim3(256), 0, s, blocks); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int p, int q, int lo_dtype, hipStream_t s)
+{
+    if (nblocks <= 0)
+        return hipSuccess;
+    const dim3 grid(512, nblocks);
+    switch (lo_dtype) {
+    case 0: hipLaunchKernelGGL(k_ir_update<double>, grid, dim3(256), 0, s, blocks, p, q); break;
+    case 1: hipLaunchKernelGGL(k_ir_update<float>, grid, dim3(256), 0, s, blocks, p, q); break;
+    case 2: hipLaunchKernelGGL(k_ir_update<bf16>, grid, dim3(256), 0, s, blocks, p, q); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const int64_t words = (int64_t)(bytes / 8);
+    if (words <= 0)
+        return hipSuccess;
+    int64_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint64_t*>(p), words);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* partials, const int32_t* ranges, int nmembers, double* out,

@@ -7,6 +7,11 @@
 
 namespace jc {
 
+// bfloat16 storage: the upper 16 bits of a binary32.
+struct bf16 {
+    uint16_t bits;
+};
+
 // Block faces in the order -x, +x, -y, +y, -z, +z.
 enum Face { XM = 0, XP = 1, YM = 2, YP = 3, ZM = 4, ZP = 5 };
 

@@ -29,13 +29,16 @@ class Solver:
     kernels) or 'fused' (one launch per iteration)."""
 
     def __init__(self, grid, block_dims=None, cuts=None, mode="staged", with_source=False,
-                 tile_y=0, z_chunk=0, use_graphs=True, device="cuda:0", stream=None):
+                 tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None):
         self.grid = tuple(int(v) for v in grid)
         self.device = torch.device(device)
         self.opt = L.Options()
         self.opt.mode = {"staged": L.JC_MODE_STAGED, "fused": L.JC_MODE_FUSED}[mode]
         self.opt.with_source = int(bool(with_source))
         self.opt.ir_dtype = L.JC_NONE
+        if ir_dtype is not None:
+            self.opt.ir_enable = 1
+            self.opt.ir_dtype = {"f64": L.JC_F64, "f32": L.JC_F32, "bf16": L.JC_BF16}[ir_dtype]
         self.opt.tile_y = int(tile_y)
         self.opt.z_chunk = int(z_chunk)
         self.opt.use_graphs = int(bool(use_graphs))
@@ -154,6 +157,24 @@ class Solver:
             out["history"] = [buf[i] for i in range(info.history_len)]
         return out
 
+    def solve_ir(self, inner=50, rtol=1e-10, max_inner=20000, history=False):
+        """Mixed-precision iterative refinement (needs ir_dtype at creation).
+        Returns a dict like solve(); iters counts inner sweeps, outer the
+        residual checks."""
+        info = L.SolveInfo()
+        buf = None
+        if history:
+            cap = max_inner // max(inner, 1) + 3
+            buf = (ctypes.c_double * cap)()
+            info.history = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+            info.history_cap = cap
+        st = check(L.lib.jc_solve_ir(self._ctx, int(inner), float(rtol), int(max_inner), ctypes.byref(info)))
+        out = dict(iters=info.iters, outer=info.outer, rel_resid=info.rel_resid, abs_resid=info.abs_resid,
+                   r0=info.r0, status=st, converged=(st == L.JC_OK))
+        if buf is not None:
+            out["history"] = [buf[i] for i in range(info.history_len)]
+        return out
+
     def synchronize(self):
         self.stream.synchronize()
 
@@ -236,3 +257,54 @@ def footprint(grid, block_dims=None, with_source=False, mode="staged"):
     bd = block_dims if block_dims is not None else grid
     check(L.lib.jc_footprint(L.i64(grid), L.i64(bd), ctypes.byref(opt), ctypes.byref(fp)))
     return int(fp.value)
+
+
+class Group:
+    """Several bound, loaded Solvers swept by shared launches (libjc group).
+
+    The members must not be used on their own streams while the group
+    exists; close() (or leaving a with-block) releases it."""
+
+    def __init__(self, solvers, use_graphs=True, stream=None):
+        self.solvers = list(solvers)
+        dev = self.solvers[0].device
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s._ctx.value for s in self.solvers])
+        self._g = ctypes.c_void_p()
+        check(L.lib.jc_group_create(arr, len(self.solvers), ctypes.c_void_p(_stream_handle(self.stream)),
+                                    1 if use_graphs else 0, ctypes.byref(self._g)))
+        fp = ctypes.c_size_t()
+        check(L.lib.jc_group_footprint(self._g, ctypes.byref(fp)))
+        self.scratch = torch.empty(int(fp.value) + 256, dtype=torch.uint8, device=dev)
+        base = self.scratch.data_ptr()
+        off = (-base) % 256
+        self.scratch.record_stream(self.stream)
+        check(L.lib.jc_group_bind(self._g, ctypes.c_void_p(base + off), int(fp.value)))
+
+    def iterate(self, n):
+        check(L.lib.jc_group_iterate(self._g, int(n)))
+
+    def residuals(self):
+        out = (ctypes.c_double * len(self.solvers))()
+        check(L.lib.jc_group_residuals(self._g, out))
+        return list(out)
+
+    def close(self):
+        if self._g:
+            L.lib.jc_group_destroy(self._g)
+            self._g = ctypes.c_void_p()
+            for s in self.solvers:
+                s.stream.wait_stream(self.stream)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

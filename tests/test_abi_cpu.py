@@ -226,3 +226,36 @@ def test_tile_info_and_items():
     assert tuple(out) == (64, 4, 64, 8 * 4 * 64 * 4)
     assert L.lib.jc_num_items(ctx) == out[3]
     L.lib.jc_destroy(ctx)
+
+
+def test_ir_options_validation_and_footprint():
+    opt = L.Options()
+    opt.ir_enable = 1
+    opt.ir_dtype = 7
+    ctx = ctypes.c_void_p()
+    assert L.lib.jc_create(L.i64((8, 8, 8)), L.i64((8, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    sizes = {}
+    for name, dt in (("none", None), ("f64", L.JC_F64), ("f32", L.JC_F32), ("bf16", L.JC_BF16)):
+        o = L.Options()
+        o.ir_dtype = L.JC_NONE
+        if dt is not None:
+            o.ir_enable = 1
+            o.ir_dtype = dt
+        fp = ctypes.c_size_t()
+        check(L.lib.jc_footprint(L.i64((128, 128, 128)), L.i64((64, 64, 64)), ctypes.byref(o), ctypes.byref(fp)))
+        sizes[name] = fp.value
+    # three refinement arrays per block (d twice, r_lo) in the storage
+    # format; rows are padded to whole 128-byte lines (64 bf16 values)
+    cells = 8 * 66 * 66 * 66
+    for name, es in (("f64", 8), ("f32", 4), ("bf16", 2)):
+        extra = sizes[name] - sizes["none"]
+        assert 3 * cells * es <= extra <= 3 * cells * es * 2.2, name
+    assert sizes["f64"] > sizes["f32"] > sizes["bf16"] > sizes["none"]
+
+
+def test_solve_ir_needs_refinement_buffers():
+    st, ctx = create((16, 16, 16), (16, 16, 16))
+    info = L.SolveInfo()
+    assert L.lib.jc_solve_ir(ctx, 50, 1e-10, 100, ctypes.byref(info)) == L.JC_ERR_STATE
+    L.lib.jc_destroy(ctx)
