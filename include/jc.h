@@ -264,6 +264,18 @@ int64_t jc_iterations(const jc_ctx* ctx);
 /* Current tile shape and launch parameters: {tile_x, tile_y, z_chunk, items}. */
 int jc_tile_info(const jc_ctx* ctx, int64_t out[4]);
 
+/* ---- synthetic inputs ------------------------------------------------- */
+
+/* Fill a device global padded binary64 array (grid = interior nx, ny, nz)
+ * with the seeded synthetic field of the Jacobi3D workloads: kind 0 =
+ * Dirichlet shell U[0,1), interior 0; kind 1 = source, interior
+ * 2 U[0,1) - 1, shell 0.  SplitMix64 in counter form: the field's
+ * generator is seeded with output kind + 1 of SplitMix64(seed) and the
+ * cell at flat padded index i takes output i + 1; U = top 53 bits * 2^-53.
+ * Enqueued on hip_stream.  JC_ERR_INVALID on bad arguments. */
+int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed, int kind,
+                   void* hip_stream);
+
 /* ---- measurement ----------------------------------------------------- */
 
 /* enable != 0: bracket every kernel launch of this context with HIP events

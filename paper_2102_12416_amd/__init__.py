@@ -6,6 +6,6 @@ streams.  Importing it fails if libjc.so has not been built.
 """
 from . import _lib
 from ._lib import JcError
-from .solver import Group, Solver, footprint, min_surface_parts
+from .solver import Group, Solver, footprint, min_surface_parts, synth_field
 
-__all__ = ["Group", "Solver", "JcError", "footprint", "min_surface_parts", "_lib"]
+__all__ = ["Group", "Solver", "JcError", "footprint", "min_surface_parts", "synth_field", "_lib"]

@@ -84,6 +84,7 @@ SIGNATURES = {
     "jc_group_iterate": (ctypes.c_int, [VP, I64]),
     "jc_group_residuals": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
     "jc_group_destroy": (None, [VP]),
+    "jc_synth_field": (ctypes.c_int, [VP, I64P, ctypes.c_uint64, ctypes.c_int, VP]),
     "jc_num_blocks": (I64, [CTX]),
     "jc_num_pairs": (I64, [CTX]),
     "jc_num_items": (I64, [CTX]),

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libjc.so")
 
-SOURCES = ["jc_kernels.hip", "jc_host.cpp", "jc_group.cpp"]
+SOURCES = ["jc_kernels.hip", "jc_synth.hip", "jc_host.cpp", "jc_group.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

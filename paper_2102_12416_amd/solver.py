@@ -308,3 +308,15 @@ class Group:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def synth_field(grid, seed, kind, device="cuda:0", stream=None):
+    """Device tensor (nz+2, ny+2, nx+2) float64 with the seeded synthetic
+    boundary field (kind 0) or source (kind 1), generated on the GPU."""
+    nx, ny, nz = (int(v) for v in grid)
+    dev = torch.device(device)
+    out = torch.empty((nz + 2, ny + 2, nx + 2), dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    check(L.lib.jc_synth_field(ctypes.c_void_p(out.data_ptr()), L.i64((nx, ny, nz)), int(seed) & ((1 << 64) - 1),
+                               int(kind), ctypes.c_void_p(_stream_handle(st))))
+    return out

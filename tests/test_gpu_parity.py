@@ -300,3 +300,14 @@ def test_768_overdecomposed_full_size(variant):
         one.iterate(500)
         single = one.store().cpu().numpy()
     assert np.array_equal(dec, single)
+
+
+@pytest.mark.parametrize("n,seed", [((13, 7, 5), 1), ((64, 40, 33), 12416), ((3, 130, 2), 99)])
+def test_device_synth_matches_input_module(n, seed):
+    """The device generator reproduces the host input recipe bit for bit."""
+    from paper_2102_12416_amd import synth_field
+    say("synth", n, seed)
+    g = synth_field(n, seed, 0).cpu().numpy()
+    b = synth_field(n, seed, 1).cpu().numpy()
+    assert np.array_equal(g, synth.boundary_field(n, seed=seed))
+    assert np.array_equal(b, synth.source_field(n, seed=seed))

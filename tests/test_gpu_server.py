@@ -1,0 +1,69 @@
+"""The continuous-batching solve server on the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+from paper_2102_12416_amd.server import Request, Server, request_footprint, summarize  # noqa: E402
+
+REQS = [Request(id=0, arrival=0.0, n=24, precision="f64", seed=501),
+        Request(id=1, arrival=0.0, n=32, precision="f32", seed=502),
+        Request(id=2, arrival=0.0, n=20, precision="f32", seed=503),
+        Request(id=3, arrival=0.0, n=40, precision="f64", seed=504),
+        Request(id=4, arrival=0.0, n=28, precision="f32", seed=505),
+        Request(id=5, arrival=0.0, n=16, precision="f64", seed=506)]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def serve(reqs, budget=1 << 34, max_iter=1500):
+    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=max_iter, keep_fields=True)
+    res = srv.run(reqs, realtime=False)
+    return srv, res
+
+
+def test_each_result_same_alone_and_in_mix():
+    say("server alone vs mix")
+    _, mix = serve(REQS)
+    for r in REQS:
+        _, alone = serve([r])
+        a, m = alone[0], mix[r.id]
+        assert a.iters == m.iters and a.converged == m.converged, r.id
+        assert np.array_equal(a.field, m.field), r.id
+
+
+def test_results_certified_by_oracle():
+    say("server certificates")
+    _, res = serve(REQS, max_iter=3000)
+    for r, out in zip(REQS, res):
+        n = (r.n,) * 3
+        u0 = synth.boundary_field(n, seed=r.seed)
+        b = synth.source_field(n, seed=r.seed)
+        rel = oracle.c_residual_norm(out.field, b) / oracle.c_residual_norm(u0, b)
+        if out.converged:
+            assert rel <= 1e-10 * (1 + 1e-9), r.id
+        else:
+            assert out.iters == 3000
+        assert abs(rel - out.rel_resid) <= 1e-9 * max(rel, 1e-300) + 1e-14, r.id
+        if r.precision == "f64" and out.converged:
+            # the plain solve is the oracle's own Jacobi, stopped at the same check
+            ref, _ = oracle.c_jacobi(u0, out.iters, b)
+            assert np.array_equal(out.field, ref)
+
+
+def test_admission_respects_budget_and_rejects_oversize():
+    say("server budget")
+    sizes = [request_footprint(r.n, r.precision) for r in REQS]
+    budget = max(sizes) + min(sizes)           # forces queueing
+    big = Request(id=99, arrival=0.0, n=200, precision="f64", seed=1)
+    assert request_footprint(200, "f64") > budget
+    srv, res = serve(REQS + [big], budget=budget, max_iter=500)
+    assert srv.stats["peak_bytes"] <= budget
+    assert res[-1].rejected and not any(r.rejected for r in res[:-1])
+    s = summarize(res, makespan=1.0)
+    assert s["served"] == len(REQS) and s["rejected"] == 1
