@@ -39,11 +39,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="512_2x2x2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="512_2x2x2", choices=sorted(WORKLOADS) + ["refine", "serve"])
+    ap.add_argument("--ir-edge", type=int, default=1024, help="refine: grid edge of the per-sweep rates")
+    ap.add_argument("--ir-sweeps", type=int, default=100, help="refine: sweeps timed per precision")
+    ap.add_argument("--ir-solve-edges", type=int, nargs="*", default=[64, 128],
+                    help="refine: edges solved to 1e-10 end to end")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-capacity-requests", type=int, default=40)
+    ap.add_argument("--serve-max-edge", type=int, default=384)
+    ap.add_argument("--serve-max-iter", type=int, default=20000)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
     ap.add_argument("--seed", type=int, default=12416)
     ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")
     ap.add_argument("--z-chunk", type=int, default=0, help="planes per tile (0: library default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default tile shape instead of timing the candidates")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -105,6 +116,120 @@ def cpu_baseline(grid, seed, seconds):
                 host_cpus=len(os.sched_getaffinity(0)))
 
 
+def bench_refinement(args):
+    """Mixed precision at 1024^3 with a source: per-sweep rate of the plain
+    binary64 sweep and of the binary32 / bfloat16 inner sweeps (one outer
+    step of 50 inner sweeps each), and time to 1e-10 at smaller grids."""
+    import torch
+
+    from paper_2102_12416_amd import Solver, _lib as L, synth_field
+    n = args.ir_edge
+    grid = (n, n, n)
+    lups = float(n) ** 3
+    out = {"metric": "Jacobi3D refinement: GLUP/s per sweep and time to 1e-10 relative residual",
+           "unit": "GLUP/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "refine_%d" % n, "grid": list(grid), "inner_sweeps": 50,
+                      "source": "U[-1,1) SplitMix64", "boundary": "U[0,1) SplitMix64"}}
+    g = synth_field(grid, args.seed, 0)
+    b = synth_field(grid, args.seed, 1)
+    rates = {}
+    # plain binary64 sweeps with the source: 24 bytes per update
+    with Solver(grid, with_source=True, use_graphs=False) as s:
+        s.load(g, b)
+        s.autotune(reps=2)
+        s.iterate(5)
+        s.set_timing(True)
+        s.iterate(args.ir_sweeps)
+        ms, k = s.kernel_time(L.JC_K_SWEEP)
+        rates["f64_plain"] = dict(glups=lups * k / (ms * 1e-3) / 1e9, gbs=24 * lups * k / (ms * 1e-3) / 1e9,
+                                  ms_per_sweep=ms / k)
+        s.set_timing(False)
+    for dt, inner_bytes in (("f32", 12), ("bf16", 6)):
+        with Solver(grid, with_source=True, ir_dtype=dt, use_graphs=False) as s:
+            s.load(g, b)
+            s.set_timing(True)
+            t0 = time.perf_counter()
+            info = s.solve_ir(inner=50, rtol=0.0, max_inner=args.ir_sweeps)
+            wall = time.perf_counter() - t0
+            ms_in, k_in = s.kernel_time(L.JC_K_IR_INNER)
+            ms_out, k_out = s.kernel_time(L.JC_K_IR_OUTER)
+            s.set_timing(False)
+            total_ms = ms_in + ms_out
+            rates["%s_refined" % dt] = dict(
+                glups=lups * info["iters"] / (total_ms * 1e-3) / 1e9,
+                inner_gbs=inner_bytes * lups * k_in / (ms_in * 1e-3) / 1e9,
+                ms_per_inner_sweep=ms_in / max(k_in, 1), outer_ms_total=ms_out,
+                inner_sweeps=info["iters"], rel_resid=info["rel_resid"], wall_s=wall)
+    del g, b
+    torch.cuda.empty_cache()
+    out["per_sweep"] = rates
+    out["value"] = round(rates["f32_refined"]["glups"], 2)
+    # time to 1e-10 at grids where it is feasible in a benchmark run
+    ttt = {}
+    for m in args.ir_solve_edges:
+        gm = (m, m, m)
+        gg = synth_field(gm, args.seed, 0)
+        bb = synth_field(gm, args.seed, 1)
+        row = {}
+        with Solver(gm, with_source=True) as s:
+            s.load(gg, bb)
+            s.autotune(reps=2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.solve(rtol=1e-10, max_iter=2000000, check_every=50)
+            row["f64_plain"] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
+                                    rel=info["rel_resid"], converged=info["converged"])
+        for dt in ("f32", "bf16"):
+            with Solver(gm, with_source=True, ir_dtype=dt) as s:
+                s.load(gg, bb)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = s.solve_ir(inner=50, rtol=1e-10, max_inner=2000000)
+                row["%s_refined" % dt] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
+                                              rel=info["rel_resid"], converged=info["converged"])
+        ttt[str(m)] = row
+        print("[bench] time to 1e-10 at %d^3: %s" % (m, json.dumps(row)), file=sys.stderr, flush=True)
+    out["time_to_1e-10"] = ttt
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Continuous-batching server: closed-loop capacity, then Poisson
+    arrivals at 0.7x capacity; p50/p99 latency and solves/s."""
+    import synth
+    from paper_2102_12416_amd.server import Request, Server, summarize
+
+    def reqs(count, rate, seed):
+        return [Request(id=r["id"], arrival=r["arrival"], n=r["n"], precision=r["precision"], seed=r["seed"])
+                for r in synth.serving_requests(count, rate, seed=seed, lo=32, hi=args.serve_max_edge)]
+
+    budget = int(args.serve_budget_gb * (1 << 30))
+    cap_reqs = reqs(args.serve_capacity_requests, 0.0, args.seed + 1)
+    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter)
+    t0 = time.perf_counter()
+    res = srv.run(cap_reqs, realtime=False)
+    cap_time = time.perf_counter() - t0
+    cap = summarize(res, cap_time)
+    print("[bench] closed-loop capacity: %s" % json.dumps(cap), file=sys.stderr, flush=True)
+    rate = 0.7 * cap["solves_per_s"]
+    run_reqs = reqs(args.serve_requests, rate, args.seed)
+    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter)
+    t0 = time.perf_counter()
+    res = srv.run(run_reqs, realtime=True)
+    span = time.perf_counter() - t0
+    summ = summarize(res, span)
+    out = {"metric": "served solves/s, p50/p99 latency at 1e-10 relative residual or the sweep cap",
+           "value": round(summ["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "f64 / f32-refined",
+           "config": {"workload": "serve", "requests": args.serve_requests, "rate_per_s": round(rate, 3),
+                      "edges": "log-uniform [32, %d]" % args.serve_max_edge, "precision": "Bernoulli(0.5) f64/f32",
+                      "rtol": 1e-10, "max_iter": args.serve_max_iter, "window": 50,
+                      "budget_gb": args.serve_budget_gb},
+           "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4), "summary": summ,
+           "capacity": cap, "server_stats": srv.stats}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +238,12 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "refine":
+        bench_refinement(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     import numpy as np
@@ -134,6 +265,10 @@ def main():
     s.load(u0)
     del u0
     nb = s.num_blocks
+    tuned = None
+    if not args.no_autotune and not (args.tile_y or args.z_chunk):
+        tuned = s.autotune(reps=3)
+        print("[bench] autotuned tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr, flush=True)
     tiles = s.tile_info()
     s.iterate(args.warmup)
     s.synchronize()
@@ -184,6 +319,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
+                   "tile_autotuned": tuned is not None,
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
         "hbm_gbs_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "pct_hbm_peak_step": round(100 * step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),

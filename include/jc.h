@@ -276,6 +276,23 @@ int jc_tile_info(const jc_ctx* ctx, int64_t out[4]);
 int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed, int kind,
                    void* hip_stream);
 
+/* ---- tile shape ------------------------------------------------------ */
+
+/* Set the sweep's tile shape: tile_y rows (4, 8, 16 or 32) and z_chunk
+ * planes per work item (>= 1, within the work-list region sized at
+ * creation: >= 16 always fits).  Results are bitwise independent of the
+ * shape; residual norms change in the last bits (reduction order).
+ * Uploads the new work list (waits for the stream when bound). */
+int jc_set_tiles(jc_ctx* ctx, int tile_y, int z_chunk);
+
+/* Time `reps` sweeps of every candidate shape (tile_y in {4,8,16,32} x
+ * z_chunk in {16, 32, 64, ..., depth}) on the bound stream and keep the
+ * fastest; out = {tile_y, z_chunk, microseconds per sweep}.  The trial
+ * sweeps write only the other ping-pong copy and face slot, so the
+ * current iterate and iteration count are unchanged.  Waits for the
+ * stream.  Needs a loaded context. */
+int jc_autotune(jc_ctx* ctx, int reps, int64_t out[3]);
+
 /* ---- measurement ----------------------------------------------------- */
 
 /* enable != 0: bracket every kernel launch of this context with HIP events

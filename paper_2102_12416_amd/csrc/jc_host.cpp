@@ -1036,6 +1036,108 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
     return status;
 }
 
+int jc_set_tiles(jc_ctx* c, int tile_y, int z_chunk)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    bool ok = false;
+    for (int t : kTileYCandidates)
+        ok = ok || t == tile_y;
+    if (!ok || z_chunk < 1)
+        return fail(JC_ERR_INVALID, "tile_y must be 4, 8, 16 or 32 and z_chunk >= 1");
+    if (items_for(c, tile_y, z_chunk) > c->max_items)
+        return fail(JC_ERR_INVALID, "z_chunk too small for the work-list region");
+    c->tile_y = tile_y;
+    c->z_chunk = z_chunk;
+    build_items(c);
+    c->hranges[1] = (int32_t)c->items.size();
+    free_graphs(c);                        // graphs hold the old launch shapes
+    if (c->bound) {
+        JC_HIP(hipMemcpyAsync(c->d_items(), c->items.data(), sizeof(Item) * c->items.size(), hipMemcpyHostToDevice,
+                              c->stream));
+        JC_HIP(hipMemcpyAsync(c->d_ranges(), c->hranges, sizeof(c->hranges), hipMemcpyHostToDevice, c->stream));
+        JC_HIP(hipStreamSynchronize(c->stream));
+    }
+    return JC_OK;
+}
+
+int jc_autotune(jc_ctx* c, int reps, int64_t out[3])
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (reps < 1 || !out)
+        return fail(JC_ERR_INVALID, "reps must be >= 1 and out not NULL");
+    const bool fused = c->opt.mode == JC_MODE_FUSED && c->np() > 0;
+    if (fused && !c->fused_primed) {
+        st = do_pack(c, c->parity);
+        if (st != JC_OK)
+            return st;
+        c->fused_primed = true;
+    }
+    int64_t maxz = 1;
+    for (const HostBlock& b : c->blocks)
+        maxz = std::max(maxz, b.n[2]);
+    std::vector<int> zcs;
+    for (int z = kMinZChunk; z < maxz; z *= 2)
+        zcs.push_back(z);
+    zcs.push_back((int)maxz);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    JC_HIP(hipEventCreate(&e0));
+    JC_HIP(hipEventCreate(&e1));
+    const bool was_timing = c->timing;
+    c->timing = false;
+    double best = -1;
+    int bt = c->tile_y, bz = c->z_chunk;
+    for (int t : kTileYCandidates) {
+        for (int z : zcs) {
+            if (items_for(c, t, z) > c->max_items)
+                continue;
+            st = jc_set_tiles(c, t, z);
+            // trial sweeps read copy `parity` and write the other copy (and
+            // face slot parity ^ 1) without swapping: the iterate is unchanged
+            for (int rep = -1; rep < reps && st == JC_OK; ++rep) {
+                if (rep == 0)
+                    st = hipEventRecord(e0, c->stream) == hipSuccess ? JC_OK : JC_ERR_DEVICE;
+                if (st == JC_OK) {
+                    const hipError_t e = jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(),
+                                                          c->parity, c->tile_y, fused, false, true,
+                                                          c->opt.with_source != 0, nullptr, c->stream);
+                    if (e != hipSuccess)
+                        st = fail(JC_ERR_DEVICE, std::string("autotune launch: ") + hipGetErrorString(e));
+                }
+            }
+            float ms = 0;
+            if (st == JC_OK && hipEventRecord(e1, c->stream) == hipSuccess &&
+                hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+                if (best < 0 || ms < best) {
+                    best = ms;
+                    bt = t;
+                    bz = z;
+                }
+            } else if (st == JC_OK) {
+                st = fail(JC_ERR_DEVICE, "autotune timing failed");
+            }
+            if (st != JC_OK)
+                break;
+        }
+        if (st != JC_OK)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = was_timing;
+    if (st != JC_OK)
+        return st;
+    st = jc_set_tiles(c, bt, bz);
+    if (st != JC_OK)
+        return st;
+    out[0] = bt;
+    out[1] = bz;
+    out[2] = (int64_t)(best * 1000.0 / reps);     // microseconds per sweep
+    return JC_OK;
+}
+
 int64_t jc_num_blocks(const jc_ctx* c) { return c ? (int64_t)c->blocks.size() : 0; }
 int64_t jc_num_pairs(const jc_ctx* c) { return c ? (int64_t)c->pairs.size() : 0; }
 int64_t jc_num_items(const jc_ctx* c) { return c ? (int64_t)c->items.size() : 0; }

@@ -231,6 +231,16 @@ class Solver:
         flat = self.arena_view(info["u_off"][c], info["plane"] * (nz + 2))
         return flat.view(nz + 2, ny + 2, info["pitch"])
 
+    def set_tiles(self, tile_y, z_chunk):
+        check(L.lib.jc_set_tiles(self._ctx, int(tile_y), int(z_chunk)))
+
+    def autotune(self, reps=5):
+        """Pick the fastest tile shape for this context; returns
+        (tile_y, z_chunk, microseconds per sweep)."""
+        out = (ctypes.c_int64 * 3)()
+        check(L.lib.jc_autotune(self._ctx, int(reps), out))
+        return tuple(out)
+
     # -------------------------------------------------------------- timing
     def set_timing(self, enable=True):
         check(L.lib.jc_set_timing(self._ctx, int(bool(enable))))

@@ -259,3 +259,16 @@ def test_solve_ir_needs_refinement_buffers():
     info = L.SolveInfo()
     assert L.lib.jc_solve_ir(ctx, 50, 1e-10, 100, ctypes.byref(info)) == L.JC_ERR_STATE
     L.lib.jc_destroy(ctx)
+
+
+def test_set_tiles_validation_and_items():
+    st, ctx = create((200, 100, 96), (100, 100, 96))
+    assert st == 0
+    assert L.lib.jc_set_tiles(ctx, 5, 32) == L.JC_ERR_INVALID
+    assert L.lib.jc_set_tiles(ctx, 8, 0) == L.JC_ERR_INVALID
+    check(L.lib.jc_set_tiles(ctx, 16, 48))
+    out = (ctypes.c_int64 * 4)()
+    check(L.lib.jc_tile_info(ctx, out))
+    # 2 blocks x ceil(100/64) x ceil(100/16) x ceil(96/48)
+    assert tuple(out) == (64, 16, 48, 2 * 2 * 7 * 2)
+    L.lib.jc_destroy(ctx)

@@ -311,3 +311,21 @@ def test_device_synth_matches_input_module(n, seed):
     b = synth_field(n, seed, 1).cpu().numpy()
     assert np.array_equal(g, synth.boundary_field(n, seed=seed))
     assert np.array_equal(b, synth.source_field(n, seed=seed))
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_autotune_keeps_iterate_and_results(mode):
+    n = (96, 80, 72)
+    say("autotune", mode)
+    u0 = synth.boundary_field(n, seed=9)
+    ref, _ = oracle.c_jacobi(u0, 11, None)
+    with Solver(n, block_dims=(48, 80, 36), mode=mode) as s:
+        s.load(u0)
+        s.iterate(5)
+        before = s.store().cpu().numpy()
+        ty, zc, us = s.autotune(reps=2)
+        assert ty in (4, 8, 16, 32) and zc >= 16 and us > 0
+        assert s.iterations == 5
+        assert np.array_equal(s.store().cpu().numpy(), before)
+        s.iterate(6)
+        assert np.array_equal(s.store().cpu().numpy(), ref)
