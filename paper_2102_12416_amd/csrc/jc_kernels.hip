@@ -153,6 +153,34 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Correctly rounded s / 6 without the general division sequence
+// (Markstein, IBM J. Res. Dev. 34(1), 1990): with y = RN(1/6), q = RN(s y)
+// is a faithful quotient, r = s - 6q is exact through an FMA, and
+// RN(q + r y) is the correctly rounded quotient whenever it is not
+// subnormal.  Tiny s (and zero, for the sign of the result) take the IEEE
+// division; the result is bit-identical to s / 6 either way.
+__device__ __forceinline__ double div6(double s)
+{
+    const double y = 0x1.5555555555555p-3;
+    const double q = s * y;
+    const double r = __builtin_fma(-6.0, q, s);
+    double v = __builtin_fma(r, y, q);
+    if (__builtin_expect(__builtin_fabs(s) < 0x1p-1000, 0))
+        v = s / 6.0;
+    return v;
+}
+
+__device__ __forceinline__ float div6(float s)
+{
+    const float y = 0x1.555556p-3f;
+    const float q = s * y;
+    const float r = __builtin_fmaf(-6.0f, q, s);
+    float v = __builtin_fmaf(r, y, q);
+    if (__builtin_expect(__builtin_fabsf(s) < 0x1p-100f, 0))
+        v = s / 6.0f;
+    return v;
+}
+
 // One work-group sweeps a tile of 64 x cells by TY rows of one block,
 // marching along z.  Each thread owns two adjacent x cells of one row
 // (one aligned-pair load per plane: cell x = 1 of every row starts a
@@ -291,37 +319,46 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
 
     const int zf = it.z0 + 1;                     // first plane of the tile
     const int zl = it.z0 + it.zlen;               // last plane of the tile
-    C zm_a, zm_b, c_a, c_b, zp_a, zp_b, h_a, h_b;
-    C s_a = C(0), s_b = C(0);                     // source of the current plane
-    own_at(zf - 1, zm_a, zm_b);
-    own_at(zf, c_a, c_b);
-    own_at(zf + 1, zp_a, zp_b);
-    Tr<T>::ld(hbase + (int64_t)zf * hstride, h_a, h_b);
+    // Register rings: own cells of plane p in slot (p - zf) mod 4 (planes
+    // z-1 .. z+2 live at step z), halo and source of plane p in slot
+    // (p - zf) mod 2.  Every load lands in the slot it is consumed from, so
+    // no register is copied while its load is in flight (such a copy
+    // waits for every outstanding load).
+    C ra[4], rb[4], ha[2], hb[2], sa_[2], sb_[2];
+    own_at(zf - 1, ra[3], rb[3]);
+    own_at(zf, ra[0], rb[0]);
+    own_at(zf + 1, ra[1], rb[1]);
+    Tr<T>::ld(hbase + (int64_t)zf * hstride, ha[0], hb[0]);
+    sa_[0] = sa_[1] = sb_[0] = sb_[1] = C(0);
     if (SRC)
-        Tr<T>::ld(sown + (int64_t)zf * plane, s_a, s_b);
+        Tr<T>::ld(sown + (int64_t)zf * plane, sa_[0], sb_[0]);
 
     double acc = 0.0;
-    for (int z = zf; z <= zl; ++z) {
-        // the next planes go in flight first; the last iteration re-reads
-        // planes it already holds (cache hits) instead of branching
+    // one plane; K = (z - zf) mod 4, a compile-time slot number
+    auto step = [&](int z, auto kc) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int SM = (K + 3) & 3, SC = K, SP = (K + 1) & 3, SQ = (K + 2) & 3;
+        static_assert(K >= 0 && K < 4, "ring slot");
+        constexpr int HC = K & 1, HN = (K + 1) & 1;
+        // the next planes go in flight first; the last step re-reads planes
+        // it already holds (cache hits) instead of branching
         const int zn = min(z + 1, zl);
-        C zq_a, zq_b, hn_a, hn_b, sn_a = C(0), sn_b = C(0);
-        own_at(min(z + 2, zl + 1), zq_a, zq_b);
-        Tr<T>::ld(hbase + (int64_t)zn * hstride, hn_a, hn_b);
+        own_at(min(z + 2, zl + 1), ra[SQ], rb[SQ]);
+        Tr<T>::ld(hbase + (int64_t)zn * hstride, ha[HN], hb[HN]);
         if (SRC)
-            Tr<T>::ld(sown + (int64_t)zn * plane, sn_a, sn_b);
-
-        C (*L)[LW] = S[z & 1];
+            Tr<T>::ld(sown + (int64_t)zn * plane, sa_[HN], sb_[HN]);
+        const C c_a = ra[SC], c_b = rb[SC];
+        C (*L)[LW] = S[HC];
         if (a_ok) {
             L[ly + 1][2 * lx + 2] = c_a;
             if (b_ok)
                 L[ly + 1][2 * lx + 3] = c_b;
         }
         if (role <= 1) {
-            if (hv0) L[hrow][hcol] = h_a;
-            if (hv1) L[hrow][hcol + 1] = h_b;
+            if (hv0) L[hrow][hcol] = ha[HC];
+            if (hv1) L[hrow][hcol + 1] = hb[HC];
         } else if (role <= 3 && hv0) {
-            L[hrow][hcol] = hcomp ? h_b : h_a;
+            L[hrow][hcol] = hcomp ? hb[HC] : ha[HC];
         }
         __syncthreads();
         const C xm_a = L[ly + 1][2 * lx + 1];
@@ -329,33 +366,34 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         C sa = xm_a + xp_a;
         sa = sa + L[ly][2 * lx + 2];
         sa = sa + L[ly + 2][2 * lx + 2];
-        sa = sa + zm_a;
-        sa = sa + zp_a;
+        sa = sa + ra[SM];
+        sa = sa + ra[SP];
         C sb = c_a + L[ly + 1][2 * lx + 4];
         sb = sb + L[ly][2 * lx + 3];
         sb = sb + L[ly + 2][2 * lx + 3];
-        sb = sb + zm_b;
-        sb = sb + zp_b;
+        sb = sb + rb[SM];
+        sb = sb + rb[SP];
+        const C s_a = sa_[HC], s_b = sb_[HC];
         if (RES) {
-            const C ra = SRC ? (s_a + sa) - six * c_a : sa - six * c_a;
-            const C rb = SRC ? (s_b + sb) - six * c_b : sb - six * c_b;
-            acc = acc + (a_ok ? (double)(ra * ra) : 0.0);
-            acc = acc + (b_ok ? (double)(rb * rb) : 0.0);
+            const C r_a = SRC ? (s_a + sa) - six * c_a : sa - six * c_a;
+            const C r_b = SRC ? (s_b + sb) - six * c_b : sb - six * c_b;
+            acc = acc + (a_ok ? (double)(r_a * r_a) : 0.0);
+            acc = acc + (b_ok ? (double)(r_b * r_b) : 0.0);
             if constexpr (RLO) {
                 // r rounded to the refinement's storage, through binary32
                 R* o = static_cast<R*>(B->rlo) + (int64_t)z * B->lplane + (int64_t)y * B->lpitch + xa;
                 if constexpr (std::is_same<R, double>::value) {
-                    if (a_ok) Tr<double>::st(o, ra, rb);
+                    if (a_ok) Tr<double>::st(o, r_a, r_b);
                 } else {
-                    if (a_ok) Tr<R>::st(o, (float)ra, (float)rb);
+                    if (a_ok) Tr<R>::st(o, (float)r_a, (float)r_b);
                 }
             }
         }
         if (STORE) {
-            const C va = SRC ? (sa + s_a) / six : sa / six;
+            const C va = SRC ? div6(sa + s_a) : div6(sa);
             // past the last cell of a row the pair's second slot is the
             // x = nx + 1 ghost: write back the value it already holds
-            const C vb = b_ok ? (SRC ? (sb + s_b) / six : sb / six) : c_b;
+            const C vb = b_ok ? (SRC ? div6(sb + s_b) : div6(sb)) : c_b;
             if (a_ok)
                 Tr<T>::st(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
             if (FUSED) {
@@ -379,12 +417,21 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
                 if (a_ok && z == nz && ozp) Tr<T>::st(ozp + zfi, va, vb);
             }
         }
-        zm_a = c_a; zm_b = c_b;
-        c_a = zp_a; c_b = zp_b;
-        zp_a = zq_a; zp_b = zq_b;
-        h_a = hn_a; h_b = hn_b;
-        s_a = sn_a; s_b = sn_b;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    int z = zf;
+    for (; z + 3 <= zl; z += 4) {
+        step(z, I0{});
+        step(z + 1, I1{});
+        step(z + 2, I2{});
+        step(z + 3, I3{});
     }
+    if (z <= zl) step(z, I0{});
+    if (z + 1 <= zl) step(z + 1, I1{});
+    if (z + 2 <= zl) step(z + 2, I2{});
     if (RES) {
         const double w = wave_sum(acc);
         if ((t & 63) == 0)
@@ -465,8 +512,8 @@ k_ir_first(const BlockDesc* __restrict__ blocks)
             C sa, sb;
             Tr<T>::ld(rl + at, sa, sb);
             const C zero = C(0);
-            const C va = (zero + sa) / C(6);
-            const C vb = (zero + sb) / C(6);
+            const C va = div6(zero + sa);
+            const C vb = div6(zero + sb);
             C ga, gb;
             Tr<T>::ld(static_cast<const T*>(B->d[1]) + at, ga, gb);   // keeps the x = nx + 1 ghost
             Tr<T>::st(d + at, va, b_ok ? vb : gb);
