@@ -80,6 +80,15 @@ template <> struct Tr<double> {
         *(v2d JC_GLOBAL*)(p) = v;
     }
     __device__ static void st1(double* p, double a) { *(double JC_GLOBAL*)(p) = a; }
+    // streaming store: the new iterate is not read again before the next
+    // sweep, so it should not displace lines the current sweep re-reads
+    __device__ static void stn(double* p, double a, double b)
+    {
+        v2d v;
+        v.x = a;
+        v.y = b;
+        __builtin_nontemporal_store(v, (v2d JC_GLOBAL*)(p));
+    }
 };
 
 template <> struct Tr<float> {
@@ -98,6 +107,13 @@ template <> struct Tr<float> {
         *(v2f JC_GLOBAL*)(p) = v;
     }
     __device__ static void st1(float* p, float a) { *(float JC_GLOBAL*)(p) = a; }
+    __device__ static void stn(float* p, float a, float b)
+    {
+        v2f v;
+        v.x = a;
+        v.y = b;
+        __builtin_nontemporal_store(v, (v2f JC_GLOBAL*)(p));
+    }
 };
 
 template <> struct Tr<bf16> {
@@ -113,6 +129,10 @@ template <> struct Tr<bf16> {
         *(uint32_t JC_GLOBAL*)(p) = f32_to_bf16(a) | (f32_to_bf16(b) << 16);
     }
     __device__ static void st1(bf16* p, float a) { *(uint16_t JC_GLOBAL*)(p) = (uint16_t)f32_to_bf16(a); }
+    __device__ static void stn(bf16* p, float a, float b)
+    {
+        __builtin_nontemporal_store(f32_to_bf16(a) | (f32_to_bf16(b) << 16), (uint32_t JC_GLOBAL*)(p));
+    }
 };
 
 // Which arrays of a block a sweep works on: the iterate u (with source b)
@@ -395,7 +415,7 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
             // x = nx + 1 ghost: write back the value it already holds
             const C vb = b_ok ? (SRC ? div6(sb + s_b) : div6(sb)) : c_b;
             if (a_ok)
-                Tr<T>::st(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
+                Tr<T>::stn(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
             if (FUSED) {
                 const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
                 const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
