@@ -33,6 +33,12 @@ WORKLOADS = {
     "768_uneven": ((768, 768, 768), None, 12416, "fused"),
 }
 
+# Tile shapes picked by jc_autotune on an MI355X for the default mode
+# (rows per tile, planes per work item); other workloads tune at start-up.
+TUNED_TILES = {
+    "512_2x2x2": (32, 64),
+}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -55,6 +61,8 @@ def parse():
     ap.add_argument("--z-chunk", type=int, default=0, help="planes per tile (0: library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default tile shape instead of timing the candidates")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-tune even where a tuned shape is recorded for the workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -84,6 +92,23 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
                       "launches": 3 + reps, "ms_per_copy": round(ms, 4),
                       "copy_gbs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}))
+
+
+def recorded_traffic(workload, mode, tile):
+    """HBM bytes per sweep launch from the committed rocprofv3 counters, if
+    they were taken on the current kernel source and the same launch shape
+    (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sweep_%s_fp64.counters.json" % workload)
+    src = os.path.join(ROOT, "paper_2102_12416_amd", "csrc", "jc_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_source_sha256") != sha or rec.get("mode") != mode or list(rec.get("tile", [])) != list(tile):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -265,10 +290,16 @@ def main():
     s.load(u0)
     del u0
     nb = s.num_blocks
-    tuned = None
-    if not args.no_autotune and not (args.tile_y or args.z_chunk):
-        tuned = s.autotune(reps=3)
-        print("[bench] autotuned tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr, flush=True)
+    tile_source = "given" if (args.tile_y or args.z_chunk) else "library default"
+    if not (args.tile_y or args.z_chunk):
+        if args.workload in TUNED_TILES and mode == default_mode and not args.autotune:
+            s.set_tiles(*TUNED_TILES[args.workload])
+            tile_source = "tuned (jc_autotune on MI355X)"
+        elif not args.no_autotune:
+            tuned = s.autotune(reps=3)
+            tile_source = "jc_autotune at start-up"
+            print("[bench] autotuned tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr,
+                  flush=True)
     tiles = s.tile_info()
     s.iterate(args.warmup)
     s.synchronize()
@@ -319,13 +350,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
-                   "tile_autotuned": tuned is not None,
+                   "tile_source": tile_source,
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
         "hbm_gbs_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "pct_hbm_peak_step": round(100 * step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "kernel": "k_sweep" if mode == "staged" else "k_sweep(fused)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(args.workload, mode,
+                                                 [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]]),
                      "bytes_per_launch": sweep_bytes, "avg_launch_ms": round(avg_ms, 5)},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in ktime.items() if v[1]},
     }
