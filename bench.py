@@ -51,7 +51,8 @@ def parse():
     ap.add_argument("--ir-solve-edges", type=int, nargs="*", default=[64, 128],
                     help="refine: edges solved to 1e-10 end to end")
     ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--serve-capacity-requests", type=int, default=40)
+    ap.add_argument("--serve-capacity-requests", type=int, default=0,
+                    help="requests of the closed-loop capacity run (0: the same set as the timed run)")
     ap.add_argument("--serve-max-edge", type=int, default=384)
     ap.add_argument("--serve-max-iter", type=int, default=20000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -229,7 +230,9 @@ def bench_serve(args):
                 for r in synth.serving_requests(count, rate, seed=seed, lo=32, hi=args.serve_max_edge)]
 
     budget = int(args.serve_budget_gb * (1 << 30))
-    cap_reqs = reqs(args.serve_capacity_requests, 0.0, args.seed + 1)
+    # capacity: the same request mix, all queued at once (closed loop)
+    ncap = args.serve_capacity_requests or args.serve_requests
+    cap_reqs = reqs(ncap, 0.0, args.seed)
     srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter)
     t0 = time.perf_counter()
     res = srv.run(cap_reqs, realtime=False)
