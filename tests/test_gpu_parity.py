@@ -329,3 +329,27 @@ def test_autotune_keeps_iterate_and_results(mode):
         assert np.array_equal(s.store().cpu().numpy(), before)
         s.iterate(6)
         assert np.array_equal(s.store().cpu().numpy(), ref)
+
+
+def test_division_edge_values_bitwise():
+    """Dirichlet values that make neighbour sums zero, negative zero,
+    subnormal or huge: the sweep's quotient is the correctly rounded s / 6
+    bit for bit, signs of zero included."""
+    n = (9, 8, 7)
+    say("division edge values")
+    rng = np.random.default_rng(31)
+    special = np.array([0.0, -0.0, 5e-324, -5e-324, 1e-310, 2.2250738585072014e-308, 1e-300, -3.5e-320,
+                        1e300, -1.7e308, 6.0, -6.0, 1.0 / 3.0])
+    u0 = np.zeros((n[2] + 2, n[1] + 2, n[0] + 2))
+    shell = np.ones(u0.shape, bool)
+    shell[1:-1, 1:-1, 1:-1] = False
+    u0[shell] = rng.choice(special, size=int(shell.sum()))
+    u0[1:-1, 1:-1, 1:-1] = -0.0
+    ref = u0
+    for _ in range(3):
+        ref = oracle.sweep(ref)
+    with Solver(n, block_dims=(5, 4, 7)) as s:
+        s.load(u0)
+        s.iterate(3)
+        got = s.store().cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
