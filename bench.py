@@ -36,7 +36,7 @@ WORKLOADS = {
 # Tile shapes picked by jc_autotune on an MI355X for the default mode
 # (rows per tile, planes per work item); other workloads tune at start-up.
 TUNED_TILES = {
-    "512_2x2x2": (32, 64),
+    "512_2x2x2": (64, 32, 64),
 }
 
 
@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
     ap.add_argument("--seed", type=int, default=12416)
+    ap.add_argument("--tile-x", type=int, default=0, help="cells per tile row, 32 or 64 (0: library default)")
     ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")
     ap.add_argument("--z-chunk", type=int, default=0, help="planes per tile (0: library default)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -289,19 +290,21 @@ def main():
         kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
     print("[bench] workload %s mode %s: building inputs" % (args.workload, mode), file=sys.stderr, flush=True)
     u0 = synth.boundary_field(grid, seed=args.seed)
-    s = Solver(grid, mode=mode, use_graphs=False, tile_y=args.tile_y, z_chunk=args.z_chunk, **kw)
+    s = Solver(grid, mode=mode, use_graphs=False, tile_x=args.tile_x, tile_y=args.tile_y, z_chunk=args.z_chunk,
+               **kw)
     s.load(u0)
     del u0
     nb = s.num_blocks
-    tile_source = "given" if (args.tile_y or args.z_chunk) else "library default"
-    if not (args.tile_y or args.z_chunk):
+    given = bool(args.tile_x or args.tile_y or args.z_chunk)
+    tile_source = "given" if given else "library default"
+    if not given:
         if args.workload in TUNED_TILES and mode == default_mode and not args.autotune:
             s.set_tiles(*TUNED_TILES[args.workload])
             tile_source = "tuned (jc_autotune on MI355X)"
         elif not args.no_autotune:
             tuned = s.autotune(reps=3)
             tile_source = "jc_autotune at start-up"
-            print("[bench] autotuned tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr,
+            print("[bench] autotuned tile_x=%d tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr,
                   flush=True)
     tiles = s.tile_info()
     s.iterate(args.warmup)

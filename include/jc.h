@@ -82,7 +82,8 @@ typedef struct jc_options {
     int tile_y;          /* rows per tile; 0 = auto */
     int z_chunk;         /* planes per tile; 0 = auto */
     int use_graphs;      /* 1: capture jc_iterate windows as HIP graphs */
-    int debug_epochs;    /* 1: stamp face buffers with the iteration and check them */
+    int debug_epochs;    /* reserved, must be 0 */
+    int tile_x;          /* cells per tile row: 32 or 64; 0 = auto (fewest idle lanes) */
 } jc_options;
 
 /* Result of a solve. */
@@ -261,7 +262,7 @@ int jc_block_info(const jc_ctx* ctx, int64_t i, int64_t out[17]);
 int jc_pair_info(const jc_ctx* ctx, int64_t i, int64_t out[10]);
 /* Iterations performed since the last jc_load_field(U). */
 int64_t jc_iterations(const jc_ctx* ctx);
-/* Current tile shape and launch parameters: {tile_x, tile_y, z_chunk, items}. */
+/* Current tile shape and work-list length: {tile_x, tile_y, z_chunk, items}. */
 int jc_tile_info(const jc_ctx* ctx, int64_t out[4]);
 
 /* ---- synthetic inputs ------------------------------------------------- */
@@ -278,20 +279,21 @@ int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed
 
 /* ---- tile shape ------------------------------------------------------ */
 
-/* Set the sweep's tile shape: tile_y rows (4, 8, 16 or 32) and z_chunk
- * planes per work item (>= 1, within the work-list region sized at
- * creation: >= 16 always fits).  Results are bitwise independent of the
- * shape; residual norms change in the last bits (reduction order).
- * Uploads the new work list (waits for the stream when bound). */
-int jc_set_tiles(jc_ctx* ctx, int tile_y, int z_chunk);
+/* Set the sweep's tile shape: tile_x cells per row (32 or 64), tile_y
+ * rows (4, 8, 16 or 32) and z_chunk planes per work item (>= 1, within
+ * the work-list region sized at creation: >= 16 always fits).  Results
+ * are bitwise independent of the shape; residual norms change in the last
+ * bits (reduction order).  Uploads the new work list (waits for the stream
+ * when bound). */
+int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 
-/* Time `reps` sweeps of every candidate shape (tile_y in {4,8,16,32} x
- * z_chunk in {16, 32, 64, ..., depth}) on the bound stream and keep the
- * fastest; out = {tile_y, z_chunk, microseconds per sweep}.  The trial
- * sweeps write only the other ping-pong copy and face slot, so the
- * current iterate and iteration count are unchanged.  Waits for the
- * stream.  Needs a loaded context. */
-int jc_autotune(jc_ctx* ctx, int reps, int64_t out[3]);
+/* Time `reps` sweeps of every candidate shape (tile_x in {64, 32} x
+ * tile_y in {4,8,16,32} x z_chunk in {16, 32, 64, ..., depth}) on the
+ * bound stream and keep the fastest; out = {tile_x, tile_y, z_chunk,
+ * microseconds per sweep}.  The trial sweeps write only the other
+ * ping-pong copy and face slot, so the current iterate and iteration count
+ * are unchanged.  Waits for the stream.  Needs a loaded context. */
+int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);
 
 /* ---- measurement ----------------------------------------------------- */
 

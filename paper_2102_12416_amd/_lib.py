@@ -41,7 +41,7 @@ class JcError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("with_source", ctypes.c_int), ("ir_dtype", ctypes.c_int),
                 ("ir_enable", ctypes.c_int), ("tile_y", ctypes.c_int), ("z_chunk", ctypes.c_int),
-                ("use_graphs", ctypes.c_int), ("debug_epochs", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("debug_epochs", ctypes.c_int), ("tile_x", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -92,7 +92,7 @@ SIGNATURES = {
     "jc_block_info": (ctypes.c_int, [CTX, I64, I64P]),
     "jc_pair_info": (ctypes.c_int, [CTX, I64, I64P]),
     "jc_tile_info": (ctypes.c_int, [CTX, I64P]),
-    "jc_set_tiles": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.c_int]),
+    "jc_set_tiles": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "jc_autotune": (ctypes.c_int, [CTX, ctypes.c_int, I64P]),
     "jc_set_timing": (ctypes.c_int, [CTX, ctypes.c_int]),
     "jc_kernel_time": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_double), I64P]),

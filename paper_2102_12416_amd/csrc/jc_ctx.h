@@ -78,6 +78,7 @@ struct jc_ctx {
     std::vector<HostBlock> blocks;
     std::vector<HostPair> pairs;
     int64_t max_slow = 0, max_fast = 0, max_count = 0;
+    int tile_x = 64;
     int tile_y = 8;
     int z_chunk = 0;
     std::vector<Item> items;

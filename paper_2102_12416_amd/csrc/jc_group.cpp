@@ -115,7 +115,7 @@ int group_sweep(jc_group* g)
     for (const Class& k : g->classes) {
         const int n = (int)k.items.size();
         if (!k.ir) {
-            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, kGroupTileY,
+            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, jc::kTileX, kGroupTileY,
                                                   true, false, true, k.src, nullptr, g->stream);
             if (e != hipSuccess)
                 return ghip(e, "group sweep");
@@ -127,7 +127,7 @@ int group_sweep(jc_group* g)
             if (c0->ir_phase == 1)
                 e = jc::launch_ir_first(g->d_desc() + k.bstart, k.bend - k.bstart, k.lo, g->stream);
             else
-                e = jc::launch_ir_inner(g->d_desc(), g->d_items() + k.item0, n, c0->ir_q, kGroupTileY, k.lo,
+                e = jc::launch_ir_inner(g->d_desc(), g->d_items() + k.item0, n, c0->ir_q, jc::kTileX, kGroupTileY, k.lo,
                                         g->stream);
             if (e != hipSuccess)
                 return ghip(e, "group inner sweep");
@@ -412,7 +412,7 @@ int jc_group_residuals(jc_group* g, double* host_l2)
     for (const Class& k : g->classes) {
         const int n = (int)k.items.size();
         if (!k.ir) {
-            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, kGroupTileY,
+            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, jc::kTileX, kGroupTileY,
                                                   true, true, false, k.src, g->d_partials() + k.item0, g->stream);
             if (e != hipSuccess)
                 return ghip(e, "group residual");
@@ -436,7 +436,7 @@ int jc_group_residuals(jc_group* g, double* host_l2)
             }
         }
         // refining members keep their iterate in copy 0 (their items' flip is 0)
-        const hipError_t e = jc::launch_ir_residual(g->d_desc(), g->d_items() + k.item0, n, 0, kGroupTileY,
+        const hipError_t e = jc::launch_ir_residual(g->d_desc(), g->d_items() + k.item0, n, 0, jc::kTileX, kGroupTileY,
                                                     k.src, k.lo, g->d_partials() + k.item0, g->stream);
         if (e != hipSuccess)
             return ghip(e, "group refinement residual");

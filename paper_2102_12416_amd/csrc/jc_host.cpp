@@ -41,31 +41,48 @@ namespace {
 
 // ------------------------------------------------------------------ geometry
 
-int64_t items_for(const jc_ctx* c, int ty, int zc)
+int64_t items_for(const jc_ctx* c, int tx, int ty, int zc)
 {
     int64_t total = 0;
     for (const HostBlock& b : c->blocks) {
-        const int64_t tx = (b.n[0] + jc::kTileX - 1) / jc::kTileX;
+        const int64_t nxt = (b.n[0] + tx - 1) / tx;
         const int64_t tyn = (b.n[1] + ty - 1) / ty;
         const int64_t tz = (b.n[2] + zc - 1) / zc;
-        total += tx * tyn * tz;
+        total += nxt * tyn * tz;
     }
     return total;
 }
 
-// Default tile: 8 rows; z chunks halved from the full depth until the
-// launch has at least 4096 tiles (16 per compute unit) or chunks reach 16.
-void default_tiles(const jc_ctx* c, int* ty, int* zc)
+// Lanes a tile width leaves idle: x tiles past the end of each block row.
+int64_t idle_cells(const jc_ctx* c, int tx)
 {
-    int64_t maxz = 1;
+    int64_t idle = 0;
     for (const HostBlock& b : c->blocks)
+        idle += ((b.n[0] + tx - 1) / tx * tx - b.n[0]) * b.n[1] * b.n[2];
+    return idle;
+}
+
+// Default tile: 64 cells wide unless 32 leaves fewer idle lanes by more
+// than 1/16 of the cells; 8 rows; z chunks halved from the full depth
+// until the launch has at least 4096 tiles (16 per compute unit) or
+// chunks reach 16.
+void default_tiles(const jc_ctx* c, int* tx, int* ty, int* zc)
+{
+    int64_t maxz = 1, cells = 0;
+    for (const HostBlock& b : c->blocks) {
         maxz = std::max(maxz, b.n[2]);
+        cells += b.n[0] * b.n[1] * b.n[2];
+    }
+    int x = c->opt.tile_x > 0 ? c->opt.tile_x : 64;
+    if (c->opt.tile_x <= 0 && (idle_cells(c, 64) - idle_cells(c, 32)) * 16 > cells)
+        x = 32;
     int t = c->opt.tile_y > 0 ? c->opt.tile_y : 8;
     int z = c->opt.z_chunk > 0 ? c->opt.z_chunk : (int)std::min<int64_t>(maxz, 1 << 20);
     if (c->opt.z_chunk <= 0) {
-        while (z > kMinZChunk && items_for(c, t, z) < 4096)
+        while (z > kMinZChunk && items_for(c, x, t, z) < 4096)
             z = (z + 1) / 2;
     }
+    *tx = x;
     *ty = t;
     *zc = z;
 }
@@ -77,7 +94,7 @@ void build_items(jc_ctx* c)
         const HostBlock& b = c->blocks[bi];
         for (int64_t z0 = 0; z0 < b.n[2]; z0 += c->z_chunk)
             for (int64_t y0 = 0; y0 < b.n[1]; y0 += c->tile_y)
-                for (int64_t x0 = 0; x0 < b.n[0]; x0 += jc::kTileX) {
+                for (int64_t x0 = 0; x0 < b.n[0]; x0 += c->tile_x) {
                     Item it{};
                     it.block = bi;
                     it.x0 = (int32_t)x0;
@@ -97,6 +114,10 @@ int validate_options(const jc_options* opt)
         return JC_OK;
     if (opt->mode != JC_MODE_STAGED && opt->mode != JC_MODE_FUSED)
         return fail(JC_ERR_INVALID, "options.mode must be JC_MODE_STAGED or JC_MODE_FUSED");
+    if (opt->debug_epochs != 0)
+        return fail(JC_ERR_INVALID, "options.debug_epochs is reserved and must be 0");
+    if (opt->tile_x != 0 && opt->tile_x != 32 && opt->tile_x != 64)
+        return fail(JC_ERR_INVALID, "options.tile_x must be 0, 32 or 64");
     if (opt->tile_y != 0) {
         bool ok = false;
         for (int t : kTileYCandidates)
@@ -198,10 +219,10 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         return fail(JC_ERR_INVALID, "too many face pairs for one launch");
     if (c->nb() > 65535)
         return fail(JC_ERR_INVALID, "too many blocks for one launch");
-    default_tiles(c, &c->tile_y, &c->z_chunk);
+    default_tiles(c, &c->tile_x, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
-    c->max_items = std::max<int64_t>((int64_t)c->items.size(), items_for(c, 4, kMinZChunk));
+    c->max_items = std::max<int64_t>((int64_t)c->items.size(), items_for(c, 32, 4, kMinZChunk));
     if (c->max_items > (int64_t)1 << 30)
         return fail(JC_ERR_INVALID, "work list too long");
     // arena layout
@@ -368,7 +389,7 @@ int do_unpack(jc_ctx* c)
 int do_sweep(jc_ctx* c, bool fused, bool resid)
 {
     int st = timed(c, fused ? JC_K_FUSED : JC_K_SWEEP, [&] {
-        return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_y,
+        return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_x, c->tile_y,
                                 fused, resid, true, c->opt.with_source != 0, c->d_partials(), c->stream);
     });
     if (st != JC_OK)
@@ -450,7 +471,7 @@ int residual_now(jc_ctx* c, double* l2)
             return st;
     }
     int st = timed(c, JC_K_RESIDUAL, [&] {
-        return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_y, fused,
+        return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_x, c->tile_y, fused,
                                 true, false, c->opt.with_source != 0, c->d_partials(), c->stream);
     });
     if (st != JC_OK)
@@ -978,7 +999,7 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
     while (true) {
         st = timed(c, JC_K_IR_OUTER, [&] {
             return jc::launch_ir_residual(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity,
-                                          c->tile_y, src, lo, c->d_partials(), c->stream);
+                                          c->tile_x, c->tile_y, src, lo, c->d_partials(), c->stream);
         });
         if (st != JC_OK)
             return st;
@@ -1010,7 +1031,8 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
         int q = 1;
         for (int64_t j = 1; j < m; ++j) {
             st = timed(c, JC_K_IR_INNER, [&] {
-                return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), q, c->tile_y, lo,
+                return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), q, c->tile_x, c->tile_y,
+                                           lo,
                                            c->stream);
             });
             if (st != JC_OK)
@@ -1036,17 +1058,19 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
     return status;
 }
 
-int jc_set_tiles(jc_ctx* c, int tile_y, int z_chunk)
+int jc_set_tiles(jc_ctx* c, int tile_x, int tile_y, int z_chunk)
 {
     if (!c)
         return fail(JC_ERR_INVALID, "NULL context");
-    bool ok = false;
+    bool ok = tile_x == 32 || tile_x == 64;
+    bool oky = false;
     for (int t : kTileYCandidates)
-        ok = ok || t == tile_y;
-    if (!ok || z_chunk < 1)
-        return fail(JC_ERR_INVALID, "tile_y must be 4, 8, 16 or 32 and z_chunk >= 1");
-    if (items_for(c, tile_y, z_chunk) > c->max_items)
+        oky = oky || t == tile_y;
+    if (!ok || !oky || z_chunk < 1)
+        return fail(JC_ERR_INVALID, "tile_x must be 32 or 64, tile_y 4, 8, 16 or 32 and z_chunk >= 1");
+    if (items_for(c, tile_x, tile_y, z_chunk) > c->max_items)
         return fail(JC_ERR_INVALID, "z_chunk too small for the work-list region");
+    c->tile_x = tile_x;
     c->tile_y = tile_y;
     c->z_chunk = z_chunk;
     build_items(c);
@@ -1061,7 +1085,7 @@ int jc_set_tiles(jc_ctx* c, int tile_y, int z_chunk)
     return JC_OK;
 }
 
-int jc_autotune(jc_ctx* c, int reps, int64_t out[3])
+int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
 {
     int st = check_ready(c);
     if (st != JC_OK)
@@ -1088,12 +1112,13 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[3])
     const bool was_timing = c->timing;
     c->timing = false;
     double best = -1;
-    int bt = c->tile_y, bz = c->z_chunk;
+    int bx = c->tile_x, bt = c->tile_y, bz = c->z_chunk;
+    for (int xw : {64, 32})
     for (int t : kTileYCandidates) {
         for (int z : zcs) {
-            if (items_for(c, t, z) > c->max_items)
+            if (items_for(c, xw, t, z) > c->max_items)
                 continue;
-            st = jc_set_tiles(c, t, z);
+            st = jc_set_tiles(c, xw, t, z);
             // trial sweeps read copy `parity` and write the other copy (and
             // face slot parity ^ 1) without swapping: the iterate is unchanged
             for (int rep = -1; rep < reps && st == JC_OK; ++rep) {
@@ -1101,7 +1126,7 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[3])
                     st = hipEventRecord(e0, c->stream) == hipSuccess ? JC_OK : JC_ERR_DEVICE;
                 if (st == JC_OK) {
                     const hipError_t e = jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(),
-                                                          c->parity, c->tile_y, fused, false, true,
+                                                          c->parity, c->tile_x, c->tile_y, fused, false, true,
                                                           c->opt.with_source != 0, nullptr, c->stream);
                     if (e != hipSuccess)
                         st = fail(JC_ERR_DEVICE, std::string("autotune launch: ") + hipGetErrorString(e));
@@ -1112,6 +1137,7 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[3])
                 hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
                 if (best < 0 || ms < best) {
                     best = ms;
+                    bx = xw;
                     bt = t;
                     bz = z;
                 }
@@ -1129,12 +1155,13 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[3])
     c->timing = was_timing;
     if (st != JC_OK)
         return st;
-    st = jc_set_tiles(c, bt, bz);
+    st = jc_set_tiles(c, bx, bt, bz);
     if (st != JC_OK)
         return st;
-    out[0] = bt;
-    out[1] = bz;
-    out[2] = (int64_t)(best * 1000.0 / reps);     // microseconds per sweep
+    out[0] = bx;
+    out[1] = bt;
+    out[2] = bz;
+    out[3] = (int64_t)(best * 1000.0 / reps);     // microseconds per sweep
     return JC_OK;
 }
 
@@ -1178,7 +1205,7 @@ int jc_tile_info(const jc_ctx* c, int64_t out[4])
 {
     if (!c || !out)
         return fail(JC_ERR_INVALID, "bad context or output");
-    out[0] = jc::kTileX;
+    out[0] = c->tile_x;
     out[1] = c->tile_y;
     out[2] = c->z_chunk;
     out[3] = (int64_t)c->items.size();

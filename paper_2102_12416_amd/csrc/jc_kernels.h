@@ -7,7 +7,7 @@
 
 namespace jc {
 
-// Tiles are 64 x cells wide (32 threads, two cells each, per row).
+// Tiles are 64 or 32 x cells wide (two cells per thread); groups use 64.
 constexpr int kTileX = 64;
 
 // Sweep / residual over a work list.  parity selects the input copy of
@@ -16,7 +16,7 @@ constexpr int kTileX = 64;
 // slot.  resid: write one partial sum of r^2 per item into partials.
 // store: write the new iterate (false = residual only).
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
-                        int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
+                        int tile_x, int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
                         hipStream_t s);
 
 // Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
@@ -25,10 +25,10 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 // Inner: one sweep of d (copy qparity -> qparity ^ 1) with source r_lo.
 // First: d_1 = lo(r_lo / 6) into copy 1.  Update: u[p] += d[q] and the
 // updated faces into slot p.
-hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
-                              bool src, int lo_dtype, double* partials, hipStream_t s);
-hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
-                           int lo_dtype, hipStream_t s);
+hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_x,
+                              int tile_y, bool src, int lo_dtype, double* partials, hipStream_t s);
+hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_x,
+                           int tile_y, int lo_dtype, hipStream_t s);
 hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int lo_dtype, hipStream_t s);
 hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int p, int q, int lo_dtype, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -201,8 +201,8 @@ __device__ __forceinline__ float div6(float s)
     return v;
 }
 
-// One work-group sweeps a tile of 64 x cells by TY rows of one block,
-// marching along z.  Each thread owns two adjacent x cells of one row
+// One work-group sweeps a tile of 2 TXP x cells (64 or 32) by TY rows of
+// one block, marching along z.  Each thread owns two adjacent x cells of one row
 // (one aligned-pair load per plane: cell x = 1 of every row starts a
 // 128-byte line).  Per plane the work-group writes the plane -- its cells
 // plus a one-cell halo ring -- into an LDS tile, synchronises once (the
@@ -214,9 +214,9 @@ __device__ __forceinline__ float div6(float s)
 // clamped addresses where it has nothing to fetch, so that the loads of
 // the next two planes stay in flight while the current one is computed
 // (no divergent branch around a load).  The halo ring is fetched by
-// threads with a halo role: threads 0-31 the row above the tile, 32-63
-// the row below, the next TY threads the column left of it and the next
-// TY the column right of it; the rest re-load their own cells.
+// threads with a halo role: the first TXP threads the row above the tile,
+// the next TXP the row below, the next TY the column left of it and the
+// next TY the column right of it; the rest re-load their own cells.
 //
 // T / FIELD: the swept field and its storage (binary64 iterate u, or the
 // correction d of the refinement stored as binary64, binary32 or
@@ -229,17 +229,19 @@ __device__ __forceinline__ float div6(float s)
 // work-group.  STORE: write the new iterate.  SRC: add the source (b for
 // u, r_lo for d).  R: also store r rounded to R into the block's r_lo
 // array (the outer pass of the refinement).
-template <typename T, int FIELD, int TY, bool FUSED, bool RES, bool STORE, bool SRC, typename R>
-__global__ void __launch_bounds__(32 * TY)
+template <typename T, int FIELD, int TXP, int TY, bool FUSED, bool RES, bool STORE, bool SRC, typename R>
+__global__ void __launch_bounds__(TXP * TY)
 k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int nitems,
         int parity, double* __restrict__ partials)
 {
-    static_assert(TY >= 4 && 32 * TY >= 64 + 2 * TY, "halo roles need 64 + 2 TY threads");
+    static_assert(TY >= 4 && TXP * TY >= 2 * TXP + 2 * TY && (TXP * TY) % 64 == 0,
+                  "halo roles need 2 TXP + 2 TY threads; whole waves");
     using C = typename Tr<T>::C;
     using F = Fld<T, FIELD>;
     constexpr bool RLO = !std::is_same<R, NoRlo>::value;
-    constexpr int NT = 32 * TY;
-    constexpr int LW = 68;   // LDS row: col 1 = x0, cols 2..65 = x0+1..x0+64, up to col 66
+    constexpr int NT = TXP * TY;
+    constexpr int W = 2 * TXP;                    // tile width in cells
+    constexpr int LW = W + 4;  // LDS row: col 1 = x0, cols 2..W+1 = x0+1..x0+W, up to col W+2
     __shared__ C S[2][TY + 2][LW];
     __shared__ double wsum[NT / 64];
 
@@ -251,10 +253,10 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
     const int p = parity ^ it.flip;
     const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
     const int t = threadIdx.x;
-    const int lx = t & 31;
-    const int ly = t >> 5;
+    const int lx = t % TXP;
+    const int ly = t / TXP;
     const int x0 = it.x0, y0 = it.y0;
-    const int x_end = min(x0 + 64, nx);           // last x cell of the tile
+    const int x_end = min(x0 + W, nx);            // last x cell of the tile
     const int y_end = min(y0 + TY, ny);           // last row of the tile
     const int ly_last = y_end - y0 - 1;
     const int xa = x0 + 2 * lx + 1;               // this thread's cells: xa, xa + 1
@@ -293,13 +295,13 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
     const T* sown = SRC ? F::source(B) + (int64_t)y_c * pitch + xa_c : nullptr;
 
     // halo role: the pair at hbase + zz * hstride
-    const int role = t < 32 ? 0 : t < 64 ? 1 : t < 64 + TY ? 2 : t < 64 + 2 * TY ? 3 : 4;
+    const int role = t < TXP ? 0 : t < 2 * TXP ? 1 : t < 2 * TXP + TY ? 2 : t < 2 * TXP + 2 * TY ? 3 : 4;
     const T* hbase = own;
     int64_t hstride = plane;
     int hrow = 0, hcol = 0, hcomp = 0;
     bool hv0 = false, hv1 = false;
     if (role <= 1) {
-        const int hl = t & 31;
+        const int hl = t % TXP;
         const int hx = x0 + 2 * hl + 1;
         const int hx_c = min(hx, xlast);
         const int hy = role == 0 ? y0 : y_end + 1;
@@ -316,7 +318,7 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hrow = role == 0 ? 0 : ly_last + 2;
         hcol = 2 * hl + 2;
     } else if (role <= 3) {
-        const int r = t - 64 - (role == 3 ? TY : 0);
+        const int r = t - 2 * TXP - (role == 3 ? TY : 0);
         const int hy = y0 + r + 1;
         hv0 = hy <= y_end;
         const int hy_c = min(hy, ny);
@@ -466,17 +468,17 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
     }
 }
 
-template <typename T, int FIELD, int TY, bool SRC, typename R>
+template <typename T, int FIELD, int TXP, int TY, bool SRC, typename R>
 hipError_t sweep_flags(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
                        bool resid, bool store, double* partials, hipStream_t s)
 {
     const int grid = ((nitems + 7) / 8) * 8;
-    const dim3 bs(32 * TY);
-#define JC_SWEEP_CASE(FU, RE, ST)                                                                    \
-    if (fused == FU && resid == RE && store == ST) {                                                \
-        hipLaunchKernelGGL((k_sweep<T, FIELD, TY, FU, RE, ST, SRC, R>), dim3(grid), bs, 0, s, blocks, \
-                           items, nitems, parity, partials);                                        \
-        return hipGetLastError();                                                                   \
+    const dim3 bs(TXP * TY);
+#define JC_SWEEP_CASE(FU, RE, ST)                                                                         \
+    if (fused == FU && resid == RE && store == ST) {                                                     \
+        hipLaunchKernelGGL((k_sweep<T, FIELD, TXP, TY, FU, RE, ST, SRC, R>), dim3(grid), bs, 0, s, blocks, \
+                           items, nitems, parity, partials);                                             \
+        return hipGetLastError();                                                                        \
     }
     if constexpr (std::is_same<R, NoRlo>::value) {
         if constexpr (FIELD == FIELD_U) {
@@ -494,15 +496,26 @@ hipError_t sweep_flags(const BlockDesc* blocks, const Item* items, int nitems, i
     return hipErrorInvalidValue;
 }
 
-template <typename T, int FIELD, bool SRC, typename R>
-hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
-                       bool fused, bool resid, bool store, double* partials, hipStream_t s)
+template <typename T, int FIELD, int TXP, bool SRC, typename R>
+hipError_t sweep_rows(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
+                      bool fused, bool resid, bool store, double* partials, hipStream_t s)
 {
     switch (tile_y) {
-    case 4: return sweep_flags<T, FIELD, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 8: return sweep_flags<T, FIELD, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 16: return sweep_flags<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 32: return sweep_flags<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 4: return sweep_flags<T, FIELD, TXP, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 8: return sweep_flags<T, FIELD, TXP, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 16: return sweep_flags<T, FIELD, TXP, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 32: return sweep_flags<T, FIELD, TXP, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int FIELD, bool SRC, typename R>
+hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_x, int tile_y,
+                       bool fused, bool resid, bool store, double* partials, hipStream_t s)
+{
+    switch (tile_x) {
+    case 32: return sweep_rows<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
+    case 64: return sweep_rows<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -747,27 +760,27 @@ k_gather(const BlockDesc* __restrict__ blocks, double* __restrict__ g, int64_t g
 }  // namespace
 
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
-                        int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
+                        int tile_x, int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
                         hipStream_t s)
 {
     if (nitems <= 0)
         return hipSuccess;
-    return src ? sweep_tiles<double, FIELD_U, true, NoRlo>(blocks, items, nitems, parity, tile_y, fused, resid,
-                                                             store, partials, s)
-               : sweep_tiles<double, FIELD_U, false, NoRlo>(blocks, items, nitems, parity, tile_y, fused, resid,
-                                                              store, partials, s);
+    return src ? sweep_tiles<double, FIELD_U, true, NoRlo>(blocks, items, nitems, parity, tile_x, tile_y, fused,
+                                                             resid, store, partials, s)
+               : sweep_tiles<double, FIELD_U, false, NoRlo>(blocks, items, nitems, parity, tile_x, tile_y, fused,
+                                                              resid, store, partials, s);
 }
 
-hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
-                              bool src, int lo_dtype, double* partials, hipStream_t s)
+hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_x,
+                              int tile_y, bool src, int lo_dtype, double* partials, hipStream_t s)
 {
     if (nitems <= 0)
         return hipSuccess;
 #define JC_IR_RES(RT)                                                                                  \
-    return src ? sweep_tiles<double, FIELD_U, true, RT>(blocks, items, nitems, parity, tile_y, true, true,  \
-                                                        false, partials, s)                                 \
-               : sweep_tiles<double, FIELD_U, false, RT>(blocks, items, nitems, parity, tile_y, true, true, \
-                                                         false, partials, s);
+    return src ? sweep_tiles<double, FIELD_U, true, RT>(blocks, items, nitems, parity, tile_x, tile_y, true,   \
+                                                        true, false, partials, s)                           \
+               : sweep_tiles<double, FIELD_U, false, RT>(blocks, items, nitems, parity, tile_x, tile_y, true,  \
+                                                         true, false, partials, s);
     switch (lo_dtype) {
     case 0: JC_IR_RES(double)
     case 1: JC_IR_RES(float)
@@ -777,18 +790,18 @@ hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int ni
 #undef JC_IR_RES
 }
 
-hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
-                           int lo_dtype, hipStream_t s)
+hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_x,
+                           int tile_y, int lo_dtype, hipStream_t s)
 {
     if (nitems <= 0)
         return hipSuccess;
     switch (lo_dtype) {
-    case 0: return sweep_tiles<double, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_y, true, false,
-                                                             true, nullptr, s);
-    case 1: return sweep_tiles<float, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_y, true, false,
-                                                            true, nullptr, s);
-    case 2: return sweep_tiles<bf16, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_y, true, false,
-                                                           true, nullptr, s);
+    case 0: return sweep_tiles<double, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_x, tile_y, true,
+                                                             false, true, nullptr, s);
+    case 1: return sweep_tiles<float, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_x, tile_y, true,
+                                                            false, true, nullptr, s);
+    case 2: return sweep_tiles<bf16, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_x, tile_y, true,
+                                                           false, true, nullptr, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -29,7 +29,8 @@ class Solver:
     kernels) or 'fused' (one launch per iteration)."""
 
     def __init__(self, grid, block_dims=None, cuts=None, mode="staged", with_source=False,
-                 tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None):
+                 tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None,
+                 tile_x=0):
         self.grid = tuple(int(v) for v in grid)
         self.device = torch.device(device)
         self.opt = L.Options()
@@ -39,6 +40,7 @@ class Solver:
         if ir_dtype is not None:
             self.opt.ir_enable = 1
             self.opt.ir_dtype = {"f64": L.JC_F64, "f32": L.JC_F32, "bf16": L.JC_BF16}[ir_dtype]
+        self.opt.tile_x = int(tile_x)
         self.opt.tile_y = int(tile_y)
         self.opt.z_chunk = int(z_chunk)
         self.opt.use_graphs = int(bool(use_graphs))
@@ -231,13 +233,13 @@ class Solver:
         flat = self.arena_view(info["u_off"][c], info["plane"] * (nz + 2))
         return flat.view(nz + 2, ny + 2, info["pitch"])
 
-    def set_tiles(self, tile_y, z_chunk):
-        check(L.lib.jc_set_tiles(self._ctx, int(tile_y), int(z_chunk)))
+    def set_tiles(self, tile_x, tile_y, z_chunk):
+        check(L.lib.jc_set_tiles(self._ctx, int(tile_x), int(tile_y), int(z_chunk)))
 
     def autotune(self, reps=5):
         """Pick the fastest tile shape for this context; returns
-        (tile_y, z_chunk, microseconds per sweep)."""
-        out = (ctypes.c_int64 * 3)()
+        (tile_x, tile_y, z_chunk, microseconds per sweep)."""
+        out = (ctypes.c_int64 * 4)()
         check(L.lib.jc_autotune(self._ctx, int(reps), out))
         return tuple(out)
 

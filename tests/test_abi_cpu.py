@@ -264,11 +264,26 @@ def test_solve_ir_needs_refinement_buffers():
 def test_set_tiles_validation_and_items():
     st, ctx = create((200, 100, 96), (100, 100, 96))
     assert st == 0
-    assert L.lib.jc_set_tiles(ctx, 5, 32) == L.JC_ERR_INVALID
-    assert L.lib.jc_set_tiles(ctx, 8, 0) == L.JC_ERR_INVALID
-    check(L.lib.jc_set_tiles(ctx, 16, 48))
+    assert L.lib.jc_set_tiles(ctx, 64, 5, 32) == L.JC_ERR_INVALID
+    assert L.lib.jc_set_tiles(ctx, 64, 8, 0) == L.JC_ERR_INVALID
+    assert L.lib.jc_set_tiles(ctx, 48, 8, 16) == L.JC_ERR_INVALID
+    check(L.lib.jc_set_tiles(ctx, 64, 16, 48))
     out = (ctypes.c_int64 * 4)()
     check(L.lib.jc_tile_info(ctx, out))
     # 2 blocks x ceil(100/64) x ceil(100/16) x ceil(96/48)
     assert tuple(out) == (64, 16, 48, 2 * 2 * 7 * 2)
+    check(L.lib.jc_set_tiles(ctx, 32, 4, 96))
+    check(L.lib.jc_tile_info(ctx, out))
+    assert tuple(out) == (32, 4, 96, 2 * 4 * 25 * 1)
     L.lib.jc_destroy(ctx)
+
+
+def test_default_tile_width_prefers_fewer_idle_lanes():
+    out = (ctypes.c_int64 * 4)()
+    for grid, bd, want in (((768, 768, 768), (96, 96, 96), 32), ((512, 512, 512), (256, 256, 256), 64),
+                           ((100, 64, 64), (100, 64, 64), 64)):
+        st, ctx = create(grid, bd)
+        assert st == 0
+        check(L.lib.jc_tile_info(ctx, out))
+        assert out[0] == want, (grid, bd, out[0])
+        L.lib.jc_destroy(ctx)

@@ -162,12 +162,14 @@ def test_staged_state_machine():
         assert s.iterations == 2
 
 
-@pytest.mark.parametrize("tile_y,z_chunk", [(4, 16), (8, 0), (16, 7), (32, 0), (4, 33)])
-def test_tile_shapes_bitwise(tile_y, z_chunk):
-    say("tile", tile_y, z_chunk)
+@pytest.mark.parametrize("tile_x,tile_y,z_chunk", [(64, 4, 16), (64, 8, 0), (64, 16, 7), (64, 32, 0), (64, 4, 33),
+                                                   (32, 4, 16), (32, 8, 5), (32, 16, 0), (32, 32, 33)])
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_tile_shapes_bitwise(tile_x, tile_y, z_chunk, mode):
+    say("tile", tile_x, tile_y, z_chunk, mode)
     n = (100, 70, 66)
-    ref = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=8, z_chunk=0, mode="fused")
-    got = run_gpu(n, 9, block_dims=(50, 35, 66), tile_y=tile_y, z_chunk=z_chunk, mode="fused")
+    ref = run_gpu(n, 9, block_dims=(50, 35, 66), tile_x=64, tile_y=8, z_chunk=0, mode="staged")
+    got = run_gpu(n, 9, block_dims=(50, 35, 66), tile_x=tile_x, tile_y=tile_y, z_chunk=z_chunk, mode=mode)
     assert np.array_equal(got, ref)
 
 
@@ -323,8 +325,8 @@ def test_autotune_keeps_iterate_and_results(mode):
         s.load(u0)
         s.iterate(5)
         before = s.store().cpu().numpy()
-        ty, zc, us = s.autotune(reps=2)
-        assert ty in (4, 8, 16, 32) and zc >= 16 and us > 0
+        tx, ty, zc, us = s.autotune(reps=2)
+        assert tx in (32, 64) and ty in (4, 8, 16, 32) and zc >= 16 and us > 0
         assert s.iterations == 5
         assert np.array_equal(s.store().cpu().numpy(), before)
         s.iterate(6)
