@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune even where a tuned shape is recorded for the workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ab", action="store_true", help="skip the device / host-staged exchange comparison")
+    ap.add_argument("--ab-iters", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
@@ -111,6 +113,41 @@ def recorded_traffic(workload, mode, tile):
     if rec.get("kernels_source_sha256") != sha or rec.get("mode") != mode or list(rec.get("tile", [])) != list(tile):
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def exchange_ab(grid, bd, seed, iters, tiles):
+    """The paper's comparison on one GPU: the same staged iteration with the
+    faces moved by the pre-posted device pairing, by host staging, and by a
+    device copy announced through a host metadata round trip.  Returns ms
+    per iteration and the communication part (pack + exchange + unpack)."""
+    import torch
+
+    import synth
+    from paper_2102_12416_amd import Solver, _lib as L
+    u0 = synth.boundary_field(grid, seed=seed)
+    out = {}
+    for mode in ("device", "host", "metadata"):
+        with Solver(grid, block_dims=bd, mode="staged", use_graphs=False, exchange=mode) as s:
+            s.set_tiles(*tiles)
+            s.load(u0)
+            s.iterate(5)
+            s.synchronize()
+            s.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.iterate(iters)
+            s.synchronize()
+            wall = time.perf_counter() - t0
+            comm = sum(s.kernel_time(k)[0] for k in (L.JC_K_PACK, L.JC_K_EXCHANGE, L.JC_K_UNPACK))
+            sweep = s.kernel_time(L.JC_K_SWEEP)[0]
+            s.set_timing(False)
+        out[mode] = dict(ms_per_iter=round(wall * 1e3 / iters, 4), comm_ms_per_iter=round(comm / iters, 4),
+                         sweep_ms_per_iter=round(sweep / iters, 4))
+    d = out["device"]
+    for mode in ("host", "metadata"):
+        out[mode]["comm_speedup_of_device"] = round(out[mode]["comm_ms_per_iter"] / d["comm_ms_per_iter"], 2)
+        out[mode]["iter_speedup_of_device"] = round(out[mode]["ms_per_iter"] / d["ms_per_iter"], 2)
+    return out
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -371,6 +408,10 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if mode == "staged" and not args.no_ab and bd is not None:
+        print("[bench] exchange A/B: device pairing vs host staging vs host metadata", file=sys.stderr, flush=True)
+        out["exchange_ab"] = exchange_ab(grid, bd, args.seed, args.ab_iters,
+                                         (tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]))
     if not args.no_cpu:
         print("[bench] CPU oracle baseline (%.0f s budget)" % args.cpu_seconds, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid, args.seed, args.cpu_seconds)

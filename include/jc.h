@@ -64,6 +64,17 @@ enum {
     JC_MODE_FUSED = 1        /* per iteration: one launch; ghosts read from the
                                 neighbours' face buffers, faces written in the epilogue */
 };
+/* How jc_exchange moves the faces (staged mode).  DEVICE: the pre-posted
+ * pairing, one device copy of every pair, no host work (the Channel
+ * analogue).  HOST: host staging, the paper's non-GPU-aware baseline:
+ * every send buffer to pinned host memory, a wait for the stream, a host
+ * copy into the receiver's host buffer, then back to the device.
+ * METADATA: the device copy, but only after a host round trip per
+ * iteration -- the host waits for the pack and builds and checks one
+ * metadata message (source, destination, size, tag) per pair, as the GPU
+ * Messaging API's receiver needs a host message before it can post its
+ * receive.  HOST and METADATA disable graph capture. */
+enum { JC_EXCHANGE_DEVICE = 0, JC_EXCHANGE_HOST = 1, JC_EXCHANGE_METADATA = 2 };
 /* kinds for jc_kernel_time */
 enum { JC_K_SWEEP = 0, JC_K_PACK = 1, JC_K_EXCHANGE = 2, JC_K_UNPACK = 3,
        JC_K_RESIDUAL = 4, JC_K_FUSED = 5, JC_K_IR_INNER = 6, JC_K_IR_OUTER = 7,
@@ -84,6 +95,7 @@ typedef struct jc_options {
     int use_graphs;      /* 1: capture jc_iterate windows as HIP graphs */
     int debug_epochs;    /* reserved, must be 0 */
     int tile_x;          /* cells per tile row: 32 or 64; 0 = auto (fewest idle lanes) */
+    int exchange;        /* JC_EXCHANGE_DEVICE (default), _HOST or _METADATA */
 } jc_options;
 
 /* Result of a solve. */

@@ -24,6 +24,7 @@ JC_ERR_NONFINITE = -5
 JC_F64, JC_F32, JC_BF16, JC_NONE = 0, 1, 2, -1
 JC_FIELD_U, JC_FIELD_B = 0, 1
 JC_MODE_STAGED, JC_MODE_FUSED = 0, 1
+JC_EXCHANGE_DEVICE, JC_EXCHANGE_HOST, JC_EXCHANGE_METADATA = 0, 1, 2
 (JC_K_SWEEP, JC_K_PACK, JC_K_EXCHANGE, JC_K_UNPACK, JC_K_RESIDUAL, JC_K_FUSED,
  JC_K_IR_INNER, JC_K_IR_OUTER) = range(8)
 
@@ -41,7 +42,8 @@ class JcError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("with_source", ctypes.c_int), ("ir_dtype", ctypes.c_int),
                 ("ir_enable", ctypes.c_int), ("tile_y", ctypes.c_int), ("z_chunk", ctypes.c_int),
-                ("use_graphs", ctypes.c_int), ("debug_epochs", ctypes.c_int), ("tile_x", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("debug_epochs", ctypes.c_int), ("tile_x", ctypes.c_int),
+                ("exchange", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <map>
 #include <string>
 #include <utility>
@@ -96,6 +97,13 @@ struct jc_ctx {
     std::vector<PairDesc> hpairs;
     int32_t hranges[2] = {0, 0};
     double* h_result = nullptr;     // pinned
+    // host-staged exchange: pinned send and receive halves, per-pair offsets
+    char* h_stage = nullptr;
+    size_t h_stage_bytes = 0;
+    std::vector<size_t> h_stage_off;
+    // metadata messages of the announced exchange
+    struct MetaMsg { int src, dst; size_t bytes; uint64_t tag; };
+    std::vector<MetaMsg> meta;
     // state
     bool loaded_u = false, loaded_b = false;
     int parity = 0;

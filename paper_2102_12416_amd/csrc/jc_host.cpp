@@ -114,6 +114,11 @@ int validate_options(const jc_options* opt)
         return JC_OK;
     if (opt->mode != JC_MODE_STAGED && opt->mode != JC_MODE_FUSED)
         return fail(JC_ERR_INVALID, "options.mode must be JC_MODE_STAGED or JC_MODE_FUSED");
+    if (opt->exchange != JC_EXCHANGE_DEVICE && opt->exchange != JC_EXCHANGE_HOST &&
+        opt->exchange != JC_EXCHANGE_METADATA)
+        return fail(JC_ERR_INVALID, "options.exchange must be JC_EXCHANGE_DEVICE, _HOST or _METADATA");
+    if (opt->exchange != JC_EXCHANGE_DEVICE && opt->mode == JC_MODE_FUSED)
+        return fail(JC_ERR_INVALID, "host-staged or metadata exchange needs the staged mode");
     if (opt->debug_epochs != 0)
         return fail(JC_ERR_INVALID, "options.debug_epochs is reserved and must be 0");
     if (opt->tile_x != 0 && opt->tile_x != 32 && opt->tile_x != 64)
@@ -371,9 +376,71 @@ int do_pack(jc_ctx* c, int slot)
 
 namespace {
 
+// Host staging (the paper's non-GPU-aware path, its "-H" runs): every
+// send buffer is copied to pinned host memory, the stream is waited for,
+// the host moves the message into the receiver's host buffer, and the
+// receive buffer is filled from there.
+hipError_t exchange_via_host(jc_ctx* c)
+{
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& p = c->pairs[q];
+        const hipError_t e = hipMemcpyAsync(c->h_stage + c->h_stage_off[q], c->arena + p.buf_off[0],
+                                            sizeof(double) * p.span, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess)
+        return e;
+    const size_t half = c->h_stage_bytes / 2;
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& p = c->pairs[q];
+        std::memcpy(c->h_stage + half + c->h_stage_off[q], c->h_stage + c->h_stage_off[q], sizeof(double) * p.span);
+    }
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& p = c->pairs[q];
+        e = hipMemcpyAsync(c->arena + p.buf_off[1], c->h_stage + half + c->h_stage_off[q], sizeof(double) * p.span,
+                           hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+// Device transfer announced by host metadata (the GPU Messaging API of
+// section 3.2.1): the receiver learns buffer, size and tag from a host
+// message sent after the pack, so the host waits for the pack, builds the
+// message of every pair, checks it, and only then enqueues the transfer.
+hipError_t exchange_with_metadata(jc_ctx* c)
+{
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess)
+        return e;
+    c->meta.resize(c->np());
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& p = c->pairs[q];
+        jc_ctx::MetaMsg& m = c->meta[q];
+        m.src = p.src_block;
+        m.dst = p.dst_block;
+        m.bytes = sizeof(double) * p.span;
+        m.tag = ((uint64_t)q << 32) | (uint64_t)(c->iters & 0xffffffffu);
+    }
+    for (int q = 0; q < c->np(); ++q) {
+        const HostPair& p = c->pairs[q];
+        const jc_ctx::MetaMsg& m = c->meta[q];
+        if (m.dst != p.dst_block || m.bytes != sizeof(double) * p.span || (m.tag >> 32) != (uint64_t)q)
+            return hipErrorInvalidValue;
+    }
+    return jc::launch_exchange(c->d_pairs(), c->np(), c->max_count, c->stream);
+}
+
 int do_exchange(jc_ctx* c)
 {
     return timed(c, JC_K_EXCHANGE, [&] {
+        if (c->opt.exchange == JC_EXCHANGE_HOST)
+            return exchange_via_host(c);
+        if (c->opt.exchange == JC_EXCHANGE_METADATA)
+            return exchange_with_metadata(c);
         return jc::launch_exchange(c->d_pairs(), c->np(), c->max_count, c->stream);
     });
 }
@@ -491,7 +558,8 @@ int iterate_window(jc_ctx* c, int64_t n)
 {
     if (n <= 0)
         return JC_OK;
-    const bool graphs = c->opt.use_graphs && c->stream != nullptr && !c->timing;
+    const bool graphs = c->opt.use_graphs && c->stream != nullptr && !c->timing &&
+                        c->opt.exchange == JC_EXCHANGE_DEVICE;
     if (!graphs) {
         for (int64_t i = 0; i < n; ++i) {
             int st = one_iteration(c, false);
@@ -674,6 +742,8 @@ void jc_destroy(jc_ctx* c)
             (void)hipEventDestroy(e);
         if (c->h_result)
             (void)hipHostFree(c->h_result);
+        if (c->h_stage)
+            (void)hipHostFree(c->h_stage);
     }
     delete c;
 }
@@ -695,6 +765,16 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
     c->arena_bytes = bytes;
     c->stream = static_cast<hipStream_t>(hip_stream);
     JC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(double) * 4, hipHostMallocDefault));
+    if (c->opt.exchange == JC_EXCHANGE_HOST && c->np()) {
+        size_t off = 0;
+        c->h_stage_off.assign(c->np(), 0);
+        for (int q = 0; q < c->np(); ++q) {
+            c->h_stage_off[q] = off;
+            off += align_up(sizeof(double) * (size_t)c->pairs[q].span, kAlign);
+        }
+        c->h_stage_bytes = 2 * off;
+        JC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), c->h_stage_bytes, hipHostMallocDefault));
+    }
     c->hdesc.assign(c->blocks.size(), BlockDesc{});
     for (int bi = 0; bi < c->nb(); ++bi) {
         const HostBlock& hb = c->blocks[bi];

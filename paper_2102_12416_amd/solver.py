@@ -30,7 +30,7 @@ class Solver:
 
     def __init__(self, grid, block_dims=None, cuts=None, mode="staged", with_source=False,
                  tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None,
-                 tile_x=0):
+                 tile_x=0, exchange="device"):
         self.grid = tuple(int(v) for v in grid)
         self.device = torch.device(device)
         self.opt = L.Options()
@@ -41,6 +41,8 @@ class Solver:
             self.opt.ir_enable = 1
             self.opt.ir_dtype = {"f64": L.JC_F64, "f32": L.JC_F32, "bf16": L.JC_BF16}[ir_dtype]
         self.opt.tile_x = int(tile_x)
+        self.opt.exchange = {"device": L.JC_EXCHANGE_DEVICE, "host": L.JC_EXCHANGE_HOST,
+                             "metadata": L.JC_EXCHANGE_METADATA}[exchange]
         self.opt.tile_y = int(tile_y)
         self.opt.z_chunk = int(z_chunk)
         self.opt.use_graphs = int(bool(use_graphs))

@@ -287,3 +287,19 @@ def test_default_tile_width_prefers_fewer_idle_lanes():
         check(L.lib.jc_tile_info(ctx, out))
         assert out[0] == want, (grid, bd, out[0])
         L.lib.jc_destroy(ctx)
+
+
+def test_exchange_mode_validation():
+    opt = L.Options()
+    opt.ir_dtype = L.JC_NONE
+    opt.exchange = 9
+    ctx = ctypes.c_void_p()
+    assert L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    opt.exchange = L.JC_EXCHANGE_HOST
+    opt.mode = L.JC_MODE_FUSED
+    assert L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    opt.mode = L.JC_MODE_STAGED
+    check(L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)))
+    L.lib.jc_destroy(ctx)

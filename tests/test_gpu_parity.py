@@ -355,3 +355,21 @@ def test_division_edge_values_bitwise():
         s.iterate(3)
         got = s.store().cpu().numpy()
     assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("exchange", ["host", "metadata"])
+def test_host_staged_and_metadata_exchange_bitwise(exchange):
+    """The paper's host-staged path and the metadata-announced transfer move
+    the same faces as the device pairing: identical iterates."""
+    n = (40, 36, 33)
+    say("exchange", exchange)
+    u0 = synth.boundary_field(n, seed=12)
+    b = synth.source_field(n, seed=12)
+    ref, _ = oracle.c_jacobi(u0, 15, b)
+    with Solver(n, block_dims=(20, 18, 17), with_source=True, exchange=exchange) as s:
+        s.load(u0, b)
+        s.set_timing(True)
+        s.iterate(15)
+        got = s.store().cpu().numpy()
+        assert s.kernel_time(L.JC_K_EXCHANGE)[1] == 15
+    assert np.array_equal(got, ref)
