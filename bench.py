@@ -1,8 +1,11 @@
 """Jacobi3D benchmark on one MI355X.
 
 Default workload: a 512^3 FP64 grid decomposed into 2x2x2 blocks of 256^3;
-every step is one full iteration of the hot path (pack the paired faces,
-exchange them through the pre-posted pairing, unpack, sweep).  Prints one
+every step is one full iteration of the hot path: the faces of every block
+are packed, moved through the pre-posted pairing and read as ghosts, and
+the blocks are swept -- by default in one fused launch per iteration
+(`--mode staged` runs the separate pack, exchange, unpack and sweep
+kernels; both are also compared with host-staged exchange).  Prints one
 JSON line with whole-job throughput in GLUP/s (1e9 interior lattice-site
 updates per second), the sweep kernel's bandwidth against the HBM roofline
 and the CPU oracle timed on a bounded sample of the same workload.
@@ -27,7 +30,7 @@ METRIC = "Jacobi3D GLUP/s + HBM GB/s (% peak); served solves/s, p50/p99 at 1e-10
 
 WORKLOADS = {
     # name: (grid, block_dims or None, uneven cuts seed or None, default mode)
-    "512_2x2x2": ((512, 512, 512), (256, 256, 256), None, "staged"),
+    "512_2x2x2": ((512, 512, 512), (256, 256, 256), None, "fused"),
     "64_single": ((64, 64, 64), None, None, "staged"),
     "768_8x8x8": ((768, 768, 768), (96, 96, 96), None, "fused"),
     "768_uneven": ((768, 768, 768), None, 12416, "fused"),
@@ -36,7 +39,8 @@ WORKLOADS = {
 # Tile shapes picked by jc_autotune on an MI355X for the default mode
 # (rows per tile, planes per work item); other workloads tune at start-up.
 TUNED_TILES = {
-    "512_2x2x2": (64, 32, 64),
+    ("512_2x2x2", "fused"): (64, 32, 256),
+    ("512_2x2x2", "staged"): (64, 32, 64),
 }
 
 
@@ -103,7 +107,7 @@ def recorded_traffic(workload, mode, tile):
     they were taken on the current kernel source and the same launch shape
     (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_sweep_%s_fp64.counters.json" % workload)
+    path = os.path.join(ROOT, "profiles", "k_sweep_%s_%s_fp64.counters.json" % (workload, mode))
     src = os.path.join(ROOT, "paper_2102_12416_amd", "csrc", "jc_kernels.hip")
     try:
         rec = json.load(open(path))
@@ -335,8 +339,8 @@ def main():
     given = bool(args.tile_x or args.tile_y or args.z_chunk)
     tile_source = "given" if given else "library default"
     if not given:
-        if args.workload in TUNED_TILES and mode == default_mode and not args.autotune:
-            s.set_tiles(*TUNED_TILES[args.workload])
+        if (args.workload, mode) in TUNED_TILES and not args.autotune:
+            s.set_tiles(*TUNED_TILES[(args.workload, mode)])
             tile_source = "tuned (jc_autotune on MI355X)"
         elif not args.no_autotune:
             tuned = s.autotune(reps=3)
@@ -408,10 +412,10 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
-    if mode == "staged" and not args.no_ab and bd is not None:
+    if not args.no_ab and bd is not None:
         print("[bench] exchange A/B: device pairing vs host staging vs host metadata", file=sys.stderr, flush=True)
-        out["exchange_ab"] = exchange_ab(grid, bd, args.seed, args.ab_iters,
-                                         (tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]))
+        st_tiles = TUNED_TILES.get((args.workload, "staged"), (tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]))
+        out["exchange_ab"] = exchange_ab(grid, bd, args.seed, args.ab_iters, st_tiles)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline (%.0f s budget)" % args.cpu_seconds, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid, args.seed, args.cpu_seconds)
