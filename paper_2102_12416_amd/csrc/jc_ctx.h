@@ -133,6 +133,13 @@ struct jc_ctx {
     int32_t* d_ranges() const { return reinterpret_cast<int32_t*>(arena + off_ranges); }
     double* d_result() const { return reinterpret_cast<double*>(arena + off_result); }
     int nb() const { return (int)blocks.size(); }
+    int64_t max_rows() const
+    {
+        int64_t m = 1;
+        for (const HostBlock& b : blocks)
+            m = b.n[1] * b.n[2] > m ? b.n[1] * b.n[2] : m;
+        return m;
+    }
     int np() const { return (int)pairs.size(); }
 };
 

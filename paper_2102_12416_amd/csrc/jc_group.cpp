@@ -33,6 +33,7 @@ struct Class {
     bool src = false;    // members with a source
     int lo = JC_F64;     // refinement storage
     int bstart = 0, bend = 0;        // joint block range
+    int64_t max_rows = 1;            // largest ny * nz of the class's blocks
     size_t item0 = 0;                // first joint item
     std::vector<Item> items;
     std::vector<int> members;
@@ -125,7 +126,7 @@ int group_sweep(jc_group* g)
             const jc_ctx* c0 = g->members[k.members[0]];
             hipError_t e;
             if (c0->ir_phase == 1)
-                e = jc::launch_ir_first(g->d_desc() + k.bstart, k.bend - k.bstart, k.lo, g->stream);
+                e = jc::launch_ir_first(g->d_desc() + k.bstart, k.bend - k.bstart, k.max_rows, k.lo, g->stream);
             else
                 e = jc::launch_ir_inner(g->d_desc(), g->d_items() + k.item0, n, c0->ir_q, jc::kTileX, kGroupTileY, k.lo,
                                         g->stream);
@@ -217,6 +218,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_
         for (int m : k.members) {
             const jc_ctx* c = ctxs[m];
             g->member_bstart[m] = (int)g->desc.size();
+            k.max_rows = std::max(k.max_rows, c->max_rows());
             const size_t i0 = g->items.size();
             const size_t first = k.items.size();
             member_items(c, (int)g->desc.size(), m, k.items);
@@ -430,7 +432,7 @@ int jc_group_residuals(jc_group* g, double* host_l2)
             }
             if (c->ir_phase == 2) {
                 // outer update with the correction of the sweeps just run
-                st = ghip(jc::launch_ir_update(bd, nb, c->parity, c->ir_q, k.lo, g->stream), "update");
+                st = ghip(jc::launch_ir_update(bd, nb, c->max_rows(), c->parity, c->ir_q, k.lo, g->stream), "update");
                 if (st != JC_OK)
                     return st;
             }

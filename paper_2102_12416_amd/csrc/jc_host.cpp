@@ -854,7 +854,8 @@ int jc_load_field(jc_ctx* c, int which, const void* src)
         return fail(JC_ERR_INVALID, "context was created without a source field");
     if (which != JC_FIELD_U && which != JC_FIELD_B)
         return fail(JC_ERR_INVALID, "which must be JC_FIELD_U or JC_FIELD_B");
-    JC_HIP(jc::launch_scatter(c->d_blocks(), c->nb(), static_cast<const double*>(src), c->grid[0], c->grid[1],
+    JC_HIP(jc::launch_scatter(c->d_blocks(), c->nb(), c->max_rows(), static_cast<const double*>(src), c->grid[0],
+                              c->grid[1],
                               which, c->stream));
     if (which == JC_FIELD_U) {
         c->loaded_u = true;
@@ -882,7 +883,7 @@ int jc_store_field(jc_ctx* c, int which, void* dst)
         return fail(JC_ERR_INVALID, "which must be JC_FIELD_U or JC_FIELD_B");
     if ((which == JC_FIELD_U && !c->loaded_u) || (which == JC_FIELD_B && !c->loaded_b))
         return fail(JC_ERR_STATE, "field was never loaded");
-    JC_HIP(jc::launch_gather(c->d_blocks(), c->nb(), static_cast<double*>(dst), c->grid[0], c->grid[1],
+    JC_HIP(jc::launch_gather(c->d_blocks(), c->nb(), c->max_rows(), static_cast<double*>(dst), c->grid[0], c->grid[1],
                              c->grid[2], which, c->parity, c->stream));
     return JC_OK;
 }
@@ -1103,24 +1104,53 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
         if (done >= max_inner)
             break;
         const int64_t m = std::min<int64_t>(inner_sweeps, max_inner - done);
-        st = timed(c, JC_K_IR_INNER, [&] {
-            return jc::launch_ir_first(c->d_blocks(), c->nb(), lo, c->stream);
-        });
-        if (st != JC_OK)
-            return st;
-        int q = 1;
-        for (int64_t j = 1; j < m; ++j) {
-            st = timed(c, JC_K_IR_INNER, [&] {
-                return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), q, c->tile_x, c->tile_y,
-                                           lo,
-                                           c->stream);
+        // the m inner sweeps of a step: first sweep (d_0 = 0) into copy 1,
+        // then alternating copies; the result lands in copy m mod 2
+        const int q = (int)(m & 1);
+        auto inner_window = [&]() -> int {
+            int s2 = timed(c, JC_K_IR_INNER, [&] {
+                return jc::launch_ir_first(c->d_blocks(), c->nb(), c->max_rows(), lo, c->stream);
             });
+            int qq = 1;
+            for (int64_t j = 1; j < m && s2 == JC_OK; ++j) {
+                s2 = timed(c, JC_K_IR_INNER, [&] {
+                    return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), qq, c->tile_x,
+                                               c->tile_y, lo, c->stream);
+                });
+                qq ^= 1;
+            }
+            return s2;
+        };
+        if (c->opt.use_graphs && c->stream != nullptr && !c->timing) {
+            // one graph per window length (key space apart from jc_iterate's)
+            const auto key = std::make_pair(m, 2);
+            auto found = c->graphs.find(key);
+            if (found == c->graphs.end()) {
+                JC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                st = inner_window();
+                hipGraph_t graph = nullptr;
+                const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+                if (st != JC_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return st;
+                }
+                if (e != hipSuccess)
+                    return fail(JC_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+                hipGraphExec_t exec = nullptr;
+                const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e2 != hipSuccess)
+                    return fail(JC_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+                found = c->graphs.emplace(key, exec).first;
+            }
+            JC_HIP(hipGraphLaunch(found->second, c->stream));
+        } else {
+            st = inner_window();
             if (st != JC_OK)
                 return st;
-            q ^= 1;
         }
         st = timed(c, JC_K_IR_OUTER, [&] {
-            return jc::launch_ir_update(c->d_blocks(), c->nb(), c->parity, q, lo, c->stream);
+            return jc::launch_ir_update(c->d_blocks(), c->nb(), c->max_rows(), c->parity, q, lo, c->stream);
         });
         if (st != JC_OK)
             return st;

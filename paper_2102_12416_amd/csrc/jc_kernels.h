@@ -29,8 +29,10 @@ hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int ni
                               int tile_y, bool src, int lo_dtype, double* partials, hipStream_t s);
 hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_x,
                            int tile_y, int lo_dtype, hipStream_t s);
-hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int lo_dtype, hipStream_t s);
-hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int p, int q, int lo_dtype, hipStream_t s);
+// max_rows: the largest ny * nz over the blocks (sizes the grid).
+hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int64_t max_rows, int lo_dtype, hipStream_t s);
+hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int64_t max_rows, int p, int q, int lo_dtype,
+                            hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Sum partials[ranges[2m] .. ranges[2m+1]) in a fixed order into out[m], m < nmembers.
@@ -47,9 +49,9 @@ hipError_t launch_unpack(const BlockDesc* blocks, const PairDesc* pairs, int npa
 
 // Global padded array <-> blocks.  which: 0 = iterate (both copies on
 // scatter; copy `parity` on gather), 1 = source.
-hipError_t launch_scatter(const BlockDesc* blocks, int nblocks, const double* global,
+hipError_t launch_scatter(const BlockDesc* blocks, int nblocks, int64_t max_rows, const double* global,
                           int64_t gnx, int64_t gny, int which, hipStream_t s);
-hipError_t launch_gather(const BlockDesc* blocks, int nblocks, double* global, int64_t gnx,
+hipError_t launch_gather(const BlockDesc* blocks, int nblocks, int64_t max_rows, double* global, int64_t gnx,
                          int64_t gny, int64_t gnz, int which, int parity, hipStream_t s);
 
 }  // namespace jc

@@ -757,6 +757,15 @@ k_gather(const BlockDesc* __restrict__ blocks, double* __restrict__ g, int64_t g
     }
 }
 
+// Row kernels: one work-group per row of the largest block, up to 16384.
+dim3 row_grid(int nblocks, int64_t max_rows)
+{
+    int64_t per = max_rows;
+    if (per > 16384) per = 16384;
+    if (per < 1) per = 1;
+    return dim3((unsigned)per, (unsigned)nblocks);
+}
+
 }  // namespace
 
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
@@ -806,11 +815,11 @@ hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitem
     }
 }
 
-hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int lo_dtype, hipStream_t s)
+hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int64_t max_rows, int lo_dtype, hipStream_t s)
 {
     if (nblocks <= 0)
         return hipSuccess;
-    const dim3 grid(512, nblocks);
+    const dim3 grid = row_grid(nblocks, max_rows);
     switch (lo_dtype) {
     case 0: hipLaunchKernelGGL(k_ir_first<double>, grid, dim3(256), 0, s, blocks); break;
     case 1: hipLaunchKernelGGL(k_ir_first<float>, grid, dim3(256), 0, s, blocks); break;
@@ -820,11 +829,12 @@ hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int lo_dtype, h
     return hipGetLastError();
 }
 
-hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int p, int q, int lo_dtype, hipStream_t s)
+hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int64_t max_rows, int p, int q, int lo_dtype,
+                            hipStream_t s)
 {
     if (nblocks <= 0)
         return hipSuccess;
-    const dim3 grid(512, nblocks);
+    const dim3 grid = row_grid(nblocks, max_rows);
     switch (lo_dtype) {
     case 0: hipLaunchKernelGGL(k_ir_update<double>, grid, dim3(256), 0, s, blocks, p, q); break;
     case 1: hipLaunchKernelGGL(k_ir_update<float>, grid, dim3(256), 0, s, blocks, p, q); break;
@@ -885,21 +895,21 @@ hipError_t launch_unpack(const BlockDesc* blocks, const PairDesc* pairs, int npa
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const BlockDesc* blocks, int nblocks, const double* global, int64_t gnx,
-                          int64_t gny, int which, hipStream_t s)
+hipError_t launch_scatter(const BlockDesc* blocks, int nblocks, int64_t max_rows, const double* global,
+                          int64_t gnx, int64_t gny, int which, hipStream_t s)
 {
     if (nblocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(256, nblocks), dim3(256), 0, s, blocks, global, gnx, gny, which);
+    hipLaunchKernelGGL(k_scatter, row_grid(nblocks, max_rows), dim3(256), 0, s, blocks, global, gnx, gny, which);
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const BlockDesc* blocks, int nblocks, double* global, int64_t gnx,
+hipError_t launch_gather(const BlockDesc* blocks, int nblocks, int64_t max_rows, double* global, int64_t gnx,
                          int64_t gny, int64_t gnz, int which, int parity, hipStream_t s)
 {
     if (nblocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(256, nblocks), dim3(256), 0, s, blocks, global, gnx, gny, gnz,
+    hipLaunchKernelGGL(k_gather, row_grid(nblocks, max_rows), dim3(256), 0, s, blocks, global, gnx, gny, gnz,
                        which, parity);
     return hipGetLastError();
 }
