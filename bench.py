@@ -106,17 +106,28 @@ def recorded_traffic(workload, mode, tile):
     """HBM bytes per sweep launch from the committed rocprofv3 counters, if
     they were taken on the current kernel source and the same launch shape
     (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep_%s_%s_fp64.counters.json" % (workload, mode))
-    src = os.path.join(ROOT, "paper_2102_12416_amd", "csrc", "jc_kernels.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = sweep_source_sha256()
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_source_sha256") != sha or rec.get("mode") != mode or list(rec.get("tile", [])) != list(tile):
+    if rec.get("sweep_source_sha256") != sha or rec.get("mode") != mode or list(rec.get("tile", [])) != list(tile):
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def sweep_source_sha256():
+    """Fingerprint of the sweep kernel: its region of jc_kernels.hip plus
+    the shared table definitions it reads."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2102_12416_amd", "csrc")
+    text = open(os.path.join(csrc, "jc_kernels.hip")).read()
+    a = text.index("// ---- sweep kernel: begin")
+    b = text.index("// ---- sweep kernel: end")
+    h = hashlib.sha256(text[a:b].encode())
+    h.update(open(os.path.join(csrc, "jc_types.h"), "rb").read())
+    return h.hexdigest()
 
 
 def exchange_ab(grid, bd, seed, iters, tiles):
