@@ -238,8 +238,12 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * ctxs is read during the call; the contexts must outlive the group and
  * must not be used on their own streams while the group exists.
  * flags: bit 0 = capture jc_group_iterate windows as HIP graphs (needs a
- * non-null stream).  Host only until jc_group_bind. */
-int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_group** out);
+ * non-null stream).  tile: {cells per row 32|64, rows 4|8|16|32, planes
+ * >= 1} for every launch of the group, or NULL for {64, 8, 32}; members'
+ * results do not depend on it, their residual norms do in the last bits,
+ * so compare mixes within one tile shape.  Host only until jc_group_bind. */
+int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, const int tile[3],
+                    jc_group** out);
 /* Device scratch the group needs (joint tables, partial sums). */
 int jc_group_footprint(const jc_group* g, size_t* bytes);
 /* Attach caller-owned scratch (>= footprint, 256-byte aligned); orders the

@@ -80,7 +80,8 @@ SIGNATURES = {
     "jc_residual": (ctypes.c_int, [CTX, ctypes.POINTER(ctypes.c_double)]),
     "jc_solve": (ctypes.c_int, [CTX, ctypes.c_double, I64, I64, ctypes.POINTER(SolveInfo)]),
     "jc_solve_ir": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.c_double, I64, ctypes.POINTER(SolveInfo)]),
-    "jc_group_create": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, VP, ctypes.c_int, ctypes.POINTER(VP)]),
+    "jc_group_create": (ctypes.c_int, [ctypes.POINTER(CTX), ctypes.c_int, VP, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(VP)]),
     "jc_group_footprint": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_size_t)]),
     "jc_group_bind": (ctypes.c_int, [VP, VP, ctypes.c_size_t]),
     "jc_group_iterate": (ctypes.c_int, [VP, I64]),

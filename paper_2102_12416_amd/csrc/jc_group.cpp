@@ -25,8 +25,8 @@ using namespace jc_rt;
 
 namespace {
 
-constexpr int kGroupTileY = 8;
-constexpr int kGroupZChunk = 32;
+// Default tile shape of a group; a group's shape is fixed at creation.
+constexpr int kGroupTile[3] = {64, 8, 32};
 
 struct Class {
     bool ir = false;     // refinement members
@@ -45,6 +45,7 @@ struct jc_group {
     std::vector<jc_ctx*> members;
     hipStream_t stream = nullptr;
     bool use_graphs = false;
+    int tile[3] = {kGroupTile[0], kGroupTile[1], kGroupTile[2]};
     std::vector<Class> classes;
     std::vector<BlockDesc> desc;        // joint block table, class-major
     std::vector<Item> items;            // joint work list, class-major
@@ -74,20 +75,20 @@ int ghip(hipError_t e, const char* what)
     return JC_OK;
 }
 
-// Items of one member's blocks with the group's fixed tile shape.
-void member_items(const jc_ctx* c, int bbase, int member, std::vector<Item>& out)
+// Items of one member's blocks with the group's tile shape.
+void member_items(const jc_ctx* c, const int tile[3], int bbase, int member, std::vector<Item>& out)
 {
     for (int bi = 0; bi < (int)c->blocks.size(); ++bi) {
         const HostBlock& b = c->blocks[bi];
-        for (int64_t z0 = 0; z0 < b.n[2]; z0 += kGroupZChunk)
-            for (int64_t y0 = 0; y0 < b.n[1]; y0 += kGroupTileY)
-                for (int64_t x0 = 0; x0 < b.n[0]; x0 += jc::kTileX) {
+        for (int64_t z0 = 0; z0 < b.n[2]; z0 += tile[2])
+            for (int64_t y0 = 0; y0 < b.n[1]; y0 += tile[1])
+                for (int64_t x0 = 0; x0 < b.n[0]; x0 += tile[0]) {
                     Item it{};
                     it.block = bbase + bi;
                     it.x0 = (int32_t)x0;
                     it.y0 = (int32_t)y0;
                     it.z0 = (int32_t)z0;
-                    it.zlen = (int32_t)std::min<int64_t>(kGroupZChunk, b.n[2] - z0);
+                    it.zlen = (int32_t)std::min<int64_t>(tile[2], b.n[2] - z0);
                     it.flip = c->parity;
                     it.owner = member;
                     out.push_back(it);
@@ -116,7 +117,7 @@ int group_sweep(jc_group* g)
     for (const Class& k : g->classes) {
         const int n = (int)k.items.size();
         if (!k.ir) {
-            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, jc::kTileX, kGroupTileY,
+            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, g->tile[0], g->tile[1],
                                                   true, false, true, k.src, nullptr, g->stream);
             if (e != hipSuccess)
                 return ghip(e, "group sweep");
@@ -128,7 +129,7 @@ int group_sweep(jc_group* g)
             if (c0->ir_phase == 1)
                 e = jc::launch_ir_first(g->d_desc() + k.bstart, k.bend - k.bstart, k.max_rows, k.lo, g->stream);
             else
-                e = jc::launch_ir_inner(g->d_desc(), g->d_items() + k.item0, n, c0->ir_q, jc::kTileX, kGroupTileY, k.lo,
+                e = jc::launch_ir_inner(g->d_desc(), g->d_items() + k.item0, n, c0->ir_q, g->tile[0], g->tile[1], k.lo,
                                         g->stream);
             if (e != hipSuccess)
                 return ghip(e, "group inner sweep");
@@ -166,7 +167,7 @@ void advance(jc_group* g, int64_t n)
 
 extern "C" {
 
-int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_group** out)
+int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, const int tile[3], jc_group** out)
 {
     if (!out)
         return fail(JC_ERR_INVALID, "out must not be NULL");
@@ -186,9 +187,18 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_
         if (c->opt.ir_enable && c->parity != 0)
             return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
     }
+    if (tile) {
+        const bool ok = (tile[0] == 32 || tile[0] == 64) &&
+                        (tile[1] == 4 || tile[1] == 8 || tile[1] == 16 || tile[1] == 32) && tile[2] >= 1;
+        if (!ok)
+            return fail(JC_ERR_INVALID, "group tile must be {32|64, 4|8|16|32, >= 1}");
+    }
     jc_group* g = new (std::nothrow) jc_group();
     if (!g)
         return fail(JC_ERR_NOMEM, "host allocation failed");
+    if (tile)
+        for (int a = 0; a < 3; ++a)
+            g->tile[a] = tile[a];
     g->members.assign(ctxs, ctxs + n);
     g->stream = static_cast<hipStream_t>(hip_stream);
     g->use_graphs = (flags & 1) && g->stream != nullptr;
@@ -221,7 +231,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, jc_
             k.max_rows = std::max(k.max_rows, c->max_rows());
             const size_t i0 = g->items.size();
             const size_t first = k.items.size();
-            member_items(c, (int)g->desc.size(), m, k.items);
+            member_items(c, g->tile, (int)g->desc.size(), m, k.items);
             g->desc.insert(g->desc.end(), c->hdesc.begin(), c->hdesc.end());
             g->items.insert(g->items.end(), k.items.begin() + first, k.items.end());
             g->lohi[2 * m] = (int32_t)i0;
@@ -414,7 +424,7 @@ int jc_group_residuals(jc_group* g, double* host_l2)
     for (const Class& k : g->classes) {
         const int n = (int)k.items.size();
         if (!k.ir) {
-            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, jc::kTileX, kGroupTileY,
+            const hipError_t e = jc::launch_sweep(g->d_desc(), g->d_items() + k.item0, n, g->parity, g->tile[0], g->tile[1],
                                                   true, true, false, k.src, g->d_partials() + k.item0, g->stream);
             if (e != hipSuccess)
                 return ghip(e, "group residual");
@@ -438,7 +448,7 @@ int jc_group_residuals(jc_group* g, double* host_l2)
             }
         }
         // refining members keep their iterate in copy 0 (their items' flip is 0)
-        const hipError_t e = jc::launch_ir_residual(g->d_desc(), g->d_items() + k.item0, n, 0, jc::kTileX, kGroupTileY,
+        const hipError_t e = jc::launch_ir_residual(g->d_desc(), g->d_items() + k.item0, n, 0, g->tile[0], g->tile[1],
                                                     k.src, k.lo, g->d_partials() + k.item0, g->stream);
         if (e != hipSuccess)
             return ghip(e, "group refinement residual");

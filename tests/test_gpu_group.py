@@ -80,3 +80,20 @@ def test_group_matches_own_path_and_oracle():
     assert done == 150
     assert np.array_equal(res[2], ref)
     np.testing.assert_allclose(hist[:, 2] / hist[0, 2], rh, rtol=1e-9)
+
+
+def test_group_tile_shape_keeps_results():
+    say("group tile shapes")
+    ref, _ = run([0, 2, 3])
+    for tile in ((32, 4, 16), (64, 32, 7)):
+        solvers = [make(SPECS[i], seed=100 + i) for i in (0, 2, 3)]
+        with Group(solvers, tile=tile) as g:
+            for _ in range(4):
+                g.residuals()
+                g.iterate(50)
+            g.residuals()
+        got = [s.store().cpu().numpy() for s in solvers]
+        for s in solvers:
+            s.close()
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), tile
