@@ -332,7 +332,7 @@ def bench_serve(args):
     # capacity: the same request mix, all queued at once (closed loop)
     ncap = args.serve_capacity_requests or args.serve_requests
     cap_reqs = reqs(ncap, 0.0, args.seed)
-    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter)
+    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter, progress_every=15.0)
     t0 = time.perf_counter()
     res = srv.run(cap_reqs, realtime=False)
     cap_time = time.perf_counter() - t0
@@ -340,7 +340,7 @@ def bench_serve(args):
     print("[bench] closed-loop capacity: %s" % json.dumps(cap), file=sys.stderr, flush=True)
     rate = 0.7 * cap["solves_per_s"]
     run_reqs = reqs(args.serve_requests, rate, args.seed)
-    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter)
+    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter, progress_every=15.0)
     t0 = time.perf_counter()
     res = srv.run(run_reqs, realtime=True)
     span = time.perf_counter() - t0

@@ -21,6 +21,7 @@ mix.
 """
 from __future__ import annotations
 
+import sys
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -90,7 +91,8 @@ class Server:
     """Continuous-batching Jacobi3D solve server on one GPU."""
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
-                 device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True):
+                 device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
+                 progress_every: float = 0.0):
         if window < 1 or max_iter % window:
             raise ValueError("max_iter must be a multiple of the window")
         self.budget = int(budget_bytes)
@@ -103,6 +105,7 @@ class Server:
         self.stream = torch.cuda.Stream(device=self.device)
         self.max_members = 4096
         self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0)
+        self.progress_every = float(progress_every)   # seconds between progress lines (0: none)
 
     # ---------------------------------------------------------------- admit
     def _admit(self, req: Request, now: float) -> _Live:
@@ -148,8 +151,14 @@ class Server:
         def clock():
             return time.perf_counter() - t0
 
+        last_report = 0.0
         while incoming or queue or active:
             now = clock()
+            if self.progress_every > 0 and now - last_report >= self.progress_every:
+                last_report = now
+                print("[serve] t=%.1fs done=%d active=%d queued=%d arriving=%d windows=%d"
+                      % (now, len(done), len(active), len(queue), len(incoming), self.stats["windows"]),
+                      file=sys.stderr, flush=True)
             while incoming and (not realtime or incoming[0].arrival <= now):
                 queue.append(incoming.popleft())
             # admission by footprint, oldest first
