@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--serve-max-edge", type=int, default=384)
     ap.add_argument("--serve-max-iter", type=int, default=20000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-lanes", default="64,160",
+                    help="ascending edge bounds of the server's size lanes ('none': one group for all)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="Poisson arrival rate (requests/s); 0 = 0.7 x the measured closed-loop capacity")
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
     ap.add_argument("--seed", type=int, default=12416)
     ap.add_argument("--tile-x", type=int, default=0, help="cells per tile row, 32 or 64 (0: library default)")
@@ -320,7 +324,9 @@ def bench_grids(args):
 
 def bench_serve(args):
     """Continuous-batching server: closed-loop capacity, then Poisson
-    arrivals at 0.7x capacity; p50/p99 latency and solves/s."""
+    arrivals at 0.7x capacity (or a given rate); p50/p99 latency and solves/s."""
+    import numpy as np
+
     import synth
     from paper_2102_12416_amd.server import Request, Server, summarize
 
@@ -329,29 +335,41 @@ def bench_serve(args):
                 for r in synth.serving_requests(count, rate, seed=seed, lo=32, hi=args.serve_max_edge)]
 
     budget = int(args.serve_budget_gb * (1 << 30))
-    # capacity: the same request mix, all queued at once (closed loop)
-    ncap = args.serve_capacity_requests or args.serve_requests
-    cap_reqs = reqs(ncap, 0.0, args.seed)
-    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter, progress_every=15.0)
-    t0 = time.perf_counter()
-    res = srv.run(cap_reqs, realtime=False)
-    cap_time = time.perf_counter() - t0
-    cap = summarize(res, cap_time)
-    print("[bench] closed-loop capacity: %s" % json.dumps(cap), file=sys.stderr, flush=True)
-    rate = 0.7 * cap["solves_per_s"]
+    lanes = () if args.serve_lanes in ("", "none") else tuple(int(v) for v in args.serve_lanes.split(","))
+
+    def server():
+        return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter,
+                      progress_every=15.0, lanes=lanes)
+
+    cap = None
+    rate = args.serve_rate
+    if rate <= 0:
+        # capacity: the same request mix, all queued at once (closed loop)
+        ncap = args.serve_capacity_requests or args.serve_requests
+        cap_reqs = reqs(ncap, 0.0, args.seed)
+        srv = server()
+        t0 = time.perf_counter()
+        res = srv.run(cap_reqs, realtime=False)
+        cap_time = time.perf_counter() - t0
+        cap = summarize(res, cap_time)
+        print("[bench] closed-loop capacity: %s" % json.dumps(cap), file=sys.stderr, flush=True)
+        rate = 0.7 * cap["solves_per_s"]
     run_reqs = reqs(args.serve_requests, rate, args.seed)
-    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter, progress_every=15.0)
+    srv = server()
     t0 = time.perf_counter()
     res = srv.run(run_reqs, realtime=True)
     span = time.perf_counter() - t0
     summ = summarize(res, span)
+    small = [r.latency for r in res if not r.rejected and r.n <= 64]
+    summ["p50_s_edge_le_64"] = float(np.percentile(small, 50)) if small else None
     out = {"metric": "served solves/s, p50/p99 latency at 1e-10 relative residual or the sweep cap",
            "value": round(summ["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "dtype": "f64 / f32-refined",
            "config": {"workload": "serve", "requests": args.serve_requests, "rate_per_s": round(rate, 3),
                       "edges": "log-uniform [32, %d]" % args.serve_max_edge, "precision": "Bernoulli(0.5) f64/f32",
                       "rtol": 1e-10, "max_iter": args.serve_max_iter, "window": 50,
-                      "budget_gb": args.serve_budget_gb},
+                      "budget_gb": args.serve_budget_gb, "lanes": list(lanes),
+                      "rate_source": "given" if args.serve_rate > 0 else "0.7 x closed-loop capacity"},
            "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4), "summary": summ,
            "capacity": cap, "server_stats": srv.stats}
     print(json.dumps(out), flush=True)

@@ -2,22 +2,29 @@
 
 Requests (cubic grids of different sizes, binary64 or binary32-refined)
 arrive over time.  The loop keeps every admitted solve's fields, halos and
-face buffers resident in HBM and sweeps all of them in shared launches (a
-libjc group).  At every window boundary (every `window` sweeps) it:
+face buffers resident in HBM and sweeps them in shared launches (libjc
+groups).  Requests are split into size lanes; each lane has its own stream,
+group and window cadence, so the windows of small solves (tens of
+microseconds) never wait behind those of large ones (milliseconds), and
+the lanes' launches overlap on the device.
 
-  1. admits queued requests, oldest first, while their device footprint
-     fits the free HBM budget (the head of the queue waits for memory;
-     a request larger than the whole budget is rejected);
+The loop admits queued requests, oldest first, while their device
+footprint fits the free HBM budget (the head of the queue waits for memory;
+a request larger than the whole budget is rejected) and hands each to its
+lane.  At every window boundary of a lane (every `window` sweeps) it:
+
+  1. lets the lane's newly admitted requests join;
   2. computes every member's residual norm in one batched pass (for the
      refined solves this is their binary64 outer step);
   3. retires members that reached the relative tolerance or the sweep cap
      (their result is copied out, their arena freed);
-  4. rebuilds the group if membership changed and runs the next window.
+  4. rebuilds the lane's group if membership changed and enqueues the next
+     window.
 
 Latency = retirement time - arrival time.  The schedule of a solve (its
-windows, checks and stop) depends only on its own data, and a group's
-tile shape is fixed, so every result is bitwise the same alone and in any
-mix.
+windows, checks and stop) depends only on its own data, and every group
+uses the same tile shape, so every result is bitwise the same alone, in
+any mix and in any lane.
 """
 from __future__ import annotations
 
@@ -87,14 +94,44 @@ class _Live:
     r0: float = -1.0
 
 
+class _Lane:
+    """Requests of one size class: their own stream, group and window
+    cadence, so a small solve never waits for the windows of large ones."""
+
+    def __init__(self, max_edge, device):
+        self.max_edge = max_edge          # largest edge in this lane (None: unbounded)
+        self.stream = torch.cuda.Stream(device=device)
+        self.active: list[_Live] = []
+        self.pending: list[_Live] = []    # admitted, joining at the next window boundary
+        self.group = None
+        self.key = None
+        self.done = None                  # event: the last enqueued window has finished
+        self.windows = 0
+
+    def busy(self):
+        return self.done is not None and not self.done.query()
+
+    def close(self):
+        if self.group is not None:
+            self.group.close()
+            self.group = None
+
+
 class Server:
-    """Continuous-batching Jacobi3D solve server on one GPU."""
+    """Continuous-batching Jacobi3D solve server on one GPU.
+
+    lanes: ascending edge bounds of the size classes; a request of edge n
+    joins the first lane with n <= bound, else the last (unbounded) lane.
+    An empty tuple serves everything in one group."""
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
-                 progress_every: float = 0.0):
+                 progress_every: float = 0.0, lanes=(64, 160)):
         if window < 1 or max_iter % window:
             raise ValueError("max_iter must be a multiple of the window")
+        bounds = [int(v) for v in lanes]
+        if any(b < 1 for b in bounds) or bounds != sorted(set(bounds)):
+            raise ValueError("lane bounds must be ascending positive edges")
         self.budget = int(budget_bytes)
         self.window = int(window)
         self.rtol = float(rtol)
@@ -102,17 +139,17 @@ class Server:
         self.device = torch.device(device)
         self.keep_fields = keep_fields
         self.use_graphs = use_graphs
-        self.stream = torch.cuda.Stream(device=self.device)
+        self.lane_bounds = tuple(bounds)
         self.max_members = 4096
-        self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0)
+        self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0, lane_windows=[])
         self.progress_every = float(progress_every)   # seconds between progress lines (0: none)
 
     # ---------------------------------------------------------------- admit
-    def _admit(self, req: Request, now: float) -> _Live:
+    def _admit(self, req: Request, now: float, stream) -> _Live:
         n = req.n
         ir = "f32" if req.precision == "f32" else None
         s = Solver((n, n, n), mode="fused", with_source=True, ir_dtype=ir, device=str(self.device),
-                   use_graphs=False)
+                   use_graphs=False, stream=stream)
         with torch.cuda.stream(s.stream):
             g = synth_field((n, n, n), req.seed, 0, device=str(self.device), stream=s.stream)
             b = synth_field((n, n, n), req.seed, 1, device=str(self.device), stream=s.stream)
@@ -132,6 +169,55 @@ class Server:
             live.res.field = live.solver.store().cpu().numpy()
         live.solver.close()
 
+    def _lane_of(self, lanes, n):
+        for lane in lanes[:-1]:
+            if n <= lane.max_edge:
+                return lane
+        return lanes[-1]
+
+    def _regroup(self, lane):
+        lane.close()
+        if lane.active:
+            lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream)
+            lane.key = tuple(l.req.id for l in lane.active)
+            self.stats["group_builds"] += 1
+
+    def _boundary(self, lane, clock, done) -> int:
+        """One window boundary of an idle lane: members join, every member's
+        residual is taken, finished ones retire, the next window is
+        enqueued.  Returns the device bytes released."""
+        if lane.pending:
+            lane.active += lane.pending
+            lane.pending = []
+        if lane.group is None or lane.key != tuple(l.req.id for l in lane.active):
+            self._regroup(lane)
+        norms = lane.group.residuals()
+        now = clock()
+        freed = 0
+        keep = []
+        for live, r in zip(lane.active, norms):
+            if live.r0 < 0:
+                live.r0 = r
+            rel = r / live.r0 if live.r0 > 0 else 0.0
+            if rel <= self.rtol or live.solver.iterations >= self.max_iter:
+                self._retire(live, now, rel)
+                freed += live.bytes
+                done.append(live.res)
+            else:
+                keep.append(live)
+        if len(keep) != len(lane.active):
+            lane.active = keep
+            self._regroup(lane)
+        if lane.active:
+            # every active solve has done a whole number of windows and is
+            # below its cap, which is a multiple of the window
+            lane.group.iterate(self.window)
+            lane.done = torch.cuda.Event()
+            lane.done.record(lane.stream)
+            lane.windows += 1
+            self.stats["windows"] += 1
+        return freed
+
     # ------------------------------------------------------------------ run
     def run(self, requests, realtime: bool = True):
         """Serve `requests` (Request objects); returns the list of Results.
@@ -141,29 +227,30 @@ class Server:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
         incoming = deque(reqs)
         queue: deque = deque()
-        active: list[_Live] = []
+        lanes = [_Lane(b, self.device) for b in self.lane_bounds] + [_Lane(None, self.device)]
         done: list[Result] = []
         used = 0
-        group = None
-        members_key = None
         t0 = time.perf_counter()
 
         def clock():
             return time.perf_counter() - t0
 
+        def members():
+            return sum(len(l.active) + len(l.pending) for l in lanes)
+
         last_report = 0.0
-        while incoming or queue or active:
+        while incoming or queue or any(l.active or l.pending for l in lanes):
             now = clock()
             if self.progress_every > 0 and now - last_report >= self.progress_every:
                 last_report = now
-                print("[serve] t=%.1fs done=%d active=%d queued=%d arriving=%d windows=%d"
-                      % (now, len(done), len(active), len(queue), len(incoming), self.stats["windows"]),
+                print("[serve] t=%.1fs done=%d active=%d queued=%d arriving=%d windows=%s"
+                      % (now, len(done), members(), len(queue), len(incoming), [l.windows for l in lanes]),
                       file=sys.stderr, flush=True)
             while incoming and (not realtime or incoming[0].arrival <= now):
                 queue.append(incoming.popleft())
-            # admission by footprint, oldest first
-            changed = False
-            while queue and len(active) < self.max_members:
+            # admission by footprint, oldest first; a request joins its
+            # lane at that lane's next window boundary
+            while queue and members() < self.max_members:
                 head = queue[0]
                 need = request_footprint(head.n, head.precision)
                 if need > self.budget:
@@ -174,57 +261,27 @@ class Server:
                 if used + need > self.budget:
                     break
                 queue.popleft()
-                if group is not None:
-                    group.close()
-                    group = None
-                live = self._admit(head, clock())
-                active.append(live)
+                lane = self._lane_of(lanes, head.n)
+                live = self._admit(head, clock(), lane.stream)
+                lane.pending.append(live)
                 used += live.bytes
-                changed = True
-            self.stats["peak_members"] = max(self.stats["peak_members"], len(active))
+            self.stats["peak_members"] = max(self.stats["peak_members"], members())
             self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
-            if not active:
-                if incoming and realtime:
-                    time.sleep(max(0.0, min(0.05, incoming[0].arrival - clock())))
-                continue
-            key = tuple(l.req.id for l in active)
-            if group is None or key != members_key:
-                if group is not None:
-                    group.close()
-                group = Group([l.solver for l in active], use_graphs=self.use_graphs, stream=self.stream)
-                members_key = key
-                self.stats["group_builds"] += 1
-            # window boundary: residuals of everyone, retire finished solves
-            norms = group.residuals()
-            now = clock()
-            keep = []
-            for live, r in zip(active, norms):
-                if live.r0 < 0:
-                    live.r0 = r
-                rel = r / live.r0 if live.r0 > 0 else 0.0
-                if rel <= self.rtol or live.solver.iterations >= self.max_iter:
-                    keep.append(None)
-                    self._retire(live, now, rel)
-                    used -= live.bytes
-                    done.append(live.res)
+            progressed = False
+            for lane in lanes:
+                if (lane.active or lane.pending) and not lane.busy():
+                    used -= self._boundary(lane, clock, done)
+                    progressed = True
+            if not progressed:
+                if not any(l.active or l.pending for l in lanes):
+                    if incoming and realtime:
+                        time.sleep(max(0.0, min(0.05, incoming[0].arrival - clock())))
                 else:
-                    keep.append(live)
-            if any(k is None for k in keep):
-                active = [k for k in keep if k is not None]
-                group.close()
-                group = None
-                if not active:
-                    continue
-                group = Group([l.solver for l in active], use_graphs=self.use_graphs, stream=self.stream)
-                members_key = tuple(l.req.id for l in active)
-                self.stats["group_builds"] += 1
-            # every active solve has done a whole number of windows and is
-            # below its cap, which is a multiple of the window
-            group.iterate(self.window)
-            self.stats["windows"] += 1
-        if group is not None:
-            group.close()
+                    time.sleep(0)
+        for lane in lanes:
+            lane.close()
         torch.cuda.synchronize(self.device)
+        self.stats["lane_windows"] = [l.windows for l in lanes]
         return sorted(done, key=lambda r: r.id)
 
 

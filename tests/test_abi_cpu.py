@@ -303,3 +303,13 @@ def test_exchange_mode_validation():
     opt.mode = L.JC_MODE_STAGED
     check(L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)))
     L.lib.jc_destroy(ctx)
+
+
+def test_server_lane_bounds_validated():
+    from paper_2102_12416_amd.server import Server
+    with pytest.raises(ValueError):
+        Server(budget_bytes=1 << 30, lanes=(160, 64), device="cpu")
+    with pytest.raises(ValueError):
+        Server(budget_bytes=1 << 30, lanes=(0,), device="cpu")
+    with pytest.raises(ValueError):
+        Server(budget_bytes=1 << 30, window=30, max_iter=100, device="cpu")

@@ -21,8 +21,8 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def serve(reqs, budget=1 << 34, max_iter=1500):
-    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=max_iter, keep_fields=True)
+def serve(reqs, budget=1 << 34, max_iter=1500, lanes=(64, 160)):
+    srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=max_iter, keep_fields=True, lanes=lanes)
     res = srv.run(reqs, realtime=False)
     return srv, res
 
@@ -35,6 +35,17 @@ def test_each_result_same_alone_and_in_mix():
         a, m = alone[0], mix[r.id]
         assert a.iters == m.iters and a.converged == m.converged, r.id
         assert np.array_equal(a.field, m.field), r.id
+
+
+@pytest.mark.parametrize("lanes", [(), (24,), (20, 28)])
+def test_lanes_do_not_change_results(lanes):
+    say("server lanes", lanes)
+    _, one = serve(REQS, lanes=())
+    srv, split = serve(REQS, lanes=lanes)
+    assert len(srv.stats["lane_windows"]) == len(lanes) + 1
+    for a, m in zip(one, split):
+        assert a.iters == m.iters and a.converged == m.converged and a.rel_resid == m.rel_resid, a.id
+        assert np.array_equal(a.field, m.field), a.id
 
 
 def test_results_certified_by_oracle():
