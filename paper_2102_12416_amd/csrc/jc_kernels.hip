@@ -90,6 +90,19 @@ template <> struct Tr<double> {
         v.y = b;
         __builtin_nontemporal_store(v, (v2d JC_GLOBAL*)(p));
     }
+    // a pair converted to storage once, stored whole or by element
+    using P = v2d;
+    __device__ static P pack(double a, double b)
+    {
+        v2d v;
+        v.x = a;
+        v.y = b;
+        return v;
+    }
+    __device__ static void stp(double* p, P v) { *(v2d JC_GLOBAL*)(p) = v; }
+    __device__ static void stpn(double* p, P v) { __builtin_nontemporal_store(v, (v2d JC_GLOBAL*)(p)); }
+    __device__ static void st1a(double* p, P v) { *(double JC_GLOBAL*)(p) = v.x; }
+    __device__ static void st1b(double* p, P v) { *(double JC_GLOBAL*)(p) = v.y; }
 };
 
 template <> struct Tr<float> {
@@ -115,6 +128,18 @@ template <> struct Tr<float> {
         v.y = b;
         __builtin_nontemporal_store(v, (v2f JC_GLOBAL*)(p));
     }
+    using P = v2f;
+    __device__ static P pack(float a, float b)
+    {
+        v2f v;
+        v.x = a;
+        v.y = b;
+        return v;
+    }
+    __device__ static void stp(float* p, P v) { *(v2f JC_GLOBAL*)(p) = v; }
+    __device__ static void stpn(float* p, P v) { __builtin_nontemporal_store(v, (v2f JC_GLOBAL*)(p)); }
+    __device__ static void st1a(float* p, P v) { *(float JC_GLOBAL*)(p) = v.x; }
+    __device__ static void st1b(float* p, P v) { *(float JC_GLOBAL*)(p) = v.y; }
 };
 
 template <> struct Tr<bf16> {
@@ -134,6 +159,12 @@ template <> struct Tr<bf16> {
     {
         __builtin_nontemporal_store(f32_to_bf16(a) | (f32_to_bf16(b) << 16), (uint32_t JC_GLOBAL*)(p));
     }
+    using P = uint32_t;                           // x in the low half
+    __device__ static P pack(float a, float b) { return f32_to_bf16(a) | (f32_to_bf16(b) << 16); }
+    __device__ static void stp(bf16* p, P v) { *(uint32_t JC_GLOBAL*)(p) = v; }
+    __device__ static void stpn(bf16* p, P v) { __builtin_nontemporal_store(v, (uint32_t JC_GLOBAL*)(p)); }
+    __device__ static void st1a(bf16* p, P v) { *(uint16_t JC_GLOBAL*)(p) = (uint16_t)(v & 0xffffu); }
+    __device__ static void st1b(bf16* p, P v) { *(uint16_t JC_GLOBAL*)(p) = (uint16_t)(v >> 16); }
 };
 
 // Which arrays of a block a sweep works on: the iterate u (with source b)
@@ -200,6 +231,35 @@ __device__ __forceinline__ float div6(float s)
     if (__builtin_expect(__builtin_fabsf(s) < 0x1p-100f, 0))
         v = s / 6.0f;
     return v;
+}
+
+// The same for a pair, with one (rarely taken) branch to the IEEE division.
+__device__ __forceinline__ double div6_fast(double s)
+{
+    const double y = 0x1.5555555555555p-3;
+    const double q = s * y;
+    return __builtin_fma(__builtin_fma(-6.0, q, s), y, q);
+}
+
+__device__ __forceinline__ float div6_fast(float s)
+{
+    const float y = 0x1.555556p-3f;
+    const float q = s * y;
+    return __builtin_fmaf(__builtin_fmaf(-6.0f, q, s), y, q);
+}
+
+__device__ __forceinline__ bool div6_tiny(double s) { return __builtin_fabs(s) < 0x1p-1000; }
+__device__ __forceinline__ bool div6_tiny(float s) { return __builtin_fabsf(s) < 0x1p-100f; }
+
+template <typename C>
+__device__ __forceinline__ void div6_pair(C sa, C sb, C& va, C& vb)
+{
+    va = div6_fast(sa);
+    vb = div6_fast(sb);
+    if (__builtin_expect(div6_tiny(sa) || div6_tiny(sb), 0)) {
+        va = div6_tiny(sa) ? sa / C(6) : va;
+        vb = div6_tiny(sb) ? sb / C(6) : vb;
+    }
 }
 
 // One work-group sweeps a tile of 2 TXP x cells (64 or 32) by TY rows of
@@ -340,21 +400,52 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hcol = role == 2 ? 1 : x_end - x0 + 2;
     }
 
+    // Face stores of the fused epilogue.  Which of this thread's cells lie
+    // on an x or y face does not change along z; a tile that touches no
+    // paired x or y face (most tiles) skips them with one uniform branch.
+    T* const oxm = FUSED ? F::gout(B, XM, p ^ 1) : nullptr;
+    T* const oxp = FUSED ? F::gout(B, XP, p ^ 1) : nullptr;
+    T* const oym = FUSED ? F::gout(B, YM, p ^ 1) : nullptr;
+    T* const oyp = FUSED ? F::gout(B, YP, p ^ 1) : nullptr;
+    T* const ozm = FUSED ? F::gout(B, ZM, p ^ 1) : nullptr;
+    T* const ozp = FUSED ? F::gout(B, ZP, p ^ 1) : nullptr;
+    const bool xy_tile = FUSED && ((x0 == 0 && oxm) || (x_end == nx && oxp) || (y0 == 0 && oym) ||
+                                   (y_end == ny && oyp));
+    const bool f_xm = a_ok && xa == 1 && oxm;
+    const bool f_xpa = a_ok && xa == nx && oxp;
+    const bool f_xpb = b_ok && xa + 1 == nx && oxp;
+    const bool f_ym = a_ok && y == 1 && oym;
+    const bool f_yp = a_ok && y == ny && oyp;
+
+    // LDS slots of this thread's four writes per plane (own x cells, halo
+    // values).  A write with nothing to store goes to column 0, which no
+    // thread reads, so the writes need no branch.
+    const int lds_a = a_ok ? (ly + 1) * LW + 2 * lx + 2 : 0;
+    const int lds_b = b_ok ? (ly + 1) * LW + 2 * lx + 3 : 0;
+    const int lds_h0 = (role <= 3 && hv0) ? hrow * LW + hcol : 0;
+    const int lds_h1 = (role <= 1 && hv1) ? hrow * LW + hcol + 1 : 0;
+
     const int zf = it.z0 + 1;                     // first plane of the tile
     const int zl = it.z0 + it.zlen;               // last plane of the tile
-    // Register rings: own cells of plane p in slot (p - zf) mod 4 (planes
-    // z-1 .. z+2 live at step z), halo and source of plane p in slot
-    // (p - zf) mod 2.  Every load lands in the slot it is consumed from, so
-    // no register is copied while its load is in flight (such a copy
+    // Register rings of 4 slots: own cells, halo and source of plane p in
+    // slot (p - zf) mod 4.  At step z the loads of plane z + 2 are issued
+    // (own cells of z - 1 .. z + 2 are live), so every value has two
+    // plane steps to arrive.  Every load lands in the slot it is consumed
+    // from: no register is copied while its load is in flight (such a copy
     // waits for every outstanding load).
-    C ra[4], rb[4], ha[2], hb[2], sa_[2], sb_[2];
+    C ra[4], rb[4], ha[4], hb[4], sa_[4], sb_[4];
+    const int zf1 = min(zf + 1, zl);
     own_at(zf - 1, ra[3], rb[3]);
     own_at(zf, ra[0], rb[0]);
     own_at(zf + 1, ra[1], rb[1]);
     Tr<T>::ld(hbase + (int64_t)zf * hstride, ha[0], hb[0]);
-    sa_[0] = sa_[1] = sb_[0] = sb_[1] = C(0);
-    if (SRC)
+    Tr<T>::ld(hbase + (int64_t)zf1 * hstride, ha[1], hb[1]);
+    for (int k = 0; k < 4; ++k)
+        sa_[k] = sb_[k] = C(0);
+    if (SRC) {
         Tr<T>::ld(sown + (int64_t)zf * plane, sa_[0], sb_[0]);
+        Tr<T>::ld(sown + (int64_t)zf1 * plane, sa_[1], sb_[1]);
+    }
 
     double acc = 0.0;
     // one plane; K = (z - zf) mod 4, a compile-time slot number
@@ -362,27 +453,21 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         constexpr int K = decltype(kc)::value;
         constexpr int SM = (K + 3) & 3, SC = K, SP = (K + 1) & 3, SQ = (K + 2) & 3;
         static_assert(K >= 0 && K < 4, "ring slot");
-        constexpr int HC = K & 1, HN = (K + 1) & 1;
-        // the next planes go in flight first; the last step re-reads planes
-        // it already holds (cache hits) instead of branching
-        const int zn = min(z + 1, zl);
+        constexpr int HC = K & 1;                 // LDS buffer of this plane
+        // plane z + 2 goes in flight first; the last steps re-read planes
+        // they already hold (cache hits) instead of branching
+        const int zh = min(z + 2, zl);
         own_at(min(z + 2, zl + 1), ra[SQ], rb[SQ]);
-        Tr<T>::ld(hbase + (int64_t)zn * hstride, ha[HN], hb[HN]);
+        Tr<T>::ld(hbase + (int64_t)zh * hstride, ha[SQ], hb[SQ]);
         if (SRC)
-            Tr<T>::ld(sown + (int64_t)zn * plane, sa_[HN], sb_[HN]);
+            Tr<T>::ld(sown + (int64_t)zh * plane, sa_[SQ], sb_[SQ]);
         const C c_a = ra[SC], c_b = rb[SC];
         C (*L)[LW] = S[HC];
-        if (a_ok) {
-            L[ly + 1][2 * lx + 2] = c_a;
-            if (b_ok)
-                L[ly + 1][2 * lx + 3] = c_b;
-        }
-        if (role <= 1) {
-            if (hv0) L[hrow][hcol] = ha[HC];
-            if (hv1) L[hrow][hcol + 1] = hb[HC];
-        } else if (role <= 3 && hv0) {
-            L[hrow][hcol] = hcomp ? hb[HC] : ha[HC];
-        }
+        C* const Lf = &S[HC][0][0];
+        Lf[lds_a] = c_a;
+        Lf[lds_b] = c_b;
+        Lf[lds_h0] = hcomp ? hb[SC] : ha[SC];
+        Lf[lds_h1] = hb[SC];
         __syncthreads();
         const C xm_a = L[ly + 1][2 * lx + 1];
         const C xp_a = b_ok ? c_b : L[ly + 1][2 * lx + 3];
@@ -396,7 +481,7 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         sb = sb + L[ly + 2][2 * lx + 3];
         sb = sb + rb[SM];
         sb = sb + rb[SP];
-        const C s_a = sa_[HC], s_b = sb_[HC];
+        const C s_a = sa_[SC], s_b = sb_[SC];
         if (RES) {
             const C r_a = SRC ? (s_a + sa) - six * c_a : sa - six * c_a;
             const C r_b = SRC ? (s_b + sb) - six * c_b : sb - six * c_b;
@@ -413,31 +498,32 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
             }
         }
         if (STORE) {
-            const C va = SRC ? div6(sa + s_a) : div6(sa);
+            C va, vb;
+            if (SRC)
+                div6_pair(sa + s_a, sb + s_b, va, vb);
+            else
+                div6_pair(sa, sb, va, vb);
             // past the last cell of a row the pair's second slot is the
             // x = nx + 1 ghost: write back the value it already holds
-            const C vb = b_ok ? (SRC ? div6(sb + s_b) : div6(sb)) : c_b;
+            vb = b_ok ? vb : c_b;
+            const auto pk = Tr<T>::pack(va, vb);
             if (a_ok)
-                Tr<T>::stn(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, va, vb);
+                Tr<T>::stpn(dst + (int64_t)z * plane + (int64_t)y * pitch + xa, pk);
             if (FUSED) {
-                const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
-                const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
-                const int64_t zfi = (int64_t)(y - 1) * ldy + (xa - 1);
-                T* oxm = F::gout(B, XM, p ^ 1);
-                T* oxp = F::gout(B, XP, p ^ 1);
-                T* oym = F::gout(B, YM, p ^ 1);
-                T* oyp = F::gout(B, YP, p ^ 1);
-                T* ozm = F::gout(B, ZM, p ^ 1);
-                T* ozp = F::gout(B, ZP, p ^ 1);
                 // a face row's padding slot takes the second value of a
                 // pair that ends past the face (ld is even)
-                if (a_ok && xa == 1 && oxm) Tr<T>::st1(oxm + xfi, va);
-                if (a_ok && xa == nx && oxp) Tr<T>::st1(oxp + xfi, va);
-                if (b_ok && xa + 1 == nx && oxp) Tr<T>::st1(oxp + xfi, vb);
-                if (a_ok && y == 1 && oym) Tr<T>::st(oym + yfi, va, vb);
-                if (a_ok && y == ny && oyp) Tr<T>::st(oyp + yfi, va, vb);
-                if (a_ok && z == 1 && ozm) Tr<T>::st(ozm + zfi, va, vb);
-                if (a_ok && z == nz && ozp) Tr<T>::st(ozp + zfi, va, vb);
+                const int64_t zfi = (int64_t)(y - 1) * ldy + (xa - 1);
+                if (z == 1 && ozm && a_ok) Tr<T>::stp(ozm + zfi, pk);
+                if (z == nz && ozp && a_ok) Tr<T>::stp(ozp + zfi, pk);
+                if (xy_tile) {
+                    const int64_t xfi = (int64_t)(z - 1) * ldx + (y - 1);
+                    const int64_t yfi = (int64_t)(z - 1) * ldy + (xa - 1);
+                    if (f_xm) Tr<T>::st1a(oxm + xfi, pk);
+                    if (f_xpa) Tr<T>::st1a(oxp + xfi, pk);
+                    if (f_xpb) Tr<T>::st1b(oxp + xfi, pk);
+                    if (f_ym) Tr<T>::stp(oym + yfi, pk);
+                    if (f_yp) Tr<T>::stp(oyp + yfi, pk);
+                }
             }
         }
     };
