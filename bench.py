@@ -48,7 +48,7 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--workload", default="512_2x2x2", choices=sorted(WORKLOADS) + ["refine", "serve", "768_grids"])
     ap.add_argument("--ir-edge", type=int, default=1024, help="refine: grid edge of the per-sweep rates")
     ap.add_argument("--ir-sweeps", type=int, default=100, help="refine: sweeps timed per precision")

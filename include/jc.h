@@ -305,8 +305,9 @@ int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 
 /* Time `reps` sweeps of every candidate shape (tile_x in {64, 32} x
  * tile_y in {4,8,16,32} x z_chunk in {16, 32, 64, ..., depth}) on the
- * bound stream and keep the fastest; out = {tile_x, tile_y, z_chunk,
- * microseconds per sweep}.  The trial sweeps write only the other
+ * bound stream after at least 150 ms of warm-up sweeps, time the four
+ * fastest again in turn over three rounds and keep the fastest of those; out = {tile_x, tile_y,
+ * z_chunk, microseconds per sweep}.  The trial sweeps write only the other
  * ping-pong copy and face slot, so the current iterate and iteration count
  * are unchanged.  Waits for the stream.  Needs a loaded context. */
 int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);

@@ -1216,62 +1216,91 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
     for (int z = kMinZChunk; z < maxz; z *= 2)
         zcs.push_back(z);
     zcs.push_back((int)maxz);
+    struct Shape {
+        int x, y, z;
+        double ms;
+    };
+    std::vector<Shape> cand;
+    for (int xw : {64, 32})
+        for (int t : kTileYCandidates)
+            for (int z : zcs)
+                if (items_for(c, xw, t, z) <= c->max_items)
+                    cand.push_back({xw, t, z, 0.0});
+    if (cand.empty())
+        return fail(JC_ERR_INVALID, "no tile shape fits the work-list region");
+
     hipEvent_t e0 = nullptr, e1 = nullptr;
     JC_HIP(hipEventCreate(&e0));
     JC_HIP(hipEventCreate(&e1));
     const bool was_timing = c->timing;
     c->timing = false;
-    double best = -1;
-    int bx = c->tile_x, bt = c->tile_y, bz = c->z_chunk;
-    for (int xw : {64, 32})
-    for (int t : kTileYCandidates) {
-        for (int z : zcs) {
-            if (items_for(c, xw, t, z) > c->max_items)
-                continue;
-            st = jc_set_tiles(c, xw, t, z);
-            // trial sweeps read copy `parity` and write the other copy (and
-            // face slot parity ^ 1) without swapping: the iterate is unchanged
-            for (int rep = -1; rep < reps && st == JC_OK; ++rep) {
-                if (rep == 0)
-                    st = hipEventRecord(e0, c->stream) == hipSuccess ? JC_OK : JC_ERR_DEVICE;
-                if (st == JC_OK) {
-                    const hipError_t e = jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(),
-                                                          c->parity, c->tile_x, c->tile_y, fused, false, true,
-                                                          c->opt.with_source != 0, nullptr, c->stream);
-                    if (e != hipSuccess)
-                        st = fail(JC_ERR_DEVICE, std::string("autotune launch: ") + hipGetErrorString(e));
-                }
-            }
-            float ms = 0;
-            if (st == JC_OK && hipEventRecord(e1, c->stream) == hipSuccess &&
-                hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-                if (best < 0 || ms < best) {
-                    best = ms;
-                    bx = xw;
-                    bt = t;
-                    bz = z;
-                }
-            } else if (st == JC_OK) {
-                st = fail(JC_ERR_DEVICE, "autotune timing failed");
-            }
-            if (st != JC_OK)
-                break;
+    // trial sweeps read copy `parity` and write the other copy (and face
+    // slot parity ^ 1) without swapping: the iterate is unchanged
+    auto sweeps = [&](int n) -> int {
+        for (int i = 0; i < n; ++i) {
+            const hipError_t e = jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity,
+                                                  c->tile_x, c->tile_y, fused, false, true,
+                                                  c->opt.with_source != 0, nullptr, c->stream);
+            if (e != hipSuccess)
+                return fail(JC_ERR_DEVICE, std::string("autotune launch: ") + hipGetErrorString(e));
         }
-        if (st != JC_OK)
-            break;
+        return JC_OK;
+    };
+    // milliseconds of `n` sweeps of shape s after one untimed sweep
+    auto time_shape = [&](Shape& s, int n, double& ms) -> int {
+        int r = jc_set_tiles(c, s.x, s.y, s.z);
+        if (r == JC_OK)
+            r = sweeps(1);
+        if (r == JC_OK && hipEventRecord(e0, c->stream) != hipSuccess)
+            r = fail(JC_ERR_DEVICE, "autotune event record failed");
+        if (r == JC_OK)
+            r = sweeps(n);
+        float t = 0;
+        if (r == JC_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            r = fail(JC_ERR_DEVICE, "autotune timing failed");
+        ms = t;
+        return r;
+    };
+    // The device needs on the order of 100 ms of sustained sweeps before
+    // their time settles (a cold start reads up to 8 % slow), so sweeps run
+    // for at least 150 ms first.  Every shape is then screened with `reps`
+    // sweeps, and the four fastest are timed again in turn over three
+    // rounds, so that drift during the search does not pick the winner.
+    double warm_total = 0;
+    for (int batch = 0; batch < 1000 && warm_total < 150.0 && st == JC_OK; ++batch) {
+        double ms = 0;
+        st = time_shape(cand[0], 8, ms);
+        warm_total += ms;
+    }
+    for (size_t i = 0; i < cand.size() && st == JC_OK; ++i)
+        st = time_shape(cand[i], reps, cand[i].ms);
+    if (st == JC_OK) {
+        std::stable_sort(cand.begin(), cand.end(), [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
+        cand.resize(std::min<size_t>(cand.size(), 4));
+        for (Shape& s : cand)
+            s.ms = 0;
+        for (int round = 0; round < 3 && st == JC_OK; ++round)
+            for (size_t i = 0; i < cand.size() && st == JC_OK; ++i) {
+                double ms = 0;
+                st = time_shape(cand[i], reps, ms);
+                cand[i].ms += ms;
+            }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->timing = was_timing;
     if (st != JC_OK)
         return st;
-    st = jc_set_tiles(c, bx, bt, bz);
+    const Shape best = *std::min_element(cand.begin(), cand.end(),
+                                         [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
+    st = jc_set_tiles(c, best.x, best.y, best.z);
     if (st != JC_OK)
         return st;
-    out[0] = bx;
-    out[1] = bt;
-    out[2] = bz;
-    out[3] = (int64_t)(best * 1000.0 / reps);     // microseconds per sweep
+    out[0] = best.x;
+    out[1] = best.y;
+    out[2] = best.z;
+    out[3] = (int64_t)(best.ms * 1000.0 / (3.0 * reps));     // microseconds per sweep
     return JC_OK;
 }
 
