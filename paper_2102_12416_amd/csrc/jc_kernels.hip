@@ -262,6 +262,13 @@ __device__ __forceinline__ void div6_pair(C sa, C sb, C& va, C& vb)
     }
 }
 
+// Planes of loads a sweep keeps in flight ahead of the plane it computes.
+// Three for binary64 fields: at one 16-wave work-group per CU (the 64 x 32
+// tile) two planes of 16-byte loads are too few bytes in flight to cover
+// the memory latency.  Two for the narrower types, where the extra
+// registers would cost a resident work-group.
+template <typename T> constexpr int prefetch_planes() { return sizeof(T) == 8 ? 3 : 2; }
+
 // One work-group sweeps a tile of 2 TXP x cells (64 or 32) by TY rows of
 // one block, marching along z.  Each thread owns two adjacent x cells of one row
 // (one aligned-pair load per plane: cell x = 1 of every row starts a
@@ -427,37 +434,43 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
 
     const int zf = it.z0 + 1;                     // first plane of the tile
     const int zl = it.z0 + it.zlen;               // last plane of the tile
-    // Register rings of 4 slots: own cells, halo and source of plane p in
-    // slot (p - zf) mod 4.  At step z the loads of plane z + 2 are issued
-    // (own cells of z - 1 .. z + 2 are live), so every value has two
-    // plane steps to arrive.  Every load lands in the slot it is consumed
-    // from: no register is copied while its load is in flight (such a copy
-    // waits for every outstanding load).
-    C ra[4], rb[4], ha[4], hb[4], sa_[4], sb_[4];
-    const int zf1 = min(zf + 1, zl);
-    own_at(zf - 1, ra[3], rb[3]);
-    own_at(zf, ra[0], rb[0]);
-    own_at(zf + 1, ra[1], rb[1]);
-    Tr<T>::ld(hbase + (int64_t)zf * hstride, ha[0], hb[0]);
-    Tr<T>::ld(hbase + (int64_t)zf1 * hstride, ha[1], hb[1]);
-    for (int k = 0; k < 4; ++k)
+    // Register rings of RS slots: own cells, halo and source of plane p in
+    // slot (p - zf) mod RS.  At step z the loads of plane z + PD are issued
+    // (own cells of z - 1 .. z + PD are live), so every value has PD plane
+    // steps to arrive.  Every load lands in the slot it is consumed from:
+    // no register is copied while its load is in flight (such a copy waits
+    // for every outstanding load).  RS is even so that the LDS buffer of a
+    // step (its slot's parity) alternates across the unrolled loop.
+    constexpr int PD = prefetch_planes<T>();
+    static_assert(PD >= 2 && PD <= 4, "prefetch distance 2..4 planes");
+    constexpr int RS = (PD + 3) & ~1;
+    C ra[RS], rb[RS], ha[RS], hb[RS], sa_[RS], sb_[RS];
+    own_at(zf - 1, ra[RS - 1], rb[RS - 1]);
+#pragma unroll
+    for (int k = 0; k < PD; ++k) {
+        own_at(min(zf + k, zl + 1), ra[k], rb[k]);
+        Tr<T>::ld(hbase + (int64_t)min(zf + k, zl) * hstride, ha[k], hb[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < RS; ++k)
         sa_[k] = sb_[k] = C(0);
     if (SRC) {
-        Tr<T>::ld(sown + (int64_t)zf * plane, sa_[0], sb_[0]);
-        Tr<T>::ld(sown + (int64_t)zf1 * plane, sa_[1], sb_[1]);
+#pragma unroll
+        for (int k = 0; k < PD; ++k)
+            Tr<T>::ld(sown + (int64_t)min(zf + k, zl) * plane, sa_[k], sb_[k]);
     }
 
     double acc = 0.0;
-    // one plane; K = (z - zf) mod 4, a compile-time slot number
+    // one plane; K = (z - zf) mod RS, a compile-time slot number
     auto step = [&](int z, auto kc) {
         constexpr int K = decltype(kc)::value;
-        constexpr int SM = (K + 3) & 3, SC = K, SP = (K + 1) & 3, SQ = (K + 2) & 3;
-        static_assert(K >= 0 && K < 4, "ring slot");
+        constexpr int SM = (K + RS - 1) % RS, SC = K, SP = (K + 1) % RS, SQ = (K + PD) % RS;
+        static_assert(K >= 0 && K < RS, "ring slot");
         constexpr int HC = K & 1;                 // LDS buffer of this plane
-        // plane z + 2 goes in flight first; the last steps re-read planes
+        // plane z + PD goes in flight first; the last steps re-read planes
         // they already hold (cache hits) instead of branching
-        const int zh = min(z + 2, zl);
-        own_at(min(z + 2, zl + 1), ra[SQ], rb[SQ]);
+        const int zh = min(z + PD, zl);
+        own_at(min(z + PD, zl + 1), ra[SQ], rb[SQ]);
         Tr<T>::ld(hbase + (int64_t)zh * hstride, ha[SQ], hb[SQ]);
         if (SRC)
             Tr<T>::ld(sown + (int64_t)zh * plane, sa_[SQ], sb_[SQ]);
@@ -527,20 +540,35 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
             }
         }
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    using I3 = std::integral_constant<int, 3>;
+#define JC_STEP(k) step(z + (k), std::integral_constant<int, (k)>{})
     int z = zf;
-    for (; z + 3 <= zl; z += 4) {
-        step(z, I0{});
-        step(z + 1, I1{});
-        step(z + 2, I2{});
-        step(z + 3, I3{});
+    if constexpr (RS == 4) {
+        for (; z + 3 <= zl; z += 4) {
+            JC_STEP(0);
+            JC_STEP(1);
+            JC_STEP(2);
+            JC_STEP(3);
+        }
+        if (z <= zl) JC_STEP(0);
+        if (z + 1 <= zl) JC_STEP(1);
+        if (z + 2 <= zl) JC_STEP(2);
+    } else {
+        static_assert(RS == 6, "ring of 4 or 6 slots");
+        for (; z + 5 <= zl; z += 6) {
+            JC_STEP(0);
+            JC_STEP(1);
+            JC_STEP(2);
+            JC_STEP(3);
+            JC_STEP(4);
+            JC_STEP(5);
+        }
+        if (z <= zl) JC_STEP(0);
+        if (z + 1 <= zl) JC_STEP(1);
+        if (z + 2 <= zl) JC_STEP(2);
+        if (z + 3 <= zl) JC_STEP(3);
+        if (z + 4 <= zl) JC_STEP(4);
     }
-    if (z <= zl) step(z, I0{});
-    if (z + 1 <= zl) step(z + 1, I1{});
-    if (z + 2 <= zl) step(z + 2, I2{});
+#undef JC_STEP
     if (RES) {
         const double w = wave_sum(acc);
         if ((t & 63) == 0)

@@ -256,15 +256,22 @@ def test_kernel_timing_counts():
 
 # --------------------------------------------------------- full-size cases
 
-def test_512_decomposed_full_size():
-    """512^3 as 2x2x2 blocks of 256^3, the benchmarked launch configuration:
-    sampled cells after 6 iterations equal the oracle's local computation;
-    1000 iterations equal the single-block run bit for bit and obey the
-    maximum principle."""
+@pytest.mark.parametrize("mode", ["fused", "staged"])
+def test_512_decomposed_full_size(mode):
+    """512^3 as 2x2x2 blocks of 256^3 in the launch configuration the
+    benchmark times for each mode (its stored tile shape): sampled cells
+    after 6 iterations equal the oracle's local computation; 1000
+    iterations equal the single-block run bit for bit and obey the maximum
+    principle."""
+    from bench import TUNED_TILES
     n = (512, 512, 512)
-    say("512^3 2x2x2 sampled + bitwise vs single block")
+    tx, ty, zc = TUNED_TILES[("512_2x2x2", mode)]
+    say("512^3 2x2x2", mode, "tile", tx, ty, zc, "sampled + bitwise vs single block")
     u0 = synth.boundary_field(n, seed=12416)
-    with Solver(n, block_dims=(256, 256, 256), mode="staged") as s:
+    with Solver(n, block_dims=(256, 256, 256), mode=mode, use_graphs=False, tile_x=tx, tile_y=ty,
+                z_chunk=zc) as s:
+        ti = s.tile_info()
+        assert (ti["tile_x"], ti["tile_y"], ti["z_chunk"]) == (tx, ty, zc)
         s.load(u0)
         s.iterate(6)
         got = s.store().cpu().numpy()
@@ -293,7 +300,8 @@ def test_768_overdecomposed_full_size(variant):
     u0 = synth.boundary_field(n, seed=12416)
     kw = dict(block_dims=(96, 96, 96)) if variant == "uniform" else \
         dict(cuts=[synth.uneven_cuts(768, 32, 160, seed=12416, axis=a) for a in range(3)])
-    with Solver(n, mode="fused", **kw) as s:
+    # the shape jc_autotune keeps for these workloads at start-up
+    with Solver(n, mode="fused", tile_x=32, tile_y=32, z_chunk=16, **kw) as s:
         s.load(u0)
         s.iterate(500)
         dec = s.store().cpu().numpy()
