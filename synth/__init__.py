@@ -167,3 +167,27 @@ def serving_requests(count: int, rate_per_s: float, seed: int = DEFAULT_SEED,
     return [dict(id=i, arrival=float(arrivals[i]), n=int(edges[i]),
                  precision=("f32" if mixed[i] else "f64"), seed=int(seed) + 1000 + i)
             for i in range(count)]
+
+
+def field_box(n, kind: int, lo, hi, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """The box ``lo <= (z, y, x) < hi`` (padded indices) of the padded
+    initial iterate (kind 0: shell g, interior 0) or of the source (kind 1:
+    interior b, shell 0), drawn by global flat index, so a box of a large
+    grid needs no whole-field array."""
+    P, R, C = _padded_shape(n)
+    if kind not in (0, 1):
+        raise ValueError("kind is 0 (boundary) or 1 (source)")
+    lo = [int(v) for v in lo]
+    hi = [int(v) for v in hi]
+    if any(l < 0 or h > m or l >= h for l, h, m in zip(lo, hi, (P, R, C))):
+        raise ValueError("box outside the padded grid")
+    z = np.arange(lo[0], hi[0], dtype=np.uint64)[:, None, None]
+    y = np.arange(lo[1], hi[1], dtype=np.uint64)[None, :, None]
+    x = np.arange(lo[2], hi[2], dtype=np.uint64)[None, None, :]
+    idx = (z * np.uint64(R) + y) * np.uint64(C) + x
+    shell = ((z == 0) | (z == P - 1) | (y == 0) | (y == R - 1) | (x == 0) | (x == C - 1))
+    if kind == 0:
+        v = uniform01(seed, STREAM_BOUNDARY, idx.ravel()).reshape(idx.shape)
+        return np.where(shell, v, 0.0)
+    v = 2.0 * uniform01(seed, STREAM_SOURCE, idx.ravel()).reshape(idx.shape) - 1.0
+    return np.where(shell, 0.0, v)

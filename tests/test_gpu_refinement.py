@@ -75,3 +75,95 @@ def test_ir_certified_to_tolerance(dtype):
     err = np.max(np.abs(u - u64)) / np.max(np.abs(u64))
     print("[result] %s max rel error vs binary64 refinement: %.3e" % (dtype, err), flush=True)
     assert err < 1e-6
+
+
+# ----------------------------------------------------------- full size 1024^3
+
+def _box(n, cell, radius):
+    P = (n[2] + 2, n[1] + 2, n[0] + 2)
+    lo = [max(0, c - radius) for c in cell]
+    hi = [min(P[a], cell[a] + radius + 1) for a in range(3)]
+    return lo, hi
+
+
+def _ir_local_oracle(n, seed, cell, dtype, inner):
+    """u after one outer step of `inner` sweeps at one cell: the oracle's
+    refinement on the box of radius inner + 2 around it.  The box edge
+    holds the exact initial iterate (so the residual is exact) and zero
+    corrections, whose error moves one cell per inner sweep and never
+    reaches the centre."""
+    lo, hi = _box(n, cell, inner + 2)
+    u_box = synth.field_box(n, 0, lo, hi, seed=seed)
+    b_box = synth.field_box(n, 1, lo, hi, seed=seed)
+    ref, _, done, _ = oracle.c_ir_solve(u_box, b_box, storage=dtype, inner=inner, rtol=0.0, max_inner=inner)
+    assert done == inner
+    return ref[cell[0] - lo[0], cell[1] - lo[1], cell[2] - lo[2]]
+
+
+def _plain_local_oracle(n, seed, cell, k):
+    """Iterate k of the plain sweep with a source at one cell, from the box
+    of radius k + 1 around it."""
+    lo, hi = _box(n, cell, k + 1)
+    box = synth.field_box(n, 0, lo, hi, seed=seed)
+    bb = synth.field_box(n, 1, lo, hi, seed=seed)
+    for _ in range(k):
+        box = oracle.sweep(box, bb)
+    return box[cell[0] - lo[0], cell[1] - lo[1], cell[2] - lo[2]]
+
+
+_CELLS_1024 = [(1, 1, 1), (1024, 1024, 1024), (1, 512, 1024), (1024, 1, 513), (512, 512, 512),
+               (513, 1024, 1), (2, 700, 31), (900, 33, 1023)]
+
+
+def _sample(u, cells):
+    import torch
+    idx = torch.tensor(cells, device=u.device)
+    return u[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+
+
+def _cells_1024():
+    rng = np.random.default_rng(1024)
+    return _CELLS_1024 + [tuple(int(v) for v in rng.integers(1, 1025, 3)) for _ in range(6)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_ir_full_size_1024_sampled(dtype):
+    """1024^3 with a source in the launch configuration of the refinement
+    benchmark (one block, default tile, eager launches): one outer step of
+    50 inner sweeps; sampled cells equal the oracle's local refinement bit
+    for bit."""
+    from paper_2102_12416_amd import synth_field
+    n, seed = (1024, 1024, 1024), 12416
+    say("IR 1024^3", dtype, "one outer step, sampled")
+    cells = _cells_1024()
+    with Solver(n, with_source=True, ir_dtype=dtype, use_graphs=False) as s:
+        g = synth_field(n, seed, 0)
+        b = synth_field(n, seed, 1)
+        # the device generator draws the input module's values
+        lo, hi = [0, 500, 1000], [3, 530, 1026]
+        assert np.array_equal(g[0:3, 500:530, 1000:1026].cpu().numpy(), synth.field_box(n, 0, lo, hi, seed=seed))
+        assert np.array_equal(b[0:3, 500:530, 1000:1026].cpu().numpy(), synth.field_box(n, 1, lo, hi, seed=seed))
+        s.load(g, b)
+        del g, b
+        info = s.solve_ir(inner=50, rtol=0.0, max_inner=50)
+        got = _sample(s.store(), cells)
+    assert info["iters"] == 50 and not info["converged"]
+    for c, v in zip(cells, got):
+        assert v == _ir_local_oracle(n, seed, c, dtype, 50), c
+
+
+def test_plain_source_full_size_1024_sampled():
+    """The binary64 sweep with a source at 1024^3 as the refinement
+    benchmark times it (tile from jc_autotune, eager launches): sampled cells
+    after 6 sweeps equal the oracle's local computation bit for bit."""
+    from paper_2102_12416_amd import synth_field
+    n, seed = (1024, 1024, 1024), 12416
+    say("plain with source 1024^3, sampled")
+    cells = _cells_1024()
+    with Solver(n, with_source=True, use_graphs=False) as s:
+        s.load(synth_field(n, seed, 0), synth_field(n, seed, 1))
+        s.autotune(reps=2)
+        s.iterate(6)
+        got = _sample(s.store(), cells)
+    for c, v in zip(cells, got):
+        assert v == _plain_local_oracle(n, seed, c, 6), c

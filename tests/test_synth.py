@@ -1,5 +1,6 @@
 """The seeded input recipe (CPU only)."""
 import numpy as np
+import pytest
 
 import synth
 
@@ -77,3 +78,21 @@ def test_serving_requests_recipe():
     t = np.array([r["arrival"] for r in reqs])
     assert np.all(np.diff(t) >= 0) and t[0] == 0.0
     assert {r["precision"] for r in reqs} == {"f32", "f64"}
+
+
+@pytest.mark.parametrize("n", [(7, 5, 4), (16, 9, 12)])
+def test_field_box_is_a_slice_of_the_whole_field(n):
+    g = synth.boundary_field(n, seed=77)
+    b = synth.source_field(n, seed=77)
+    P = g.shape
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        lo = [int(rng.integers(0, P[a] - 1)) for a in range(3)]
+        hi = [int(rng.integers(lo[a] + 1, P[a] + 1)) for a in range(3)]
+        sl = tuple(slice(l, h) for l, h in zip(lo, hi))
+        assert np.array_equal(synth.field_box(n, 0, lo, hi, seed=77), g[sl])
+        assert np.array_equal(synth.field_box(n, 1, lo, hi, seed=77), b[sl])
+    full = [0, 0, 0], list(P)
+    assert np.array_equal(synth.field_box(n, 0, *full, seed=77), g)
+    with pytest.raises(ValueError):
+        synth.field_box(n, 0, [0, 0, 0], [P[0] + 1, P[1], P[2]])
