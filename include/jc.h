@@ -94,7 +94,8 @@ typedef struct jc_options {
     int z_chunk;         /* planes per tile; 0 = auto */
     int use_graphs;      /* 1: capture jc_iterate windows as HIP graphs */
     int debug_epochs;    /* reserved, must be 0 */
-    int tile_x;          /* cells per tile row: 32 or 64; 0 = auto (fewest idle lanes) */
+    int tile_x;          /* cells per tile row: 16, 32 or 64 (16 needs tile_y >= 8 or
+                            auto); 0 = auto (64, or 32 where it idles fewer lanes) */
     int exchange;        /* JC_EXCHANGE_DEVICE (default), _HOST or _METADATA */
 } jc_options;
 
@@ -238,8 +239,8 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * ctxs is read during the call; the contexts must outlive the group and
  * must not be used on their own streams while the group exists.
  * flags: bit 0 = capture jc_group_iterate windows as HIP graphs (needs a
- * non-null stream).  tile: {cells per row 32|64, rows 4|8|16|32, planes
- * >= 1} for every launch of the group, or NULL for {64, 8, 32}; members'
+ * non-null stream).  tile: {cells per row 16|32|64, rows 4|8|16|32 (at
+ * least 8 for 16-cell rows), planes >= 1} for every launch of the group, or NULL for {64, 8, 32}; members'
  * results do not depend on it, their residual norms do in the last bits,
  * so compare mixes within one tile shape.  Host only until jc_group_bind. */
 int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, const int tile[3],
@@ -295,19 +296,20 @@ int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed
 
 /* ---- tile shape ------------------------------------------------------ */
 
-/* Set the sweep's tile shape: tile_x cells per row (32 or 64), tile_y
- * rows (4, 8, 16 or 32) and z_chunk planes per work item (>= 1, within
+/* Set the sweep's tile shape: tile_x cells per row (16, 32 or 64), tile_y
+ * rows (4, 8, 16 or 32; at least 8 with 16-cell rows, so that a work-group
+ * is whole 64-lane waves) and z_chunk planes per work item (>= 1, within
  * the work-list region sized at creation: >= 16 always fits).  Results
  * are bitwise independent of the shape; residual norms change in the last
  * bits (reduction order).  Uploads the new work list (waits for the stream
  * when bound). */
 int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 
-/* Time `reps` sweeps of every candidate shape (tile_x in {64, 32} x
- * tile_y in {4,8,16,32} x z_chunk in {16, 32, 64, ..., depth}) on the
- * bound stream after at least 150 ms of warm-up sweeps, time the four
- * fastest again in turn over three rounds and keep the fastest of those; out = {tile_x, tile_y,
- * z_chunk, microseconds per sweep}.  The trial sweeps write only the other
+/* Time `reps` sweeps of every valid candidate shape (tile_x in {64, 32,
+ * 16} x tile_y in {4, 8, 16, 32} x z_chunk in {16, 32, 64, ..., depth}) on
+ * the bound stream after at least 150 ms of warm-up sweeps, time the four
+ * fastest again in turn over three rounds and keep the fastest of those;
+ * out = {tile_x, tile_y, z_chunk, microseconds per sweep}.  The trial sweeps write only the other
  * ping-pong copy and face slot, so the current iterate and iteration count
  * are unchanged.  Waits for the stream.  Needs a loaded context. */
 int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);

@@ -60,7 +60,20 @@ struct HostPair {
 // Bytes of one element of the refinement storage format.
 inline size_t lo_size(int dtype) { return dtype == JC_F64 ? 8 : dtype == JC_F32 ? 4 : 2; }
 
+constexpr int kTileXCandidates[] = {64, 32, 16};
 constexpr int kTileYCandidates[] = {4, 8, 16, 32};
+
+// A tile is 16, 32 or 64 cells wide (two per thread) and 4..32 rows; a
+// work-group is whole 64-lane waves, so a 16-cell tile needs 8 rows.
+inline bool tile_shape_ok(int tile_x, int tile_y)
+{
+    bool ok_x = false, ok_y = false;
+    for (int x : kTileXCandidates)
+        ok_x = ok_x || x == tile_x;
+    for (int y : kTileYCandidates)
+        ok_y = ok_y || y == tile_y;
+    return ok_x && ok_y && (tile_x / 2) * tile_y >= 64;
+}
 constexpr int kMinZChunk = 16;
 
 }  // namespace jc_rt

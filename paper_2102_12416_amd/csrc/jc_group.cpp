@@ -188,10 +188,9 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
     }
     if (tile) {
-        const bool ok = (tile[0] == 32 || tile[0] == 64) &&
-                        (tile[1] == 4 || tile[1] == 8 || tile[1] == 16 || tile[1] == 32) && tile[2] >= 1;
+        const bool ok = jc_rt::tile_shape_ok(tile[0], tile[1]) && tile[2] >= 1;
         if (!ok)
-            return fail(JC_ERR_INVALID, "group tile must be {32|64, 4|8|16|32, >= 1}");
+            return fail(JC_ERR_INVALID, "group tile must be {16|32|64, 4|8|16|32 (>= 8 for 16), >= 1}");
     }
     jc_group* g = new (std::nothrow) jc_group();
     if (!g)

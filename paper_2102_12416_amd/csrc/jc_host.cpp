@@ -121,8 +121,10 @@ int validate_options(const jc_options* opt)
         return fail(JC_ERR_INVALID, "host-staged or metadata exchange needs the staged mode");
     if (opt->debug_epochs != 0)
         return fail(JC_ERR_INVALID, "options.debug_epochs is reserved and must be 0");
-    if (opt->tile_x != 0 && opt->tile_x != 32 && opt->tile_x != 64)
-        return fail(JC_ERR_INVALID, "options.tile_x must be 0, 32 or 64");
+    if (opt->tile_x != 0 && opt->tile_x != 16 && opt->tile_x != 32 && opt->tile_x != 64)
+        return fail(JC_ERR_INVALID, "options.tile_x must be 0, 16, 32 or 64");
+    if (opt->tile_x == 16 && opt->tile_y == 4)
+        return fail(JC_ERR_INVALID, "a 16-cell tile needs options.tile_y of 8, 16 or 32 (whole waves)");
     if (opt->tile_y != 0) {
         bool ok = false;
         for (int t : kTileYCandidates)
@@ -227,7 +229,8 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
     default_tiles(c, &c->tile_x, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
-    c->max_items = std::max<int64_t>((int64_t)c->items.size(), items_for(c, 32, 4, kMinZChunk));
+    c->max_items = std::max<int64_t>({(int64_t)c->items.size(), items_for(c, 32, 4, kMinZChunk),
+                                      items_for(c, 16, 8, kMinZChunk)});
     if (c->max_items > (int64_t)1 << 30)
         return fail(JC_ERR_INVALID, "work list too long");
     // arena layout
@@ -1172,12 +1175,9 @@ int jc_set_tiles(jc_ctx* c, int tile_x, int tile_y, int z_chunk)
 {
     if (!c)
         return fail(JC_ERR_INVALID, "NULL context");
-    bool ok = tile_x == 32 || tile_x == 64;
-    bool oky = false;
-    for (int t : kTileYCandidates)
-        oky = oky || t == tile_y;
-    if (!ok || !oky || z_chunk < 1)
-        return fail(JC_ERR_INVALID, "tile_x must be 32 or 64, tile_y 4, 8, 16 or 32 and z_chunk >= 1");
+    if (!tile_shape_ok(tile_x, tile_y) || z_chunk < 1)
+        return fail(JC_ERR_INVALID, "tile_x must be 16, 32 or 64, tile_y 4, 8, 16 or 32 (at least 8 for "
+                                    "tile_x 16) and z_chunk >= 1");
     if (items_for(c, tile_x, tile_y, z_chunk) > c->max_items)
         return fail(JC_ERR_INVALID, "z_chunk too small for the work-list region");
     c->tile_x = tile_x;
@@ -1221,10 +1221,10 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
         double ms;
     };
     std::vector<Shape> cand;
-    for (int xw : {64, 32})
+    for (int xw : kTileXCandidates)
         for (int t : kTileYCandidates)
             for (int z : zcs)
-                if (items_for(c, xw, t, z) <= c->max_items)
+                if (tile_shape_ok(xw, t) && items_for(c, xw, t, z) <= c->max_items)
                     cand.push_back({xw, t, z, 0.0});
     if (cand.empty())
         return fail(JC_ERR_INVALID, "no tile shape fits the work-list region");

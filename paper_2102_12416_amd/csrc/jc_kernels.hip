@@ -269,7 +269,7 @@ __device__ __forceinline__ void div6_pair(C sa, C sb, C& va, C& vb)
 // registers would cost a resident work-group.
 template <typename T> constexpr int prefetch_planes() { return sizeof(T) == 8 ? 3 : 2; }
 
-// One work-group sweeps a tile of 2 TXP x cells (64 or 32) by TY rows of
+// One work-group sweeps a tile of 2 TXP x cells (64, 32 or 16) by TY rows of
 // one block, marching along z.  Each thread owns two adjacent x cells of one row
 // (one aligned-pair load per plane: cell x = 1 of every row starts a
 // 128-byte line).  Per plane the work-group writes the plane -- its cells
@@ -616,7 +616,12 @@ hipError_t sweep_rows(const BlockDesc* blocks, const Item* items, int nitems, in
                       bool fused, bool resid, bool store, double* partials, hipStream_t s)
 {
     switch (tile_y) {
-    case 4: return sweep_flags<T, FIELD, TXP, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 4:
+        // a 16-cell tile needs 8 rows for whole waves
+        if constexpr (TXP * 4 >= 64)
+            return sweep_flags<T, FIELD, TXP, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+        else
+            return hipErrorInvalidValue;
     case 8: return sweep_flags<T, FIELD, TXP, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
     case 16: return sweep_flags<T, FIELD, TXP, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
     case 32: return sweep_flags<T, FIELD, TXP, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
@@ -629,6 +634,7 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
                        bool fused, bool resid, bool store, double* partials, hipStream_t s)
 {
     switch (tile_x) {
+    case 16: return sweep_rows<T, FIELD, 8, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
     case 32: return sweep_rows<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
     case 64: return sweep_rows<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
     default: return hipErrorInvalidValue;

@@ -39,6 +39,7 @@ def create(grid, bd, **kw):
     opt.ir_dtype = L.JC_NONE
     opt.tile_y = kw.get("tile_y", 0)
     opt.z_chunk = kw.get("z_chunk", 0)
+    opt.tile_x = kw.get("tile_x", 0)
     ctx = ctypes.c_void_p()
     st = L.lib.jc_create(L.i64(grid), L.i64(bd), ctypes.byref(opt), ctypes.byref(ctx))
     return st, ctx
@@ -275,6 +276,23 @@ def test_set_tiles_validation_and_items():
     check(L.lib.jc_set_tiles(ctx, 32, 4, 96))
     check(L.lib.jc_tile_info(ctx, out))
     assert tuple(out) == (32, 4, 96, 2 * 4 * 25 * 1)
+    # 16-cell rows: whole waves need at least 8 rows
+    assert L.lib.jc_set_tiles(ctx, 16, 4, 16) == L.JC_ERR_INVALID
+    check(L.lib.jc_set_tiles(ctx, 16, 8, 16))
+    check(L.lib.jc_tile_info(ctx, out))
+    # the finest shapes the tuner may pick fit the work-list region
+    assert tuple(out) == (16, 8, 16, 2 * 7 * 13 * 6)
+    L.lib.jc_destroy(ctx)
+
+
+def test_sixteen_cell_tile_options():
+    st, ctx = create((40, 24, 24), (40, 24, 24), tile_x=16, tile_y=4)
+    assert st == L.JC_ERR_INVALID
+    st, ctx = create((40, 24, 24), (40, 24, 24), tile_x=16)
+    assert st == 0
+    out = (ctypes.c_int64 * 4)()
+    check(L.lib.jc_tile_info(ctx, out))
+    assert out[0] == 16 and out[1] >= 8
     L.lib.jc_destroy(ctx)
 
 

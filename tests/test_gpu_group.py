@@ -85,7 +85,7 @@ def test_group_matches_own_path_and_oracle():
 def test_group_tile_shape_keeps_results():
     say("group tile shapes")
     ref, _ = run([0, 2, 3])
-    for tile in ((32, 4, 16), (64, 32, 7)):
+    for tile in ((32, 4, 16), (64, 32, 7), (16, 8, 16)):
         solvers = [make(SPECS[i], seed=100 + i) for i in (0, 2, 3)]
         with Group(solvers, tile=tile) as g:
             for _ in range(4):

@@ -163,7 +163,8 @@ def test_staged_state_machine():
 
 
 @pytest.mark.parametrize("tile_x,tile_y,z_chunk", [(64, 4, 16), (64, 8, 0), (64, 16, 7), (64, 32, 0), (64, 4, 33),
-                                                   (32, 4, 16), (32, 8, 5), (32, 16, 0), (32, 32, 33)])
+                                                   (32, 4, 16), (32, 8, 5), (32, 16, 0), (32, 32, 33),
+                                                   (16, 8, 16), (16, 16, 7), (16, 32, 0)])
 @pytest.mark.parametrize("mode", ["staged", "fused"])
 def test_tile_shapes_bitwise(tile_x, tile_y, z_chunk, mode):
     say("tile", tile_x, tile_y, z_chunk, mode)

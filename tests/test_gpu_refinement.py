@@ -167,3 +167,22 @@ def test_plain_source_full_size_1024_sampled():
         got = _sample(s.store(), cells)
     for c, v in zip(cells, got):
         assert v == _plain_local_oracle(n, seed, c, 6), c
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_ir_sixteen_cell_tiles_match_oracle(dtype):
+    """The refinement passes with 16-cell tiles (8 threads per row) equal
+    the oracle's refinement bit for bit."""
+    n, bd = (37, 29, 23), (19, 15, 23)
+    say("IR 16-cell tiles", dtype)
+    u0 = synth.boundary_field(n, seed=31)
+    b = synth.source_field(n, seed=31)
+    ref, _, done, _ = oracle.c_ir_solve(u0, b, storage=dtype, inner=20, rtol=0.0, max_inner=200)
+    with Solver(n, block_dims=bd, mode="fused", with_source=True, ir_dtype=dtype, tile_x=16, tile_y=8,
+                z_chunk=16) as s:
+        assert s.tile_info()["tile_x"] == 16
+        s.load(u0, b)
+        info = s.solve_ir(inner=20, rtol=0.0, max_inner=200)
+        u = s.store().cpu().numpy()
+    assert info["iters"] == done == 200
+    assert np.array_equal(u, ref)
