@@ -48,6 +48,7 @@ struct HostBlock {
     size_t u_off[2], b_off; // byte offsets of element (0,0,0)'s line base
     int64_t lpitch, lplane; // refinement arrays (d, r_lo)
     size_t d_off[2], rlo_off;
+    size_t xg_off[2];       // compact Dirichlet ghost column of face XM / XP (unpaired faces)
 };
 
 struct HostPair {
@@ -101,6 +102,7 @@ struct jc_ctx {
     size_t off_blocks = 0, off_pairs = 0, off_items = 0, off_partials = 0, off_ranges = 0,
            off_result = 0, footprint = 0;
     size_t lo_begin = 0, lo_end = 0;   // refinement arrays and buffers
+    size_t lxg_off = 0;                 // zero ghost column of the correction (in the refinement region)
     // binding
     char* arena = nullptr;
     size_t arena_bytes = 0;

@@ -254,6 +254,19 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         p.buf_off[0] = off; off += bytes;
         p.buf_off[1] = off; off += bytes;
     }
+    // compact Dirichlet ghost columns of the unpaired x faces
+    int64_t max_xcol = 0;
+    for (HostBlock& b : c->blocks) {
+        const int64_t col = b.n[2] * jc::face_ld(b.n[1]);
+        for (int f = jc::XM; f <= jc::XP; ++f) {
+            b.xg_off[f] = 0;
+            if (b.pair_in[f] < 0) {
+                b.xg_off[f] = off;
+                off = align_up(off + sizeof(double) * (size_t)col, kAlign);
+                max_xcol = std::max(max_xcol, col);
+            }
+        }
+    }
     c->lo_begin = c->lo_end = off;
     if (c->opt.ir_enable) {
         const size_t es = lo_size(c->opt.ir_dtype);
@@ -271,6 +284,9 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
             p.lbuf_off[0] = off; off += bytes;
             p.lbuf_off[1] = off; off += bytes;
         }
+        // one zero column serves every unpaired x face of the correction
+        c->lxg_off = off;
+        off = align_up(off + es * (size_t)std::max<int64_t>(max_xcol, 1), kAlign);
         c->lo_end = off;
     }
     c->footprint = off;
@@ -795,6 +811,8 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
                                    ? reinterpret_cast<double*>(c->arena + c->pairs[hb.pair_out[f]].buf_off[s])
                                    : nullptr;
             }
+        for (int f = jc::XM; f <= jc::XP; ++f)
+            d.xg[f] = hb.pair_in[f] < 0 ? reinterpret_cast<const double*>(c->arena + hb.xg_off[f]) : nullptr;
         for (int a = 0; a < 3; ++a) {
             d.n[a] = (int32_t)hb.n[a];
             d.off[a] = (int32_t)hb.off[a];
@@ -814,6 +832,8 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
                     d.lgin[f][s] = hb.pair_in[f] >= 0 ? c->arena + c->pairs[hb.pair_in[f]].lbuf_off[s] : nullptr;
                     d.lgout[f][s] = hb.pair_out[f] >= 0 ? c->arena + c->pairs[hb.pair_out[f]].lbuf_off[s] : nullptr;
                 }
+            for (int f = jc::XM; f <= jc::XP; ++f)
+                d.lxg[f] = hb.pair_in[f] < 0 ? c->arena + c->lxg_off : nullptr;
         }
     }
     c->hpairs.assign(c->pairs.size(), PairDesc{});

@@ -179,6 +179,7 @@ template <typename T> struct Fld<T, FIELD_U> {
     __device__ static const T* source(const BlockDesc* B) { return B->b; }
     __device__ static const T* gin(const BlockDesc* B, int f, int s) { return B->gin[f][s]; }
     __device__ static T* gout(const BlockDesc* B, int f, int s) { return B->gout[f][s]; }
+    __device__ static const T* xg(const BlockDesc* B, int f) { return B->xg[f]; }
     __device__ static int64_t pitch(const BlockDesc* B) { return B->pitch; }
     __device__ static int64_t plane(const BlockDesc* B) { return B->plane; }
 };
@@ -192,6 +193,7 @@ template <typename T> struct Fld<T, FIELD_D> {
         return static_cast<const T*>(B->lgin[f][s]);
     }
     __device__ static T* gout(const BlockDesc* B, int f, int s) { return static_cast<T*>(B->lgout[f][s]); }
+    __device__ static const T* xg(const BlockDesc* B, int f) { return static_cast<const T*>(B->lxg[f]); }
     __device__ static int64_t pitch(const BlockDesc* B) { return B->lpitch; }
     __device__ static int64_t plane(const BlockDesc* B) { return B->lplane; }
 };
@@ -394,14 +396,18 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         const int ps = (hx & 1) ? hx : hx - 1;    // aligned pair holding hx
         hcomp = (hx & 1) ? 0 : 1;
         hbase = src + (int64_t)hy_c * pitch + ps;
-        if (FUSED) {
-            const T* g = (hx == 0) ? F::gin(B, XM, p) : (hx == nx + 1) ? F::gin(B, XP, p) : nullptr;
-            if (g) {
-                const int fi = hy_c - 1;          // value (z - 1, y - 1)
-                hbase = g - ldx + (fi & ~1);
-                hcomp = fi & 1;
-                hstride = ldx;
-            }
+        // a paired face's ghosts (fused: the neighbour's face buffer) or a
+        // Dirichlet face's compact ghost column, else the block's own column
+        const T* g = nullptr;
+        if (FUSED)
+            g = (hx == 0) ? F::gin(B, XM, p) : (hx == nx + 1) ? F::gin(B, XP, p) : nullptr;
+        if (!g)
+            g = (hx == 0) ? F::xg(B, XM) : (hx == nx + 1) ? F::xg(B, XP) : nullptr;
+        if (g) {
+            const int fi = hy_c - 1;              // value (z - 1, y - 1)
+            hbase = g - ldx + (fi & ~1);
+            hcomp = fi & 1;
+            hstride = ldx;
         }
         hrow = r + 1;
         hcol = role == 2 ? 1 : x_end - x0 + 2;
@@ -840,11 +846,18 @@ k_scatter(const BlockDesc* __restrict__ blocks, const double* __restrict__ g, in
         const int z = (int)(r / (ny + 2));
         const int64_t grow = (int64_t)(B.off[2] + z) * gplane + (int64_t)(B.off[1] + y) * gpitch + B.off[0];
         const int64_t brow = (int64_t)z * B.plane + (int64_t)y * B.pitch;
+        const bool col_row = y >= 1 && y <= ny && z >= 1 && z <= nz;
+        const int64_t col_at = (int64_t)(z - 1) * face_ld(ny) + (y - 1);
         for (int x = threadIdx.x; x < nx + 2; x += 256) {
             const double v = g[grow + x];
             if (which == 0) {
                 B.u[0][brow + x] = v;
                 B.u[1][brow + x] = v;
+                // the compact Dirichlet ghost columns of unpaired x faces
+                if (col_row && x == 0 && B.xg[XM])
+                    const_cast<double*>(B.xg[XM])[col_at] = v;
+                if (col_row && x == nx + 1 && B.xg[XP])
+                    const_cast<double*>(B.xg[XP])[col_at] = v;
             } else {
                 const_cast<double*>(B.b)[brow + x] = v;
             }
