@@ -379,7 +379,9 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hv1 = hx + 1 <= x_end;
         hbase = src + (int64_t)hy * pitch + hx_c;
         if (FUSED) {
-            const T* g = (hy == 0) ? F::gin(B, YM, p) : (hy == ny + 1) ? F::gin(B, YP, p) : nullptr;
+            const T* const gym = F::gin(B, YM, p);    // read uniformly, selected per thread
+            const T* const gyp = F::gin(B, YP, p);
+            const T* g = (hy == 0) ? gym : (hy == ny + 1) ? gyp : nullptr;
             if (g) {
                 hbase = g - ldy + (hx_c - 1);     // value (z - 1, x - 1)
                 hstride = ldy;
@@ -397,12 +399,12 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         hcomp = (hx & 1) ? 0 : 1;
         hbase = src + (int64_t)hy_c * pitch + ps;
         // a paired face's ghosts (fused: the neighbour's face buffer) or a
-        // Dirichlet face's compact ghost column, else the block's own column
-        const T* g = nullptr;
-        if (FUSED)
-            g = (hx == 0) ? F::gin(B, XM, p) : (hx == nx + 1) ? F::gin(B, XP, p) : nullptr;
-        if (!g)
-            g = (hx == 0) ? F::xg(B, XM) : (hx == nx + 1) ? F::xg(B, XP) : nullptr;
+        // Dirichlet face's compact ghost column, else the block's own
+        // column; both faces' pointers are read uniformly, then selected
+        // per thread (a per-thread pointer load would stall the prologue)
+        const T* const gxm = (FUSED && F::gin(B, XM, p)) ? F::gin(B, XM, p) : F::xg(B, XM);
+        const T* const gxp = (FUSED && F::gin(B, XP, p)) ? F::gin(B, XP, p) : F::xg(B, XP);
+        const T* g = (hx == 0) ? gxm : (hx == nx + 1) ? gxp : nullptr;
         if (g) {
             const int fi = hy_c - 1;              // value (z - 1, y - 1)
             hbase = g - ldx + (fi & ~1);
