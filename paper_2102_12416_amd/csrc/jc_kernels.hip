@@ -398,12 +398,15 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         const int ps = (hx & 1) ? hx : hx - 1;    // aligned pair holding hx
         hcomp = (hx & 1) ? 0 : 1;
         hbase = src + (int64_t)hy_c * pitch + ps;
-        // a paired face's ghosts (fused: the neighbour's face buffer) or a
-        // Dirichlet face's compact ghost column, else the block's own
-        // column; both faces' pointers are read uniformly, then selected
-        // per thread (a per-thread pointer load would stall the prologue)
-        const T* const gxm = (FUSED && F::gin(B, XM, p)) ? F::gin(B, XM, p) : F::xg(B, XM);
-        const T* const gxp = (FUSED && F::gin(B, XP, p)) ? F::gin(B, XP, p) : F::xg(B, XP);
+        // Fused: a paired face's ghosts come from the neighbour's face
+        // buffer and a Dirichlet face's from its compact ghost column.
+        // Staged: from the block's own column, whose 128-byte lines each
+        // hold one row's x = 0 ghost and the previous row's x = nx + 1
+        // ghost, both read there.  Both faces' pointers are read uniformly
+        // and selected per thread (a per-thread pointer load would stall
+        // the prologue).
+        const T* const gxm = !FUSED ? nullptr : F::gin(B, XM, p) ? F::gin(B, XM, p) : F::xg(B, XM);
+        const T* const gxp = !FUSED ? nullptr : F::gin(B, XP, p) ? F::gin(B, XP, p) : F::xg(B, XP);
         const T* g = (hx == 0) ? gxm : (hx == nx + 1) ? gxp : nullptr;
         if (g) {
             const int fi = hy_c - 1;              // value (z - 1, y - 1)

@@ -40,10 +40,11 @@ struct BlockDesc {
     void* lgout[6][2];
     // Dirichlet ghost columns of the x faces that have no pair (null for
     // a paired face), laid out like an x face buffer: value (z - 1, y - 1)
-    // at (z - 1) * face_ld(ny) + (y - 1).  In the block arrays a ghost
-    // column holds one value per 128-byte line; here it is contiguous.
-    // xg: of the iterate (written when u is loaded; both copies hold the
-    // same ghosts); lxg: of the refinement correction (zeros).
+    // at (z - 1) * face_ld(ny) + (y - 1).  Fused sweeps read them: there a
+    // ghost column of the block arrays would cost a 128-byte line per row
+    // for one value; here it is contiguous.  xg: of the iterate (written
+    // when u is loaded; both copies hold the same ghosts); lxg: of the
+    // refinement correction (zeros).
     const double* xg[2];
     const void* lxg[2];
     int32_t n[3];            // interior nx, ny, nz
