@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--workload", default="512_2x2x2", choices=sorted(WORKLOADS) + ["refine", "serve", "768_grids"])
     ap.add_argument("--ir-edge", type=int, default=1024, help="refine: grid edge of the per-sweep rates")
     ap.add_argument("--ir-sweeps", type=int, default=100, help="refine: sweeps timed per precision")
+    ap.add_argument("--ir-tile", default="", help="refine: tile_x,tile_y,z_chunk of the refinement solvers "
+                    "(default: the library's choice)")
     ap.add_argument("--ir-solve-edges", type=int, nargs="*", default=[64, 128],
                     help="refine: edges solved to 1e-10 end to end")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -230,6 +232,11 @@ def bench_refinement(args):
     for dt, inner_bytes in (("f32", 12), ("bf16", 6)):
         with Solver(grid, with_source=True, ir_dtype=dt, use_graphs=False) as s:
             s.load(g, b)
+            if args.ir_tile:
+                s.set_tiles(*[int(v) for v in args.ir_tile.split(",")])
+            else:
+                s.autotune(reps=2)      # tunes the inner sweep of the correction
+            out["config"]["ir_tile_%s" % dt] = list(s.tile_info().values())[:3]
             s.set_timing(True)
             t0 = time.perf_counter()
             info = s.solve_ir(inner=50, rtol=0.0, max_inner=args.ir_sweeps)
@@ -265,6 +272,7 @@ def bench_refinement(args):
         for dt in ("f32", "bf16"):
             with Solver(gm, with_source=True, ir_dtype=dt) as s:
                 s.load(gg, bb)
+                s.autotune(reps=2)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 info = s.solve_ir(inner=50, rtol=1e-10, max_inner=2000000)

@@ -309,7 +309,12 @@ int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
  * 16} x tile_y in {4, 8, 16, 32} x z_chunk in {16, 32, 64, ..., depth}) on
  * the bound stream after at least 150 ms of warm-up sweeps, time the four
  * fastest again in turn over three rounds and keep the fastest of those;
- * out = {tile_x, tile_y, z_chunk, microseconds per sweep}.  The trial sweeps write only the other
+ * out = {tile_x, tile_y, z_chunk, microseconds per sweep}.  The sweep timed
+ * is the one the context's solve loop runs: the plain sweep, or, on a
+ * context with refinement buffers (ir_enable), the inner sweep of the
+ * correction (the refinement arrays are zeroed first; every refinement
+ * step rebuilds them; JC_ERR_STATE while a group's refinement step is in
+ * progress on the context).  The trial sweeps write only the other
  * ping-pong copy and face slot, so the current iterate and iteration count
  * are unchanged.  Waits for the stream.  Needs a loaded context. */
 int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);

@@ -1084,12 +1084,15 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
     const bool src = c->opt.with_source != 0;
     info->history_len = 0;
     info->outer = 0;
-    // d = 0 with zero ghosts, once: sweeps never write a ghost
+    // d = 0 with zero ghosts, once: sweeps never write a ghost.  A solve
+    // starts its refinement afresh from the current iterate, so a group's
+    // unfinished step on this context (if any) is dropped.
     st = timed(c, JC_K_IR_OUTER, [&] {
         return jc::launch_zero(c->arena + c->lo_begin, c->lo_end - c->lo_begin, c->stream);
     });
     if (st != JC_OK)
         return st;
+    c->ir_phase = 0;
     // faces of the current iterate into slot `parity` of the u buffers
     if (c->np()) {
         st = do_pack(c, c->parity);
@@ -1223,7 +1226,21 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
     if (reps < 1 || !out)
         return fail(JC_ERR_INVALID, "reps must be >= 1 and out not NULL");
     const bool fused = c->opt.mode == JC_MODE_FUSED && c->np() > 0;
-    if (fused && !c->fused_primed) {
+    // a context with refinement buffers is tuned for the sweep its solve
+    // loop runs: the inner sweep of the correction
+    const bool ir = c->opt.ir_enable != 0;
+    if (ir && c->ir_phase != 0)
+        return fail(JC_ERR_STATE, "autotune: a group's refinement step is in progress on this context "
+                                  "(its r_lo or correction is still to be used)");
+    if (ir) {
+        // every refinement step rebuilds d from r_lo and no sweep writes a
+        // ghost, so trial sweeps on zeroed arrays leave no trace in a solve
+        st = jc::launch_zero(c->arena + c->lo_begin, c->lo_end - c->lo_begin, c->stream) == hipSuccess
+                 ? JC_OK
+                 : fail(JC_ERR_DEVICE, "autotune: zeroing the refinement arrays failed");
+        if (st != JC_OK)
+            return st;
+    } else if (fused && !c->fused_primed) {
         st = do_pack(c, c->parity);
         if (st != JC_OK)
             return st;
@@ -1258,9 +1275,11 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
     // slot parity ^ 1) without swapping: the iterate is unchanged
     auto sweeps = [&](int n) -> int {
         for (int i = 0; i < n; ++i) {
-            const hipError_t e = jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity,
-                                                  c->tile_x, c->tile_y, fused, false, true,
-                                                  c->opt.with_source != 0, nullptr, c->stream);
+            const hipError_t e =
+                ir ? jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), 1, c->tile_x,
+                                         c->tile_y, c->opt.ir_dtype, c->stream)
+                   : jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_x,
+                                      c->tile_y, fused, false, true, c->opt.with_source != 0, nullptr, c->stream);
             if (e != hipSuccess)
                 return fail(JC_ERR_DEVICE, std::string("autotune launch: ") + hipGetErrorString(e));
         }

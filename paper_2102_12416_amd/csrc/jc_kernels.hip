@@ -49,16 +49,17 @@ __device__ __forceinline__ float bf16_to_f32(uint32_t h)
     return __uint_as_float(h << 16);
 }
 
+// Round to nearest even without a branch: adding 0x7fff plus the kept
+// half's lowest bit carries into the upper half exactly when the dropped
+// half is above one half, or equal to it with an odd kept half (equal, bit
+// for bit, to the comparison form for every binary32 pattern).  A NaN
+// stays a (quiet) NaN.
 __device__ __forceinline__ uint32_t f32_to_bf16(float f)
 {
     const uint32_t x = __float_as_uint(f);
-    if ((x & 0x7fffffffu) > 0x7f800000u)          // NaN stays a (quiet) NaN
-        return (x >> 16) | 0x40u;
-    const uint32_t lower = x & 0xffffu;
-    uint32_t upper = x >> 16;
-    if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))
-        upper += 1u;
-    return upper & 0xffffu;
+    const uint32_t rounded = (x + 0x7fffu + ((x >> 16) & 1u)) >> 16;
+    const uint32_t quiet_nan = (x >> 16) | 0x40u;
+    return (x & 0x7fffffffu) > 0x7f800000u ? quiet_nan : rounded;
 }
 
 // Storage formats of a swept field: arithmetic type C, and loads / stores

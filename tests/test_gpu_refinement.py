@@ -129,9 +129,9 @@ def _cells_1024():
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_ir_full_size_1024_sampled(dtype):
     """1024^3 with a source in the launch configuration of the refinement
-    benchmark (one block, default tile, eager launches): one outer step of
-    50 inner sweeps; sampled cells equal the oracle's local refinement bit
-    for bit."""
+    benchmark (one block, tile from jc_autotune of the inner sweep, eager
+    launches): one outer step of 50 inner sweeps; sampled cells equal the
+    oracle's local refinement bit for bit."""
     from paper_2102_12416_amd import synth_field
     n, seed = (1024, 1024, 1024), 12416
     say("IR 1024^3", dtype, "one outer step, sampled")
@@ -145,6 +145,7 @@ def test_ir_full_size_1024_sampled(dtype):
         assert np.array_equal(b[0:3, 500:530, 1000:1026].cpu().numpy(), synth.field_box(n, 1, lo, hi, seed=seed))
         s.load(g, b)
         del g, b
+        s.autotune(reps=2)
         info = s.solve_ir(inner=50, rtol=0.0, max_inner=50)
         got = _sample(s.store(), cells)
     assert info["iters"] == 50 and not info["converged"]
@@ -186,3 +187,41 @@ def test_ir_sixteen_cell_tiles_match_oracle(dtype):
         u = s.store().cpu().numpy()
     assert info["iters"] == done == 200
     assert np.array_equal(u, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_ir_autotune_keeps_results(dtype):
+    """jc_autotune on a refinement context times the inner sweep; the
+    refinement afterwards equals the oracle's bit for bit."""
+    n, bd = (40, 34, 30), (20, 34, 15)
+    say("IR autotune", dtype)
+    u0 = synth.boundary_field(n, seed=41)
+    b = synth.source_field(n, seed=41)
+    ref, _, done, _ = oracle.c_ir_solve(u0, b, storage=dtype, inner=25, rtol=0.0, max_inner=150)
+    with Solver(n, block_dims=bd, mode="fused", with_source=True, ir_dtype=dtype) as s:
+        s.load(u0, b)
+        tx, ty, zc, us = s.autotune(reps=2)
+        assert tx in (16, 32, 64) and (tx // 2) * ty >= 64 and zc >= 1 and us > 0
+        info = s.solve_ir(inner=25, rtol=0.0, max_inner=150)
+        u = s.store().cpu().numpy()
+    assert info["iters"] == done == 150
+    assert np.array_equal(u, ref)
+
+
+def test_ir_autotune_refused_during_a_group_step():
+    """A group leaves a refining member mid-step (its r_lo current);
+    autotuning it then would destroy that state and is refused."""
+    from paper_2102_12416_amd import Group, JcError, _lib as L
+    n = (24, 24, 24)
+    say("IR autotune state")
+    u0 = synth.boundary_field(n, seed=42)
+    b = synth.source_field(n, seed=42)
+    with Solver(n, with_source=True, ir_dtype="f32") as s:
+        s.load(u0, b)
+        with Group([s]) as g:
+            g.residuals()
+        with pytest.raises(JcError) as e:
+            s.autotune(reps=1)
+        assert e.value.code == L.JC_ERR_STATE
+        s.solve_ir(inner=10, rtol=0.0, max_inner=10)     # starts afresh
+        s.autotune(reps=1)
