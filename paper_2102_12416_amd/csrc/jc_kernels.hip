@@ -283,8 +283,8 @@ template <typename T> constexpr int prefetch_planes() { return sizeof(T) == 8 ? 
 //
 // Every thread issues the same global loads in every iteration, with
 // clamped addresses where it has nothing to fetch, so that the loads of
-// the next two planes stay in flight while the current one is computed
-// (no divergent branch around a load).  The halo ring is fetched by
+// the next planes (prefetch_planes<T>()) stay in flight while the current
+// one is computed (no divergent branch around a load).  The halo ring is fetched by
 // threads with a halo role: the first TXP threads the row above the tile,
 // the next TXP the row below, the next TY the column left of it and the
 // next TY the column right of it; the rest re-load their own cells.
@@ -293,9 +293,10 @@ template <typename T> constexpr int prefetch_planes() { return sizeof(T) == 8 ? 
 // correction d of the refinement stored as binary64, binary32 or
 // bfloat16 with binary32 arithmetic).  FUSED: ghost cells of faces that
 // have a neighbour block are read from the neighbour's face buffer of the
-// input slot (the pairing's pre-posted receive side), and every face cell
-// written is also written to this block's face buffer of the output slot
-// -- pack, exchange and unpack folded into the sweep.  RES: accumulate r^2
+// input slot (the pairing's pre-posted receive side), ghost cells of
+// unpaired x faces from the block's compact Dirichlet ghost columns, and
+// every face cell written is also written to this block's face buffer of
+// the output slot -- pack, exchange and unpack folded into the sweep.  RES: accumulate r^2
 // of the input iterate, r = (b + s) - 6u, into one partial per
 // work-group.  STORE: write the new iterate.  SRC: add the source (b for
 // u, r_lo for d).  R: also store r rounded to R into the block's r_lo
