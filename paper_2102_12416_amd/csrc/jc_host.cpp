@@ -886,6 +886,7 @@ int jc_load_field(jc_ctx* c, int which, const void* src)
         c->iters = 0;
         c->ghost = GHOST_CURRENT;     // the scatter filled every ghost with iterate 0
         c->fused_primed = false;
+        c->ir_phase = 0;              // a group's unfinished refinement step belonged to the old iterate
     } else {
         c->loaded_b = true;
     }

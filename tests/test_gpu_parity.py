@@ -382,3 +382,21 @@ def test_host_staged_and_metadata_exchange_bitwise(exchange):
         got = s.store().cpu().numpy()
         assert s.kernel_time(L.JC_K_EXCHANGE)[1] == 15
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mode", ["fused", "staged"])
+def test_reload_refreshes_dirichlet_ghosts(mode):
+    """Loading a second field replaces every ghost the sweeps read,
+    including the compact Dirichlet ghost columns of unpaired x faces."""
+    n = (40, 22, 18)
+    say("reload", mode)
+    a = synth.boundary_field(n, seed=51)
+    b = synth.boundary_field(n, seed=52)
+    ref, _ = oracle.c_jacobi(b, 9, None)
+    with Solver(n, block_dims=(20, 22, 18), mode=mode) as s:
+        s.load(a)
+        s.iterate(3)
+        s.load(b)
+        s.iterate(9)
+        got = s.store().cpu().numpy()
+    assert np.array_equal(got, ref)
