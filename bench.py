@@ -501,6 +501,9 @@ def main():
                                                             % halo_values if mode == "fused" else "")},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in ktime.items() if v[1]},
     }
+    tr = out["roofline"]["traffic"]
+    # counter-measured DRAM bytes (recorded for this kernel source) over the live launch time
+    out["roofline"]["traffic_gbs"] = None if tr is None else round(tr / (avg_ms * 1e-3) / 1e9, 1)
     s.close()
     del s
     torch.cuda.empty_cache()
