@@ -272,6 +272,8 @@ def bench_refinement(args):
             info = s.solve(rtol=1e-10, max_iter=2000000, check_every=50)
             row["f64_plain"] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
                                     rel=info["rel_resid"], converged=info["converged"])
+            u64 = s.store()          # the FP64 path is bitwise the oracle's Jacobi (parity tests)
+            scale = float(u64.abs().max())
         for dt in ("f32", "bf16"):
             with Solver(gm, with_source=True, ir_dtype=dt) as s:
                 s.load(gg, bb)
@@ -280,7 +282,9 @@ def bench_refinement(args):
                 t0 = time.perf_counter()
                 info = s.solve_ir(inner=50, rtol=1e-10, max_inner=2000000)
                 row["%s_refined" % dt] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
-                                              rel=info["rel_resid"], converged=info["converged"])
+                                              rel=info["rel_resid"], converged=info["converged"],
+                                              max_rel_err_vs_f64=float((s.store() - u64).abs().max()) / scale)
+        del u64
         ttt[str(m)] = row
         print("[bench] time to 1e-10 at %d^3: %s" % (m, json.dumps(row)), file=sys.stderr, flush=True)
     out["time_to_1e-10"] = ttt
