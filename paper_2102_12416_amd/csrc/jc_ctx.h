@@ -45,10 +45,8 @@ struct HostBlock {
     int pair_out[6];        // pair index whose source is this face, or -1
     int pair_in[6];         // pair index whose destination is this face, or -1
     int64_t pitch, plane;   // binary64 arrays
-    int64_t lead;           // elements from an array's base to element (0,0,0)
-    size_t u_off[2], b_off; // byte offsets of the arrays' bases
+    size_t u_off[2], b_off; // byte offsets of element (0,0,0)'s line base
     int64_t lpitch, lplane; // refinement arrays (d, r_lo)
-    int64_t llead;
     size_t d_off[2], rlo_off;
     size_t xg_off[2];       // compact Dirichlet ghost column of face XM / XP (unpaired faces)
 };
@@ -59,20 +57,6 @@ struct HostPair {
     size_t buf_off[2];
     size_t lbuf_off[2];     // refinement face buffers
 };
-
-// Row layout of a block array whose elements are 128 / le bytes.  Rows of
-// a width that is a whole number of 128-byte lines are aligned: x = 1 of
-// every row starts a line (pitch a multiple of le, element (0,0,0) at le - 1).
-// Any other width is packed: pitch = nx + 2 rounded up to even, element
-// (0,0,0) at 1, so a row's partly used last line is the next row's first
-// instead of padding that is fetched for nothing, and every thread's pair
-// (x, x + 1), x odd, still starts at an even element (an aligned vector).
-inline void row_layout(int64_t nx, int64_t le, int64_t* pitch, int64_t* lead)
-{
-    const bool aligned = nx % le == 0;
-    *pitch = aligned ? (nx + 2 + le - 1) / le * le : (nx + 3) / 2 * 2;
-    *lead = aligned ? le - 1 : 1;
-}
 
 // Bytes of one element of the refinement storage format.
 inline size_t lo_size(int dtype) { return dtype == JC_F64 ? 8 : dtype == JC_F32 ? 4 : 2; }

@@ -189,7 +189,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
                 b.nbr[jc::ZP] = k + 1 < pz ? bidx(i, j, k + 1) : -1;
                 for (int f = 0; f < 6; ++f)
                     b.pair_out[f] = b.pair_in[f] = -1;
-                row_layout(b.n[0], jc::line_elems<double>(), &b.pitch, &b.lead);
+                b.pitch = round_up(b.n[0] + 2, jc::line_elems<double>());
                 b.plane = b.pitch * (b.n[1] + 2);
                 c->blocks.push_back(b);
             }
@@ -242,8 +242,8 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
     c->off_ranges = off; off = align_up(off + sizeof(int32_t) * 2, kAlign);
     c->off_result = off; off = align_up(off + sizeof(double) * 4, kAlign);
     for (HostBlock& b : c->blocks) {
-        // the lead before element (0,0,0) plus slack for the pair beyond
-        // the last row's ghost
+        // element (0,0,0) sits 15 elements into a 128-byte line so that
+        // cell x = 1 of every row starts a line; 16 elements of slack
         const size_t bytes = align_up(sizeof(double) * (size_t)(b.plane * (b.n[2] + 2) + 16), kAlign);
         b.u_off[0] = off; off += bytes;
         b.u_off[1] = off; off += bytes;
@@ -272,7 +272,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         const size_t es = lo_size(c->opt.ir_dtype);
         const int64_t le = 128 / (int64_t)es;
         for (HostBlock& b : c->blocks) {
-            row_layout(b.n[0], le, &b.lpitch, &b.llead);
+            b.lpitch = round_up(b.n[0] + 2, le);
             b.lplane = b.lpitch * (b.n[1] + 2);
             const size_t bytes = align_up(es * (size_t)(b.lplane * (b.n[2] + 2) + le), kAlign);
             b.d_off[0] = off; off += bytes;
@@ -798,9 +798,10 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
     for (int bi = 0; bi < c->nb(); ++bi) {
         const HostBlock& hb = c->blocks[bi];
         BlockDesc& d = c->hdesc[bi];
-        d.u[0] = reinterpret_cast<double*>(c->arena + hb.u_off[0]) + hb.lead;
-        d.u[1] = reinterpret_cast<double*>(c->arena + hb.u_off[1]) + hb.lead;
-        d.b = c->opt.with_source ? reinterpret_cast<double*>(c->arena + hb.b_off) + hb.lead : nullptr;
+        const int64_t lead = jc::line_elems<double>() - 1;
+        d.u[0] = reinterpret_cast<double*>(c->arena + hb.u_off[0]) + lead;
+        d.u[1] = reinterpret_cast<double*>(c->arena + hb.u_off[1]) + lead;
+        d.b = c->opt.with_source ? reinterpret_cast<double*>(c->arena + hb.b_off) + lead : nullptr;
         for (int f = 0; f < 6; ++f)
             for (int s = 0; s < 2; ++s) {
                 d.gin[f][s] = hb.pair_in[f] >= 0
@@ -820,7 +821,7 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
         d.plane = hb.plane;
         if (c->opt.ir_enable) {
             const size_t es = lo_size(c->opt.ir_dtype);
-            const size_t llead = (size_t)hb.llead * es;
+            const size_t llead = (128 / es - 1) * es;
             d.d[0] = c->arena + hb.d_off[0] + llead;
             d.d[1] = c->arena + hb.d_off[1] + llead;
             d.rlo = c->arena + hb.rlo_off + llead;
@@ -1361,7 +1362,7 @@ int jc_block_info(const jc_ctx* c, int64_t i, int64_t out[17])
         out[6 + f] = b.nbr[f];
     out[12] = b.pitch;
     out[13] = b.plane;
-    const int64_t lead = b.lead * (int64_t)sizeof(double);
+    const int64_t lead = (jc::line_elems<double>() - 1) * (int64_t)sizeof(double);
     out[14] = (int64_t)b.u_off[0] + lead;
     out[15] = (int64_t)b.u_off[1] + lead;
     out[16] = c->parity;

@@ -92,12 +92,8 @@ def test_uniform_decomposition_and_pairing(grid, bd, nb, npairs):
         for b in blocks:
             for a in range(3):
                 assert 0 <= b[3 + a] and b[3 + a] + b[a] <= grid[a]
-            # pitch: rows of whole 128-byte lines stay line-aligned (a multiple
-            # of 16 doubles with room for both x ghosts); other widths are packed
-            if b[0] % 16 == 0:
-                assert b[12] % 16 == 0 and b[12] >= b[0] + 2
-            else:
-                assert b[12] == (b[0] + 3) // 2 * 2
+            # pitch: a multiple of 16 doubles with room for both x ghosts
+            assert b[12] % 16 == 0 and b[12] >= b[0] + 2
             assert b[13] == b[12] * (b[1] + 2)
         # every directed pair has its reverse, with opposite faces and equal counts
         table = {(p[0], p[1]): p for p in pairs}
