@@ -1269,7 +1269,10 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     JC_HIP(hipEventCreate(&e0));
-    JC_HIP(hipEventCreate(&e1));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(JC_ERR_DEVICE, "autotune: hipEventCreate failed");
+    }
     const bool was_timing = c->timing;
     c->timing = false;
     // trial sweeps read copy `parity` and write the other copy (and face
