@@ -400,3 +400,22 @@ def test_reload_refreshes_dirichlet_ghosts(mode):
         s.iterate(9)
         got = s.store().cpu().numpy()
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+@pytest.mark.parametrize("n,bd", [((1, 1, 1), None), ((1, 6, 5), None), ((2, 3, 4), None),
+                                  ((6, 5, 4), (1, 5, 4)), ((9, 7, 5), (2, 1, 5)), ((3, 3, 3), (1, 1, 1))])
+def test_degenerate_sizes_vs_oracle(mode, n, bd):
+    """The smallest grids and blocks: one cell, one- or two-cell-wide rows
+    (a thread's pair holds a cell and the x = nx + 1 ghost, and both x faces
+    of a block can fall on one thread), blocks one cell thick."""
+    say("degenerate", n, bd, mode)
+    u0 = synth.boundary_field(n, seed=61)
+    b = synth.source_field(n, seed=61)
+    ref, _ = oracle.c_jacobi(u0, 7, b)
+    kw = {} if bd is None else dict(block_dims=bd)
+    with Solver(n, mode=mode, with_source=True, **kw) as s:
+        s.load(u0, b)
+        s.iterate(7)
+        got = s.store().cpu().numpy()
+    assert np.array_equal(got, ref)

@@ -225,3 +225,19 @@ def test_ir_autotune_refused_during_a_group_step():
         assert e.value.code == L.JC_ERR_STATE
         s.solve_ir(inner=10, rtol=0.0, max_inner=10)     # starts afresh
         s.autotune(reps=1)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_ir_one_cell_blocks(dtype):
+    """Refinement on blocks one cell wide in x and y."""
+    n, bd = (6, 5, 7), (1, 1, 7)
+    say("IR one-cell blocks", dtype)
+    u0 = synth.boundary_field(n, seed=62)
+    b = synth.source_field(n, seed=62)
+    ref, _, done, _ = oracle.c_ir_solve(u0, b, storage=dtype, inner=10, rtol=0.0, max_inner=60)
+    with Solver(n, block_dims=bd, mode="fused", with_source=True, ir_dtype=dtype) as s:
+        s.load(u0, b)
+        info = s.solve_ir(inner=10, rtol=0.0, max_inner=60)
+        u = s.store().cpu().numpy()
+    assert info["iters"] == done == 60
+    assert np.array_equal(u, ref)
