@@ -1,6 +1,6 @@
 // Host runtime of libjc: decomposition, face pairing, work lists, arena
 // layout, the state machine of the staged exchange, graph-captured
-// iteration windows and the solve driver.  Implements include/jc.h.
+// iteration windows and the solve loops.  Implements include/jc.h.
 //
 // Paper section 4.3 (Jacobi3D): the domain is split into equal cuboid
 // blocks with minimal surface area; each iteration exchanges block halos
