@@ -126,7 +126,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
-                 progress_every: float = 0.0, lanes=(64, 160)):
+                 progress_every: float = 0.0, lanes=(64, 160), tile=(64, 32, 32)):
         if window < 1 or max_iter % window:
             raise ValueError("max_iter must be a multiple of the window")
         bounds = [int(v) for v in lanes]
@@ -140,6 +140,9 @@ class Server:
         self.keep_fields = keep_fields
         self.use_graphs = use_graphs
         self.lane_bounds = tuple(bounds)
+        # one tile shape for every group: a member's residual norms (and so
+        # its stopping check) then do not depend on who else is in the group
+        self.tile = tuple(int(v) for v in tile)
         self.max_members = 4096
         self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0, lane_windows=[])
         self.progress_every = float(progress_every)   # seconds between progress lines (0: none)
@@ -178,7 +181,8 @@ class Server:
     def _regroup(self, lane):
         lane.close()
         if lane.active:
-            lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream)
+            lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream,
+                               tile=self.tile)
             lane.key = tuple(l.req.id for l in lane.active)
             self.stats["group_builds"] += 1
 
