@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-lanes", default="64,160",
                     help="ascending edge bounds of the server's size lanes ('none': one group for all)")
-    ap.add_argument("--serve-tile", default="64,32,32", help="tile_x,tile_y,z_chunk of the server's groups")
+    ap.add_argument("--serve-tile", default="", help="tile_x,tile_y,z_chunk of the server's groups "
+                    "(default: the library's group tile)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate (requests/s); 0 = 0.7 x the measured closed-loop capacity")
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
@@ -396,7 +397,8 @@ def bench_serve(args):
 
     def server():
         return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter,
-                      progress_every=15.0, lanes=lanes, tile=[int(v) for v in args.serve_tile.split(",")])
+                      progress_every=15.0, lanes=lanes,
+                      tile=[int(v) for v in args.serve_tile.split(",")] if args.serve_tile else None)
 
     cap = None
     rate = args.serve_rate
@@ -425,7 +427,7 @@ def bench_serve(args):
            "config": {"workload": "serve", "requests": args.serve_requests, "rate_per_s": round(rate, 3),
                       "edges": "log-uniform [32, %d]" % args.serve_max_edge, "precision": "Bernoulli(0.5) f64/f32",
                       "rtol": 1e-10, "max_iter": args.serve_max_iter, "window": 50,
-                      "budget_gb": args.serve_budget_gb, "lanes": list(lanes), "tile": args.serve_tile,
+                      "budget_gb": args.serve_budget_gb, "lanes": list(lanes), "tile": args.serve_tile or "64,8,32 (group default)",
                       "rate_source": "given" if args.serve_rate > 0 else "0.7 x closed-loop capacity"},
            "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4), "summary": summ,
            "capacity": cap, "server_stats": srv.stats}

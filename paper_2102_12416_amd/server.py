@@ -126,7 +126,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
-                 progress_every: float = 0.0, lanes=(64, 160), tile=(64, 32, 32)):
+                 progress_every: float = 0.0, lanes=(64, 160), tile=None):
         if window < 1 or max_iter % window:
             raise ValueError("max_iter must be a multiple of the window")
         bounds = [int(v) for v in lanes]
@@ -140,9 +140,11 @@ class Server:
         self.keep_fields = keep_fields
         self.use_graphs = use_graphs
         self.lane_bounds = tuple(bounds)
-        # one tile shape for every group: a member's residual norms (and so
-        # its stopping check) then do not depend on who else is in the group
-        self.tile = tuple(int(v) for v in tile)
+        # one tile shape for every group (None: the library's group default,
+        # 64 x 8 x 32, which measured best for the served mix): a member's
+        # residual norms, and so its stopping check, then do not depend on
+        # who else is in the group
+        self.tile = None if tile is None else tuple(int(v) for v in tile)
         self.max_members = 4096
         self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0, lane_windows=[])
         self.progress_every = float(progress_every)   # seconds between progress lines (0: none)
