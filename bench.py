@@ -38,6 +38,18 @@ WORKLOADS = {
 
 # Tile shapes picked by jc_autotune on an MI355X for the default mode
 # (rows per tile, planes per work item); other workloads tune at start-up.
+# The paper's Jacobi3D results (section 4.3; hardware in section 4.1), quoted
+# as context beside the one-GPU exchange comparison: not the same transfer
+# (there between processes and nodes), not a target.
+PAPER_COMM_SPEEDUPS = {
+    "hardware": "Summit: IBM AC922 nodes, 2x Power9 + 6x NVIDIA V100 each, NVLink 50 GB/s in a socket, "
+                "EDR InfiniBand between nodes",
+    "comm_speedup_gpu_aware_vs_host_staged": {"Charm++ GPU Messaging, weak scaling": "1.1-12.4x",
+                                              "AMPI, weak scaling": "1.3-12.8x",
+                                              "Charm4py, weak scaling": "1.9-19.7x"},
+    "source": "paper section 4.3",
+}
+
 TUNED_TILES = {
     ("512_2x2x2", "fused"): (64, 32, 256),
     ("512_2x2x2", "staged"): (64, 32, 64),
@@ -565,6 +577,7 @@ def main():
         print("[bench] exchange A/B: device pairing vs host staging vs host metadata", file=sys.stderr, flush=True)
         st_tiles = TUNED_TILES.get((args.workload, "staged"), (tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]))
         out["exchange_ab"] = exchange_ab(grid, bd, args.seed, args.ab_iters, st_tiles)
+        out["exchange_ab"]["paper_context"] = PAPER_COMM_SPEEDUPS
     if not args.no_cpu:
         print("[bench] CPU oracle baseline (%.0f s budget)" % args.cpu_seconds, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid, args.seed, args.cpu_seconds)
