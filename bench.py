@@ -95,6 +95,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ab", action="store_true", help="skip the device / host-staged exchange comparison")
     ap.add_argument("--ab-iters", type=int, default=100)
+    ap.add_argument("--graphs", choices=["auto", "on", "off"], default="auto",
+                    help="time a hipGraph replay of the whole window (fused mode; the sweep's time is then the "
+                         "stream time per iteration) instead of eager launches with HIP events around each; "
+                         "auto: on for the 768^3 batching workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
@@ -481,9 +485,13 @@ def main():
         kw["block_dims"] = bd
     if uneven_seed is not None:
         kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
+    graphs = args.graphs == "on" or (args.graphs == "auto" and args.workload.startswith("768_"))
+    if graphs and mode != "fused":
+        print("bench.py: --graphs needs the fused mode (one launch per iteration)", file=sys.stderr)
+        sys.exit(2)
     print("[bench] workload %s mode %s: building inputs" % (args.workload, mode), file=sys.stderr, flush=True)
     u0 = synth.boundary_field(grid, seed=args.seed)
-    s = Solver(grid, mode=mode, use_graphs=False, tile_x=args.tile_x, tile_y=args.tile_y, z_chunk=args.z_chunk,
+    s = Solver(grid, mode=mode, use_graphs=graphs, tile_x=args.tile_x, tile_y=args.tile_y, z_chunk=args.z_chunk,
                **kw)
     s.load(u0)
     del u0
@@ -501,11 +509,18 @@ def main():
                   flush=True)
     tiles = s.tile_info()
     s.iterate(args.warmup)
+    if graphs:
+        # capture the timed window's graph outside the timed region (both
+        # start parities when the window is odd)
+        s.iterate(args.steps)
+        if args.steps % 2:
+            s.iterate(args.steps)
     s.synchronize()
-    print("[bench] warmup done (%d iterations); timing %d" % (args.warmup, args.steps), file=sys.stderr,
-          flush=True)
+    print("[bench] warmup done (%d iterations); timing %d%s" % (args.warmup, args.steps,
+          " as one graph replay" if graphs else ""), file=sys.stderr, flush=True)
 
-    s.set_timing(True)
+    if not graphs:
+        s.set_timing(True)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -518,8 +533,13 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     kinds = {"sweep": L.JC_K_SWEEP, "pack": L.JC_K_PACK, "exchange": L.JC_K_EXCHANGE,
              "unpack": L.JC_K_UNPACK, "fused": L.JC_K_FUSED}
-    ktime = {k: s.kernel_time(v) for k, v in kinds.items()}
-    s.set_timing(False)
+    if graphs:
+        # one fused launch per iteration: the stream time per iteration bounds
+        # the sweep's launch time from above
+        ktime = {"fused": (gpu_ms, args.steps)}
+    else:
+        ktime = {k: s.kernel_time(v) for k, v in kinds.items()}
+        s.set_timing(False)
     print("[bench] timed region done: %.3f s wall, %.3f ms on the stream" % (wall, gpu_ms), file=sys.stderr,
           flush=True)
 
@@ -554,6 +574,7 @@ def main():
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
                    "tile_source": tile_source,
+                   "launch": "hipGraph replay of the timed window" if graphs else "eager, HIP events per launch",
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
         "hbm_gbs_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "pct_hbm_peak_step": round(100 * step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
