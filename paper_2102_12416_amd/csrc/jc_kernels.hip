@@ -59,7 +59,7 @@ __device__ __forceinline__ uint32_t f32_to_bf16(float f)
     const uint32_t x = __float_as_uint(f);
     const uint32_t rounded = (x + 0x7fffu + ((x >> 16) & 1u)) >> 16;
     const uint32_t quiet_nan = (x >> 16) | 0x40u;
-    return (x & 0x7fffffffu) > 0x7f800000u ? quiet_nan : rounded;
+    return __builtin_isnan(f) ? quiet_nan : rounded;   // an unordered self-compare
 }
 
 // Storage formats of a swept field: arithmetic type C, and loads / stores
