@@ -240,9 +240,10 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * must not be used on their own streams while the group exists.
  * flags: bit 0 = capture jc_group_iterate windows as HIP graphs (needs a
  * non-null stream).  tile: {cells per row 16|32|64, rows 4|8|16|32 (at
- * least 8 for 16-cell rows), planes >= 1} for every launch of the group, or NULL for {64, 8, 32}; members'
- * results do not depend on it, their residual norms do in the last bits,
- * so compare mixes within one tile shape.  Host only until jc_group_bind. */
+ * least 8 for 16-cell rows), planes >= 1} for every launch of the group,
+ * or NULL for {64, 8, 32}; members' results do not depend on it, their
+ * residual norms do in the last bits, so compare mixes within one tile
+ * shape.  Host only until jc_group_bind. */
 int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, const int tile[3],
                     jc_group** out);
 /* Device scratch the group needs (joint tables, partial sums). */
@@ -250,7 +251,10 @@ int jc_group_footprint(const jc_group* g, size_t* bytes);
 /* Attach caller-owned scratch (>= footprint, 256-byte aligned); orders the
  * group stream after every member's queued work; uploads the tables. */
 int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes);
-/* n sweeps of every member (inner sweeps for refining members). */
+/* n sweeps of every member (inner sweeps for refining members).
+ * JC_ERR_STATE if a refining member's residual is due, or if refining
+ * members of one storage format are at different points of their step
+ * (after leaving different groups): jc_group_residuals first. */
 int jc_group_iterate(jc_group* g, int64_t n);
 /* |r|_2 of every member's current iterate into host_l2[members], after the
  * outer step of refining members; waits for the stream.  JC_ERR_NONFINITE

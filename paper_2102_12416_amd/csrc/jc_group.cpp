@@ -314,10 +314,20 @@ int jc_group_iterate(jc_group* g, int64_t n)
     if (n < 0)
         return fail(JC_ERR_INVALID, "n must be >= 0");
     for (const Class& k : g->classes)
-        if (k.ir)
-            for (int m : k.members)
-                if (g->members[m]->ir_phase == 0)
+        if (k.ir) {
+            // one launch serves the whole class: its members must be at the
+            // same point of their refinement step (jc_group_residuals
+            // brings every member there)
+            const jc_ctx* c0 = g->members[k.members[0]];
+            for (int m : k.members) {
+                const jc_ctx* c = g->members[m];
+                if (c->ir_phase == 0)
                     return fail(JC_ERR_STATE, "a refining member needs jc_group_residuals before sweeping");
+                if (c->ir_phase != c0->ir_phase || c->ir_q != c0->ir_q)
+                    return fail(JC_ERR_STATE, "refining members are at different points of their step; "
+                                              "call jc_group_residuals first");
+            }
+        }
     if (n == 0)
         return JC_OK;
     int st = prime_faces(g);

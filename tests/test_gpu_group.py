@@ -97,3 +97,35 @@ def test_group_tile_shape_keeps_results():
             s.close()
         for a, b in zip(ref, got):
             assert np.array_equal(a, b), tile
+
+
+def test_mixed_refinement_steps_need_residuals_first():
+    """Two refining members that left different groups at different points
+    of their step cannot share a launch until jc_group_residuals brings
+    both to the same point; the results then still equal the oracle's."""
+    import oracle
+    import synth
+    from paper_2102_12416_amd import Group, JcError, Solver, _lib as L
+    n = (20, 18, 16)
+    us = [synth.boundary_field(n, seed=71 + i) for i in range(2)]
+    bs = [synth.source_field(n, seed=71 + i) for i in range(2)]
+    a = Solver(n, with_source=True, ir_dtype="f32").load(us[0], bs[0])
+    b = Solver(n, with_source=True, ir_dtype="f32").load(us[1], bs[1])
+    with Group([a]) as g:
+        g.residuals()
+        g.iterate(10)             # a: inner sweeps ran, correction pending
+    with Group([b]) as g:
+        g.residuals()             # b: r_lo current, no sweeps yet
+    with Group([a, b]) as g:
+        with pytest.raises(JcError) as e:
+            g.iterate(10)
+        assert e.value.code == L.JC_ERR_STATE
+        g.residuals()
+        g.iterate(10)
+        g.residuals()
+    for s, u0, b0, sweeps in ((a, us[0], bs[0], 20), (b, us[1], bs[1], 10)):
+        ref, _, done, _ = oracle.c_ir_solve(u0, b0, storage="f32", inner=10, rtol=0.0, max_inner=sweeps)
+        assert done == sweeps
+        assert np.array_equal(s.store().cpu().numpy(), ref)
+    a.close()
+    b.close()
