@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--graphs", choices=["auto", "on", "off"], default="auto",
                     help="time a hipGraph replay of the whole window (fused mode; the sweep's time is then the "
                          "stream time per iteration) instead of eager launches with HIP events around each; "
-                         "auto: on for the 768^3 batching workloads")
+                         "auto: on in fused mode")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
@@ -491,7 +491,7 @@ def main():
         kw["block_dims"] = bd
     if uneven_seed is not None:
         kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
-    graphs = args.graphs == "on" or (args.graphs == "auto" and args.workload.startswith("768_"))
+    graphs = args.graphs == "on" or (args.graphs == "auto" and mode == "fused")
     if graphs and mode != "fused":
         print("bench.py: --graphs needs the fused mode (one launch per iteration)", file=sys.stderr)
         sys.exit(2)
