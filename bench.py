@@ -34,6 +34,9 @@ WORKLOADS = {
     "64_single": ((64, 64, 64), None, None, "staged"),
     "768_8x8x8": ((768, 768, 768), (96, 96, 96), None, "fused"),
     "768_uneven": ((768, 768, 768), None, 12416, "fused"),
+    # one GPU's share of the paper's weak-scaling base (1536^3 per node of
+    # six GPUs, section 4.3): a single 512 x 768 x 1536 block
+    "paper_share": ((512, 768, 1536), None, None, "fused"),
 }
 
 # Tile shapes picked by jc_autotune on an MI355X for the default mode
