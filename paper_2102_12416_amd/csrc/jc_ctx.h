@@ -58,6 +58,15 @@ struct HostPair {
     size_t lbuf_off[2];     // refinement face buffers
 };
 
+// A block of depth nz is cut into ceil(nz / zc) z chunks of nearly equal
+// length (no short tail chunk): chunk k covers planes [z0, z0 + len).
+inline void z_chunk_range(int64_t nz, int64_t zc, int64_t k, int64_t* z0, int64_t* len)
+{
+    const int64_t nch = (nz + zc - 1) / zc;
+    *z0 = k * nz / nch;
+    *len = (k + 1) * nz / nch - *z0;
+}
+
 // Bytes of one element of the refinement storage format.
 inline size_t lo_size(int dtype) { return dtype == JC_F64 ? 8 : dtype == JC_F32 ? 4 : 2; }
 

@@ -80,15 +80,18 @@ void member_items(const jc_ctx* c, const int tile[3], int bbase, int member, std
 {
     for (int bi = 0; bi < (int)c->blocks.size(); ++bi) {
         const HostBlock& b = c->blocks[bi];
-        for (int64_t z0 = 0; z0 < b.n[2]; z0 += tile[2])
+        const int64_t nch = (b.n[2] + tile[2] - 1) / tile[2];
+        for (int64_t k = 0; k < nch; ++k)
             for (int64_t y0 = 0; y0 < b.n[1]; y0 += tile[1])
                 for (int64_t x0 = 0; x0 < b.n[0]; x0 += tile[0]) {
+                    int64_t z0 = 0, zlen = 0;
+                    z_chunk_range(b.n[2], tile[2], k, &z0, &zlen);
                     Item it{};
                     it.block = bbase + bi;
                     it.x0 = (int32_t)x0;
                     it.y0 = (int32_t)y0;
                     it.z0 = (int32_t)z0;
-                    it.zlen = (int32_t)std::min<int64_t>(tile[2], b.n[2] - z0);
+                    it.zlen = (int32_t)zlen;
                     it.flip = c->parity;
                     it.owner = member;
                     out.push_back(it);

@@ -92,15 +92,18 @@ void build_items(jc_ctx* c)
     c->items.clear();
     for (int bi = 0; bi < c->nb(); ++bi) {
         const HostBlock& b = c->blocks[bi];
-        for (int64_t z0 = 0; z0 < b.n[2]; z0 += c->z_chunk)
+        const int64_t nch = (b.n[2] + c->z_chunk - 1) / c->z_chunk;
+        for (int64_t k = 0; k < nch; ++k)
             for (int64_t y0 = 0; y0 < b.n[1]; y0 += c->tile_y)
                 for (int64_t x0 = 0; x0 < b.n[0]; x0 += c->tile_x) {
+                    int64_t z0 = 0, zlen = 0;
+                    z_chunk_range(b.n[2], c->z_chunk, k, &z0, &zlen);
                     Item it{};
                     it.block = bi;
                     it.x0 = (int32_t)x0;
                     it.y0 = (int32_t)y0;
                     it.z0 = (int32_t)z0;
-                    it.zlen = (int32_t)std::min<int64_t>(c->z_chunk, b.n[2] - z0);
+                    it.zlen = (int32_t)zlen;
                     it.flip = 0;
                     it.owner = 0;
                     c->items.push_back(it);
