@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate (requests/s); 0 = 0.7 x the measured closed-loop capacity")
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
+    ap.add_argument("--temporal", action="store_true",
+                    help="one-block workloads: two sweeps per launch (temporal blocking)")
     ap.add_argument("--seed", type=int, default=12416)
     ap.add_argument("--tile-x", type=int, default=0, help="cells per tile row, 32 or 64 (0: library default)")
     ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")
@@ -495,13 +497,17 @@ def main():
     if uneven_seed is not None:
         kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
     graphs = args.graphs == "on" or (args.graphs == "auto" and mode == "fused")
+    temporal = bool(args.temporal)
+    if temporal and (bd is not None or uneven_seed is not None or args.steps % 2):
+        print("bench.py: --temporal needs a one-block workload and an even --steps", file=sys.stderr)
+        sys.exit(2)
     if graphs and mode != "fused":
         print("bench.py: --graphs needs the fused mode (one launch per iteration)", file=sys.stderr)
         sys.exit(2)
     print("[bench] workload %s mode %s: building inputs" % (args.workload, mode), file=sys.stderr, flush=True)
     u0 = synth.boundary_field(grid, seed=args.seed)
     s = Solver(grid, mode=mode, use_graphs=graphs, tile_x=args.tile_x, tile_y=args.tile_y, z_chunk=args.z_chunk,
-               **kw)
+               temporal=temporal, **kw)
     s.load(u0)
     del u0
     nb = s.num_blocks
@@ -541,8 +547,11 @@ def main():
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     kinds = {"sweep": L.JC_K_SWEEP, "pack": L.JC_K_PACK, "exchange": L.JC_K_EXCHANGE,
-             "unpack": L.JC_K_UNPACK, "fused": L.JC_K_FUSED}
-    if graphs:
+             "unpack": L.JC_K_UNPACK, "fused": L.JC_K_FUSED, "sweep2": L.JC_K_SWEEP2}
+    if graphs and temporal:
+        # one two-sweep launch per two iterations
+        ktime = {"sweep2": (gpu_ms, args.steps // 2)}
+    elif graphs:
         # one fused launch per iteration: the stream time per iteration bounds
         # the sweep's launch time from above
         ktime = {"fused": (gpu_ms, args.steps)}
@@ -556,15 +565,18 @@ def main():
     lups = float(nx) * ny * nz
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     glups = lups * args.steps / (ms_per_step * args.steps * 1e-3) / 1e9
-    dom = "fused" if mode == "fused" else "sweep"
+    dom = "sweep2" if temporal else "fused" if mode == "fused" else "sweep"
     dom_ms, dom_n = ktime[dom]
     avg_ms = dom_ms / max(dom_n, 1)
-    sweep_bytes = 16.0 * lups                       # read u, write u' per cell update
+    # read u, write u' per cell update; the two-sweep launch reads iterate k
+    # and writes iterate k + 2 once per cell (8 B per update)
+    sweep_bytes = (8.0 if temporal else 16.0) * lups
+    launch_bytes = 16.0 * lups
     halo_values = sum(s.pair_info(q)["count"] for q in range(s.num_pairs))
     # the fused sweep also moves the halo: each exchanged face value is
     # written once (epilogue) and read once (the neighbour's ghost); the
     # staged sweep leaves that to pack / exchange / unpack (48 B per value)
-    kernel_bytes = sweep_bytes + (16.0 * halo_values if mode == "fused" else 0.0)
+    kernel_bytes = launch_bytes + (16.0 * halo_values if mode == "fused" else 0.0)
     achieved = kernel_bytes / (avg_ms * 1e-3) / 1e9
     step_bytes = sweep_bytes + (16.0 if mode == "fused" else 48.0) * halo_values
     out = {
@@ -582,19 +594,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
+                   "temporal": temporal,
                    "tile_source": tile_source,
                    "launch": "hipGraph replay of the timed window" if graphs else "eager, HIP events per launch",
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
         "hbm_gbs_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "pct_hbm_peak_step": round(100 * step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
-        "roofline": {"bound": "hbm", "kernel": "k_sweep" if mode == "staged" else "k_sweep(fused)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_sweep2" if temporal else "k_sweep" if mode == "staged" else "k_sweep(fused)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(args.workload, mode,
-                                                 [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]]),
+                     "traffic": None if temporal else recorded_traffic(
+                         args.workload, mode, [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]]),
                      "bytes_per_launch": kernel_bytes, "avg_launch_ms": round(avg_ms, 5),
-                     "bytes_per_unit": "16 B per update" + (" + 16 B per exchanged face value (%d values)"
-                                                            % halo_values if mode == "fused" else "")},
+                     "bytes_per_unit": ("16 B per cell per two-sweep launch (8 B per update)" if temporal else
+                                        "16 B per update" + (" + 16 B per exchanged face value (%d values)"
+                                                             % halo_values if mode == "fused" else ""))},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in ktime.items() if v[1]},
     }
     tr = out["roofline"]["traffic"]

@@ -75,10 +75,10 @@ enum {
  * Messaging API's receiver needs a host message before it can post its
  * receive.  HOST and METADATA disable graph capture. */
 enum { JC_EXCHANGE_DEVICE = 0, JC_EXCHANGE_HOST = 1, JC_EXCHANGE_METADATA = 2 };
-/* kinds for jc_kernel_time */
+/* kinds for jc_kernel_time (JC_K_SWEEP2: the two-sweep launches of temporal blocking) */
 enum { JC_K_SWEEP = 0, JC_K_PACK = 1, JC_K_EXCHANGE = 2, JC_K_UNPACK = 3,
        JC_K_RESIDUAL = 4, JC_K_FUSED = 5, JC_K_IR_INNER = 6, JC_K_IR_OUTER = 7,
-       JC_K_COUNT = 8 };
+       JC_K_SWEEP2 = 8, JC_K_COUNT = 9 };
 
 typedef struct jc_ctx jc_ctx;
 typedef struct jc_group jc_group;
@@ -97,6 +97,13 @@ typedef struct jc_options {
     int tile_x;          /* cells per tile row: 16, 32 or 64 (16 needs tile_y >= 8 or
                             auto); 0 = auto (64, or 32 where it idles fewer lanes) */
     int exchange;        /* JC_EXCHANGE_DEVICE (default), _HOST or _METADATA */
+    int temporal;        /* 1: temporal blocking -- jc_iterate and the windows of jc_solve
+                            advance two sweeps per launch (binary64; iterate k + 1 stays
+                            on chip, so each cell is read and written once per two
+                            sweeps; results bitwise equal to one-sweep launches).  Needs a
+                            context of one block (no face pairs); the residual sweeps of
+                            jc_solve, jc_sweep, refinement and groups run one sweep per
+                            launch.  0: one sweep per launch. */
 } jc_options;
 
 /* Result of a solve. */

@@ -85,6 +85,10 @@ inline bool tile_shape_ok(int tile_x, int tile_y)
     return ok_x && ok_y && (tile_x / 2) * tile_y >= 64;
 }
 constexpr int kMinZChunk = 16;
+// Temporal blocking: rows of the two-sweep tile (64 cells wide) and the
+// fewest planes per work-group (each reads two planes beyond each end).
+constexpr int kTwoStepRows = 16;
+constexpr int kTwoStepMinZ = 32;
 
 }  // namespace jc_rt
 

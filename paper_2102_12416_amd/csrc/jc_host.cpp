@@ -137,6 +137,8 @@ int validate_options(const jc_options* opt)
     }
     if (opt->z_chunk < 0)
         return fail(JC_ERR_INVALID, "options.z_chunk must be >= 0");
+    if (opt->temporal != 0 && opt->temporal != 1)
+        return fail(JC_ERR_INVALID, "options.temporal must be 0 or 1");
     if (opt->ir_enable && opt->ir_dtype != JC_F64 && opt->ir_dtype != JC_F32 && opt->ir_dtype != JC_BF16)
         return fail(JC_ERR_INVALID, "options.ir_dtype must be JC_F64, JC_F32 or JC_BF16 when ir_enable is set");
     return JC_OK;
@@ -229,6 +231,8 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         return fail(JC_ERR_INVALID, "too many face pairs for one launch");
     if (c->nb() > 65535)
         return fail(JC_ERR_INVALID, "too many blocks for one launch");
+    if (c->opt.temporal && c->nb() != 1)
+        return fail(JC_ERR_INVALID, "options.temporal needs a context of one block (no face pairs)");
     default_tiles(c, &c->tile_x, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
@@ -495,6 +499,24 @@ int do_sweep(jc_ctx* c, bool fused, bool resid)
     return JC_OK;
 }
 
+// Two sweeps in one launch (temporal blocking; one block, no pairs).
+int do_sweep2(jc_ctx* c)
+{
+    const HostBlock& b = c->blocks[0];
+    const int zc = std::max(c->z_chunk, jc_rt::kTwoStepMinZ);
+    int st = timed(c, JC_K_SWEEP2, [&] {
+        return jc::launch_sweep2(c->d_blocks(), (int)b.n[0], (int)b.n[1], (int)b.n[2], c->parity,
+                                 jc_rt::kTwoStepRows, zc, c->opt.with_source != 0, c->stream);
+    });
+    if (st != JC_OK)
+        return st;
+    c->parity ^= 1;
+    c->iters += 2;
+    c->ghost = GHOST_CURRENT;
+    c->fused_primed = c->opt.mode == JC_MODE_FUSED;
+    return JC_OK;
+}
+
 int do_halo(jc_ctx* c)
 {
     if (c->np() == 0) {
@@ -575,6 +597,26 @@ int residual_now(jc_ctx* c, double* l2)
     return JC_OK;
 }
 
+// n plain iterations launched eagerly: with temporal blocking, pairs of
+// sweeps in one launch each and a last single sweep when n is odd.
+int iterate_eager(jc_ctx* c, int64_t n)
+{
+    int64_t i = 0;
+    if (c->opt.temporal) {
+        for (; i + 2 <= n; i += 2) {
+            int st = do_sweep2(c);
+            if (st != JC_OK)
+                return st;
+        }
+    }
+    for (; i < n; ++i) {
+        int st = one_iteration(c, false);
+        if (st != JC_OK)
+            return st;
+    }
+    return JC_OK;
+}
+
 // n plain iterations, as one graph replay when graphs are enabled.
 int iterate_window(jc_ctx* c, int64_t n)
 {
@@ -582,14 +624,8 @@ int iterate_window(jc_ctx* c, int64_t n)
         return JC_OK;
     const bool graphs = c->opt.use_graphs && c->stream != nullptr && !c->timing &&
                         c->opt.exchange == JC_EXCHANGE_DEVICE;
-    if (!graphs) {
-        for (int64_t i = 0; i < n; ++i) {
-            int st = one_iteration(c, false);
-            if (st != JC_OK)
-                return st;
-        }
-        return JC_OK;
-    }
+    if (!graphs)
+        return iterate_eager(c, n);
     // the priming pack of fused mode stays outside the graph
     if (c->opt.mode == JC_MODE_FUSED && !c->fused_primed && c->np()) {
         int st = do_pack(c, c->parity);
@@ -605,9 +641,7 @@ int iterate_window(jc_ctx* c, int64_t n)
         const int ghost0 = c->ghost;
         const bool primed0 = c->fused_primed;
         JC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        int st = JC_OK;
-        for (int64_t i = 0; i < n && st == JC_OK; ++i)
-            st = one_iteration(c, false);
+        int st = iterate_eager(c, n);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &graph);
         // capture only recorded the launches: restore the state and replay
@@ -630,7 +664,9 @@ int iterate_window(jc_ctx* c, int64_t n)
     }
     JC_HIP(hipGraphLaunch(found->second, c->stream));
     // the state after n iterations, as the eager path would leave it
-    c->parity ^= (int)(n & 1);
+    // (a two-sweep launch flips the copy once)
+    const int64_t launches = c->opt.temporal ? n / 2 + (n & 1) : n;
+    c->parity ^= (int)(launches & 1);
     c->iters += n;
     if (c->np()) {
         c->ghost = GHOST_STALE;

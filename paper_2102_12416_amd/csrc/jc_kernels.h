@@ -19,6 +19,12 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
                         int tile_x, int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
                         hipStream_t s);
 
+// Two sweeps of the single block of a context without face pairs in one
+// launch (binary64): iterate k from copy parity, iterate k + 2 into copy
+// parity ^ 1.  Tiles of 64 cells by tile_y (8 or 16) rows by z_chunk planes.
+hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
+                         bool src, hipStream_t s);
+
 // Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
 // of d and r_lo).  Residual: r of u[parity] with fused ghosts (face
 // buffers of slot parity), partial sums of r^2, r rounded into r_lo.

@@ -656,6 +656,204 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
 
 // ---- sweep kernel: end ----
 
+// ---- two-step sweep (temporal blocking) ----
+// Two Jacobi sweeps of a single-block binary64 context per launch: iterate
+// k is read from copy p and iterate k + 2 written to copy p ^ 1; iterate
+// k + 1 lives only in LDS and registers.  Each cell's two updates take
+// the same sums in the same order as two one-step sweeps, so the result
+// is bitwise the same; HBM moves one read and one write per cell for two
+// sweeps instead of two of each.
+//
+// A work-group owns a tile of 2 TXP x cells by TY rows and a z range, and
+// marches along z as the one-step sweep does.  Iterate k + 1 is needed on
+// the tile and on a one-cell ring around it, so iterate k is loaded on a
+// two-cell ring: one aligned pair per thread over (TXP + 2) pairs by (TY +
+// 4) rows.  The first TXP * TY threads (whole waves) own the tile's pairs,
+// the next 4 (TXP + 2) the two rows above and the two rows below it, the
+// next 2 TY the pair left and the pair right of each tile row.  At plane
+// step s every thread writes iterate k of its pair at plane s into LDS,
+// the work-group synchronises once, every thread computes iterate k + 1 of
+// its pair at plane s (a ghost cell keeps its value: the context has no
+// face pairs, so every ghost is a Dirichlet value) into a second LDS
+// plane, and the tile threads compute iterate k + 2 at plane s - 1 from
+// the previous step's second plane.  Both LDS planes are double-buffered
+// by step parity.  Values at cells two steps out of the block (the
+// outermost ring of a tile on the block edge) are clamped loads that only
+// feed discarded results.
+template <int TXP, int TY, bool SRC>
+__global__ void __launch_bounds__(((TXP + 2) * (TY + 4) + 63) / 64 * 64)
+k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tiles_y, int nch, int ntiles)
+{
+    constexpr int EP = TXP + 2;                   // pairs of an extended row
+    constexpr int ER = TY + 4;                    // extended rows
+    constexpr int NTILE = TXP * TY;               // tile threads
+    static_assert(NTILE % 64 == 0, "tile threads are whole waves");
+    constexpr int LW = 2 * EP + 2;                // LDS row: pad, 2 EP cells, pad
+    constexpr int LN = (ER + 2) * LW;             // LDS plane: pad row, ER rows, pad row
+    __shared__ double A[2][LN + 1];               // iterate k; element LN: sink of idle lanes
+    __shared__ double Bn[2][LN + 1];              // iterate k + 1
+
+    const int id = logical_block(blockIdx.x, gridDim.x);
+    if (id >= ntiles)
+        return;                                   // uniform over the work-group
+    const BlockDesc* B = blocks;
+    const int p = parity;
+    const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+    const int per = tiles_x * tiles_y;
+    const int chunk = id / per;
+    const int x0 = (id % tiles_x) * (2 * TXP);
+    const int y0 = ((id % per) / tiles_x) * TY;
+    const int z0 = (int)((int64_t)chunk * nz / nch);
+    const int zf = z0 + 1;
+    const int zl = (int)((int64_t)(chunk + 1) * nz / nch);
+
+    // this thread's pair (j, r) of the extended region
+    const int t = threadIdx.x;
+    int j = 0, r = 0;
+    bool live = true;
+    if (t < NTILE) {
+        j = 1 + t % TXP;
+        r = 2 + t / TXP;
+    } else {
+        int q = t - NTILE;
+        if (q < 2 * EP) {
+            j = q % EP;
+            r = q / EP;
+        } else if ((q -= 2 * EP) < 2 * EP) {
+            j = q % EP;
+            r = TY + 2 + q / EP;
+        } else if ((q -= 2 * EP) < 2 * TY) {
+            j = (q & 1) ? EP - 1 : 0;
+            r = 2 + (q >> 1);
+        } else {
+            live = false;
+        }
+    }
+    const bool tile = t < NTILE;                  // uniform over each wave
+    const int xs = x0 - 1 + 2 * j;                // cells xs, xs + 1 (xs odd, >= -1)
+    const int ye = y0 - 1 + r;
+    const int xs_c = min(xs, nx | 1);             // last pair holding a cell <= nx + 1
+    const int ye_c = min(max(ye, 0), ny + 1);
+    const bool y_in = ye >= 1 && ye <= ny;
+    const bool in_a = live && y_in && xs >= 1 && xs <= nx;
+    const bool in_b = live && y_in && xs + 1 >= 1 && xs + 1 <= nx;
+    const bool a_ok = tile && ye <= ny && xs <= nx;   // tile cells in the block: stored
+    const bool b_ok = tile && ye <= ny && xs + 1 <= nx;
+    const int64_t pitch = B->pitch;
+    const int64_t plane = B->plane;
+    const int64_t rowoff = (int64_t)ye_c * pitch + xs_c;
+    const double* __restrict__ col = B->u[p] + rowoff;
+    const double* __restrict__ scol = SRC ? B->b + rowoff : nullptr;
+    double* __restrict__ dst = B->u[p ^ 1] + rowoff;
+
+    const int base = (r + 1) * LW + 2 * j + 1;    // LDS slot of cell xs
+    const int wa = live ? base : LN;
+    const int wb = live ? base + 1 : LN;
+
+    // register rings: iterate k and the source of plane s in slot
+    // (s - zf + 1) mod RS, loads issued PD planes ahead; iterate k + 1 of
+    // plane s in slot (s - zf + 1) mod 3
+    constexpr int PD = 3;
+    constexpr int RS = 6;
+    const int zhi = min(zl + 2, nz + 1);          // last plane read
+    double ua[RS], ub[RS], ba[RS], bb[RS], va[3], vb[3];
+#pragma unroll
+    for (int k = 0; k < RS; ++k)
+        ba[k] = bb[k] = 0.0;
+    va[0] = vb[0] = va[1] = vb[1] = va[2] = vb[2] = 0.0;
+    Tr<double>::ld(col + (int64_t)max(zf - 2, 0) * plane, ua[RS - 1], ub[RS - 1]);
+#pragma unroll
+    for (int k = 0; k < PD; ++k) {
+        const int64_t zk = (int64_t)min(zf - 1 + k, zhi) * plane;
+        Tr<double>::ld(col + zk, ua[k], ub[k]);
+        if (SRC)
+            Tr<double>::ld(scol + zk, ba[k], bb[k]);
+    }
+
+    auto step = [&](int s, auto kc, auto two) {
+        constexpr int K = decltype(kc)::value;
+        constexpr bool TWO = decltype(two)::value;
+        constexpr int SM = (K + RS - 1) % RS, SC = K, SP = (K + 1) % RS, SQ = (K + PD) % RS;
+        constexpr int VC = K % 3, VM = (K + 2) % 3, VMM = (K + 1) % 3;
+        constexpr int HC = K & 1;
+        const int64_t zq = (int64_t)min(s + PD, zhi) * plane;
+        Tr<double>::ld(col + zq, ua[SQ], ub[SQ]);
+        if (SRC)
+            Tr<double>::ld(scol + zq, ba[SQ], bb[SQ]);
+        double* const Ak = A[HC];
+        Ak[wa] = ua[SC];
+        Ak[wb] = ub[SC];
+        __syncthreads();
+        // iterate k + 1 at plane s
+        double sa = Ak[base - 1] + ub[SC];
+        sa = sa + Ak[base - LW];
+        sa = sa + Ak[base + LW];
+        sa = sa + ua[SM];
+        sa = sa + ua[SP];
+        double sb = ua[SC] + Ak[base + 2];
+        sb = sb + Ak[base + 1 - LW];
+        sb = sb + Ak[base + 1 + LW];
+        sb = sb + ub[SM];
+        sb = sb + ub[SP];
+        double na, nb;
+        if (SRC)
+            div6_pair(sa + ba[SC], sb + bb[SC], na, nb);
+        else
+            div6_pair(sa, sb, na, nb);
+        const bool z_in = s >= 1 && s <= nz;
+        va[VC] = (in_a && z_in) ? na : ua[SC];
+        vb[VC] = (in_b && z_in) ? nb : ub[SC];
+        Bn[HC][wa] = va[VC];
+        Bn[HC][wb] = vb[VC];
+        // iterate k + 2 at plane s - 1
+        if (TWO && tile) {
+            const double* const Bk = Bn[HC ^ 1];
+            double qa = Bk[base - 1] + vb[VM];
+            qa = qa + Bk[base - LW];
+            qa = qa + Bk[base + LW];
+            qa = qa + va[VMM];
+            qa = qa + va[VC];
+            double qb = va[VM] + Bk[base + 2];
+            qb = qb + Bk[base + 1 - LW];
+            qb = qb + Bk[base + 1 + LW];
+            qb = qb + vb[VMM];
+            qb = qb + vb[VC];
+            double wa2, wb2;
+            if (SRC)
+                div6_pair(qa + ba[SM], qb + bb[SM], wa2, wb2);
+            else
+                div6_pair(qa, qb, wa2, wb2);
+            // past the last cell of a row the pair's second slot is the
+            // x = nx + 1 ghost: write back the value it holds
+            wb2 = b_ok ? wb2 : ub[SM];
+            if (a_ok)
+                Tr<double>::stn(dst + (int64_t)(s - 1) * plane, wa2, wb2);
+        }
+    };
+    using F_ = std::false_type;
+    using T_ = std::true_type;
+#define JC_STEP2(k) step(s + (k), std::integral_constant<int, ((k) + 2) % RS>{}, T_{})
+    int s = zf - 1;
+    step(s, std::integral_constant<int, 0>{}, F_{});
+    step(s + 1, std::integral_constant<int, 1>{}, F_{});
+    s += 2;
+    const int s_end = zl + 1;
+    for (; s + 5 <= s_end; s += 6) {
+        JC_STEP2(0);
+        JC_STEP2(1);
+        JC_STEP2(2);
+        JC_STEP2(3);
+        JC_STEP2(4);
+        JC_STEP2(5);
+    }
+    if (s <= s_end) JC_STEP2(0);
+    if (s + 1 <= s_end) JC_STEP2(1);
+    if (s + 2 <= s_end) JC_STEP2(2);
+    if (s + 3 <= s_end) JC_STEP2(3);
+    if (s + 4 <= s_end) JC_STEP2(4);
+#undef JC_STEP2
+}
+
 // First inner sweep of a refinement step: d_1 = lo((0 + r_lo) / 6)
 // (d_0 = 0, so no neighbour is read); writes copy 1 of d and its faces.
 template <typename T>
@@ -921,6 +1119,30 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
                                                              resid, store, partials, s)
                : sweep_tiles<double, FIELD_U, false, NoRlo>(blocks, items, nitems, parity, tile_x, tile_y, fused,
                                                               resid, store, partials, s);
+}
+
+hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
+                         bool src, hipStream_t s)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || z_chunk < 1)
+        return hipErrorInvalidValue;
+    const int64_t tx = (nx + 63) / 64, ty = (ny + tile_y - 1) / tile_y, nch = (nz + z_chunk - 1) / z_chunk;
+    const int64_t n = tx * ty * nch;
+    if (n > ((int64_t)1 << 30))
+        return hipErrorInvalidValue;
+    const int grid = (int)((n + 7) / 8 * 8);
+#define JC_SWEEP2_CASE(TY, SRC)                                                                               \
+    if (tile_y == TY && src == SRC) {                                                                        \
+        hipLaunchKernelGGL((k_sweep2<32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, s, blocks, \
+                           parity, (int)tx, (int)ty, (int)nch, (int)n);                                      \
+        return hipGetLastError();                                                                            \
+    }
+    JC_SWEEP2_CASE(8, false)
+    JC_SWEEP2_CASE(8, true)
+    JC_SWEEP2_CASE(16, false)
+    JC_SWEEP2_CASE(16, true)
+#undef JC_SWEEP2_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_x,

@@ -40,6 +40,7 @@ def create(grid, bd, **kw):
     opt.tile_y = kw.get("tile_y", 0)
     opt.z_chunk = kw.get("z_chunk", 0)
     opt.tile_x = kw.get("tile_x", 0)
+    opt.temporal = kw.get("temporal", 0)
     ctx = ctypes.c_void_p()
     st = L.lib.jc_create(L.i64(grid), L.i64(bd), ctypes.byref(opt), ctypes.byref(ctx))
     return st, ctx
@@ -294,6 +295,16 @@ def test_sixteen_cell_tile_options():
     check(L.lib.jc_tile_info(ctx, out))
     assert out[0] == 16 and out[1] >= 8
     L.lib.jc_destroy(ctx)
+
+
+def test_temporal_option_needs_one_block():
+    st, ctx = create((40, 24, 24), (40, 24, 24), temporal=1)
+    assert st == 0
+    L.lib.jc_destroy(ctx)
+    st, _ = create((40, 24, 24), (20, 24, 24), temporal=1)
+    assert st == L.JC_ERR_INVALID and "one block" in L.last_error()
+    st, _ = create((8, 8, 8), (8, 8, 8), temporal=2)
+    assert st == L.JC_ERR_INVALID and "temporal" in L.last_error()
 
 
 def test_default_tile_width_prefers_fewer_idle_lanes():

@@ -1,0 +1,118 @@
+"""Temporal blocking (two sweeps per launch) against the CPU oracle.
+
+The two-sweep kernel gives every cell's two updates the same sums in the
+same order as two one-sweep launches (iterate k + 1 stays in LDS and
+registers), so the iterate is expected bitwise equal to the oracle's after
+any number of sweeps; an odd count ends with one single sweep."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+from paper_2102_12416_amd import Solver, _lib as L  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
+@pytest.mark.parametrize("n,iters,src,zc", [
+    ((64, 64, 64), 10, False, 0),
+    ((70, 19, 37), 7, True, 0),          # ragged tile in x and y, odd count
+    ((130, 33, 97), 8, False, 32),       # three z chunks, three x tiles
+    ((1, 1, 1), 5, False, 0),
+    ((2, 3, 1), 4, True, 0),
+    ((65, 17, 70), 9, True, 16),         # z_chunk below the two-sweep minimum
+    ((127, 40, 33), 6, False, 0),        # odd nx: the last pair holds the x ghost
+])
+def test_temporal_vs_oracle(mode, n, iters, src, zc):
+    say("temporal", mode, n, iters, "source" if src else "", "z_chunk", zc)
+    u0 = synth.boundary_field(n, seed=7)
+    b = synth.source_field(n, seed=7) if src else None
+    ref, _ = oracle.c_jacobi(u0, iters, b)
+    for graphs in (False, True):
+        with Solver(n, mode=mode, with_source=src, temporal=True, z_chunk=zc, use_graphs=graphs) as s:
+            s.load(u0, b)
+            s.iterate(iters)
+            got = s.store().cpu().numpy()
+            assert s.iterations == iters
+        assert np.array_equal(got, ref), (graphs, float(np.max(np.abs(got - ref))))
+
+
+def test_temporal_launch_counts():
+    """n sweeps take n // 2 two-sweep launches and n % 2 single sweeps."""
+    n = (40, 30, 20)
+    say("temporal launch counts")
+    with Solver(n, temporal=True, use_graphs=False) as s:
+        s.load(synth.boundary_field(n, seed=3))
+        s.set_timing(True)
+        s.iterate(7)
+        assert s.kernel_time(L.JC_K_SWEEP2)[1] == 3
+        assert s.kernel_time(L.JC_K_SWEEP)[1] == 1
+        s.iterate(4)
+        assert s.kernel_time(L.JC_K_SWEEP2)[1] == 5
+        assert s.kernel_time(L.JC_K_SWEEP)[1] == 1
+        assert s.iterations == 11
+
+
+@pytest.mark.parametrize("src", [False, True])
+def test_temporal_solve_matches_one_sweep_launches(src):
+    """jc_solve with temporal blocking: the same checks, residual history,
+    stop and iterate as with one sweep per launch."""
+    n = (48, 40, 36)
+    say("temporal solve", "source" if src else "")
+    u0 = synth.boundary_field(n, seed=11)
+    b = synth.source_field(n, seed=11) if src else None
+    out = []
+    for temporal in (False, True):
+        with Solver(n, with_source=src, temporal=temporal) as s:
+            s.load(u0, b)
+            info = s.solve(rtol=1e-6, max_iter=5000, check_every=25, history=True)
+            out.append((info, s.store().cpu().numpy()))
+    (i0, u_0), (i1, u_1) = out
+    assert i0["converged"] and i1["converged"]
+    assert i0["iters"] == i1["iters"]
+    assert i0["history"] == i1["history"]
+    assert np.array_equal(u_0, u_1)
+    ref, _ = oracle.c_jacobi(u0, i1["iters"], b)
+    assert np.array_equal(u_1, ref)
+
+
+def test_temporal_full_size_paper_share():
+    """The per-GPU block of the paper's largest Jacobi3D run (512 x 768 x
+    1536, one block) in the launch configuration the benchmark times with
+    temporal blocking (fused mode, graph replay): sampled cells after 6
+    sweeps equal the oracle's local computation; after 41 sweeps the
+    iterate equals the one-sweep launches bit for bit."""
+    import torch
+    from paper_2102_12416_amd import synth_field
+    n, seed = (512, 768, 1536), 12416
+    say("temporal 512x768x1536, sampled + bitwise vs one-sweep launches")
+    rng = np.random.default_rng(5)
+    cells = [tuple(int(rng.integers(1, m + 1)) for m in (n[2], n[1], n[0])) for _ in range(16)]
+    cells += [(1, 1, 1), (1536, 768, 512), (1, 768, 1), (1536, 1, 512), (768, 384, 256), (2, 17, 511)]
+    with Solver(n, mode="fused", temporal=True) as s:
+        s.load(synth_field(n, seed, 0))
+        s.iterate(6)
+        u = s.store()
+        idx = torch.tensor(cells, device=u.device)
+        got = u[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+        del u
+        for c, v in zip(cells, got):
+            lo = [max(0, c[a] - 7) for a in range(3)]
+            hi = [min((n[2], n[1], n[0])[a] + 2, c[a] + 8) for a in range(3)]
+            box = synth.field_box(n, 0, lo, hi, seed=seed)
+            for _ in range(6):
+                box = oracle.sweep(box)
+            assert v == box[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]], c
+        s.iterate(35)
+        assert s.iterations == 41
+        a = s.store()
+        with Solver(n, mode="fused") as one:
+            one.load(synth_field(n, seed, 0))
+            one.iterate(41)
+            assert torch.equal(a, one.store())
