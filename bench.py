@@ -58,6 +58,12 @@ TUNED_TILES = {
     ("512_2x2x2", "staged"): (64, 32, 64),
 }
 
+# two-sweep launch shape (rows, planes per work-group) from jc_autotune on
+# MI355X: 24-row tiles, one work-group per compute unit over the whole depth
+TUNED_TEMPORAL = {
+    "paper_share": (24, 1536),
+}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -89,6 +95,8 @@ def parse():
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
     ap.add_argument("--temporal", action="store_true",
                     help="one-block workloads: two sweeps per launch (temporal blocking)")
+    ap.add_argument("--temporal-tile", default="",
+                    help="rows,z_chunk of the two-sweep launch (16 or 24 rows; default: stored or autotuned)")
     ap.add_argument("--seed", type=int, default=12416)
     ap.add_argument("--tile-x", type=int, default=0, help="cells per tile row, 32 or 64 (0: library default)")
     ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")
@@ -513,7 +521,18 @@ def main():
     nb = s.num_blocks
     given = bool(args.tile_x or args.tile_y or args.z_chunk)
     tile_source = "given" if given else "library default"
-    if not given:
+    if temporal:
+        # the timed launches are all two-sweep launches: tune their shape
+        if args.temporal_tile:
+            s.set_temporal_tiles(*[int(v) for v in args.temporal_tile.split(",")])
+            tile_source = "given"
+        elif args.workload in TUNED_TEMPORAL and not args.autotune:
+            s.set_temporal_tiles(*TUNED_TEMPORAL[args.workload])
+            tile_source = "tuned (jc_autotune on MI355X)"
+        else:
+            s.autotune(reps=3)
+            tile_source = "jc_autotune at start-up"
+    elif not given:
         if (args.workload, mode) in TUNED_TILES and not args.autotune:
             s.set_tiles(*TUNED_TILES[(args.workload, mode)])
             tile_source = "tuned (jc_autotune on MI355X)"
@@ -595,6 +614,8 @@ def main():
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
                    "temporal": temporal,
+                   "temporal_tile": ([s.temporal_info()["rows"], s.temporal_info()["z_chunk"]]
+                                     if temporal else None),
                    "tile_source": tile_source,
                    "launch": "hipGraph replay of the timed window" if graphs else "eager, HIP events per launch",
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},

@@ -316,6 +316,16 @@ int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed
  * when bound). */
 int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 
+/* Shape of the two-sweep launch of temporal blocking: rows of its tile
+ * (16 or 24; the tile is 64 cells wide) and planes per work-group (>= 1).
+ * Results are bitwise independent of it.  JC_ERR_STATE unless the context
+ * was created with temporal = 1. */
+int jc_set_temporal_tiles(jc_ctx* ctx, int rows, int z_chunk);
+/* out = {temporal (0 or 1), rows, planes per work-group} of the two-sweep
+ * launch.  Until set (jc_set_temporal_tiles or jc_autotune), the planes
+ * follow the one-sweep z_chunk, at least 32. */
+int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
+
 /* Time `reps` sweeps of every valid candidate shape (tile_x in {64, 32,
  * 16} x tile_y in {4, 8, 16, 32} x z_chunk in {16, 32, 64, ..., depth}) on
  * the bound stream after at least 150 ms of warm-up sweeps, time the four
@@ -325,9 +335,13 @@ int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
  * context with refinement buffers (ir_enable), the inner sweep of the
  * correction (the refinement arrays are zeroed first; every refinement
  * step rebuilds them; JC_ERR_STATE while a group's refinement step is in
- * progress on the context).  The trial sweeps write only the other
- * ping-pong copy and face slot, so the current iterate and iteration count
- * are unchanged.  Waits for the stream.  Needs a loaded context. */
+ * progress on the context).  With temporal = 1 the two-sweep launch is
+ * then timed over rows {16, 24} x z chunks of 1/1 .. 1/16 of the depth
+ * (max(reps, 2) launches each, the three fastest again over three rounds)
+ * and the fastest kept (jc_temporal_info).  The trial sweeps write only
+ * the other ping-pong copy and face slot, so the current iterate and
+ * iteration count are unchanged.  Waits for the stream.  Needs a loaded
+ * context. */
 int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);
 
 /* ---- measurement ----------------------------------------------------- */

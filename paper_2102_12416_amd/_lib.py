@@ -97,6 +97,8 @@ SIGNATURES = {
     "jc_tile_info": (ctypes.c_int, [CTX, I64P]),
     "jc_set_tiles": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "jc_autotune": (ctypes.c_int, [CTX, ctypes.c_int, I64P]),
+    "jc_set_temporal_tiles": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.c_int]),
+    "jc_temporal_info": (ctypes.c_int, [CTX, I64P]),
     "jc_set_timing": (ctypes.c_int, [CTX, ctypes.c_int]),
     "jc_kernel_time": (ctypes.c_int, [CTX, ctypes.c_int, ctypes.POINTER(ctypes.c_double), I64P]),
 }

@@ -85,10 +85,12 @@ inline bool tile_shape_ok(int tile_x, int tile_y)
     return ok_x && ok_y && (tile_x / 2) * tile_y >= 64;
 }
 constexpr int kMinZChunk = 16;
-// Temporal blocking: rows of the two-sweep tile (64 cells wide) and the
-// fewest planes per work-group (each reads two planes beyond each end).
+// Temporal blocking: default rows of the two-sweep tile (64 cells wide;
+// 16 or 24) and the fewest planes per work-group when the chunk follows
+// the one-sweep z_chunk (each work-group reads two planes beyond each end).
 constexpr int kTwoStepRows = 16;
 constexpr int kTwoStepMinZ = 32;
+inline bool two_step_rows_ok(int rows) { return rows == 16 || rows == 24; }
 
 }  // namespace jc_rt
 
@@ -109,6 +111,10 @@ struct jc_ctx {
     int tile_x = 64;
     int tile_y = 8;
     int z_chunk = 0;
+    // temporal blocking: rows and planes of the two-sweep work-group
+    // (t2_zc 0: the one-sweep z_chunk, at least kTwoStepMinZ)
+    int t2_rows = jc_rt::kTwoStepRows;
+    int t2_zc = 0;
     std::vector<Item> items;
     int64_t max_items = 0;
     // arena layout

@@ -499,15 +499,22 @@ int do_sweep(jc_ctx* c, bool fused, bool resid)
     return JC_OK;
 }
 
+int two_step_chunk(const jc_ctx* c)
+{
+    return c->t2_zc > 0 ? c->t2_zc : std::max(c->z_chunk, jc_rt::kTwoStepMinZ);
+}
+
+hipError_t launch_two_step(jc_ctx* c, int rows, int zc)
+{
+    const HostBlock& b = c->blocks[0];
+    return jc::launch_sweep2(c->d_blocks(), (int)b.n[0], (int)b.n[1], (int)b.n[2], c->parity, rows, zc,
+                             c->opt.with_source != 0, c->stream);
+}
+
 // Two sweeps in one launch (temporal blocking; one block, no pairs).
 int do_sweep2(jc_ctx* c)
 {
-    const HostBlock& b = c->blocks[0];
-    const int zc = std::max(c->z_chunk, jc_rt::kTwoStepMinZ);
-    int st = timed(c, JC_K_SWEEP2, [&] {
-        return jc::launch_sweep2(c->d_blocks(), (int)b.n[0], (int)b.n[1], (int)b.n[2], c->parity,
-                                 jc_rt::kTwoStepRows, zc, c->opt.with_source != 0, c->stream);
-    });
+    int st = timed(c, JC_K_SWEEP2, [&] { return launch_two_step(c, c->t2_rows, two_step_chunk(c)); });
     if (st != JC_OK)
         return st;
     c->parity ^= 1;
@@ -680,6 +687,80 @@ void free_graphs(jc_ctx* c)
     for (auto& kv : c->graphs)
         (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+}
+
+// Times the two-sweep launch over tile rows {16, 24} x z-chunk counts and
+// keeps the fastest (temporal contexts; run by jc_autotune after its
+// one-sweep search, on a warm device).  Which shape wins depends on how
+// the work-groups fill the compute units and on how close in time
+// neighbouring tiles read their shared halo rows (an L2 hit), so it is
+// measured rather than modelled.  Trial launches read copy `parity` and
+// write the other copy: the iterate is unchanged.
+int tune_two_step(jc_ctx* c, int reps)
+{
+    const int64_t nz = c->blocks[0].n[2];
+    struct Cand {
+        int rows, zc;
+        double ms;
+    };
+    std::vector<Cand> cand;
+    for (int rows : {16, 24})
+        for (int nch : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            const int zc = (int)((nz + nch - 1) / nch);
+            bool dup = false;
+            for (const Cand& k : cand)
+                dup = dup || (k.rows == rows && k.zc == zc);
+            if (!dup)
+                cand.push_back({rows, zc, 0.0});
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    JC_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(JC_ERR_DEVICE, "autotune: hipEventCreate failed");
+    }
+    // milliseconds of n launches after one untimed launch
+    auto time_one = [&](const Cand& k, int n, double& ms) -> int {
+        hipError_t e = launch_two_step(c, k.rows, k.zc);
+        if (e == hipSuccess)
+            e = hipEventRecord(e0, c->stream);
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            e = launch_two_step(c, k.rows, k.zc);
+        if (e == hipSuccess)
+            e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(e1);
+        float t = 0;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&t, e0, e1);
+        ms = t;
+        return e == hipSuccess ? JC_OK
+                               : fail(JC_ERR_DEVICE, std::string("autotune (two-sweep launch): ") + hipGetErrorString(e));
+    };
+    int st = JC_OK;
+    for (size_t i = 0; i < cand.size() && st == JC_OK; ++i)
+        st = time_one(cand[i], reps, cand[i].ms);
+    if (st == JC_OK) {
+        std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+        cand.resize(std::min<size_t>(cand.size(), 3));
+        for (Cand& k : cand)
+            k.ms = 0;
+        for (int round = 0; round < 3 && st == JC_OK; ++round)
+            for (size_t i = 0; i < cand.size() && st == JC_OK; ++i) {
+                double ms = 0;
+                st = time_one(cand[i], reps, ms);
+                cand[i].ms += ms;
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != JC_OK)
+        return st;
+    const Cand best = *std::min_element(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+    c->t2_rows = best.rows;
+    c->t2_zc = best.zc;
+    free_graphs(c);
+    return JC_OK;
 }
 
 }  // namespace
@@ -1258,6 +1339,30 @@ int jc_set_tiles(jc_ctx* c, int tile_x, int tile_y, int z_chunk)
     return JC_OK;
 }
 
+int jc_set_temporal_tiles(jc_ctx* c, int rows, int z_chunk)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (!c->opt.temporal)
+        return fail(JC_ERR_STATE, "the context was created without temporal blocking");
+    if (!jc_rt::two_step_rows_ok(rows) || z_chunk < 1)
+        return fail(JC_ERR_INVALID, "rows must be 16 or 24 and z_chunk >= 1");
+    c->t2_rows = rows;
+    c->t2_zc = z_chunk;
+    free_graphs(c);                        // graphs hold the old launch shapes
+    return JC_OK;
+}
+
+int jc_temporal_info(const jc_ctx* c, int64_t out[3])
+{
+    if (!c || !out)
+        return fail(JC_ERR_INVALID, "NULL argument");
+    out[0] = c->opt.temporal;
+    out[1] = c->t2_rows;
+    out[2] = two_step_chunk(c);
+    return JC_OK;
+}
+
 int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
 {
     int st = check_ready(c);
@@ -1377,6 +1482,11 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
     const Shape best = *std::min_element(cand.begin(), cand.end(),
                                          [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
     st = jc_set_tiles(c, best.x, best.y, best.z);
+    if (st == JC_OK && c->opt.temporal) {
+        c->timing = false;
+        st = tune_two_step(c, std::max(reps, 2));
+        c->timing = was_timing;
+    }
     if (st != JC_OK)
         return st;
     out[0] = best.x;

@@ -21,7 +21,7 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 
 // Two sweeps of the single block of a context without face pairs in one
 // launch (binary64): iterate k from copy parity, iterate k + 2 into copy
-// parity ^ 1.  Tiles of 64 cells by tile_y (8 or 16) rows by z_chunk planes.
+// parity ^ 1.  Tiles of 64 cells by tile_y (8, 16 or 24) rows by z_chunk planes.
 hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
                          bool src, hipStream_t s);
 

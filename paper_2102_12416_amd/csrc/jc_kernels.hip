@@ -1141,6 +1141,8 @@ hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int pa
     JC_SWEEP2_CASE(8, true)
     JC_SWEEP2_CASE(16, false)
     JC_SWEEP2_CASE(16, true)
+    JC_SWEEP2_CASE(24, false)
+    JC_SWEEP2_CASE(24, true)
 #undef JC_SWEEP2_CASE
     return hipErrorInvalidValue;
 }

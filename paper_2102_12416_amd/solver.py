@@ -222,6 +222,14 @@ class Solver:
         check(L.lib.jc_tile_info(self._ctx, out))
         return dict(tile_x=out[0], tile_y=out[1], z_chunk=out[2], items=out[3])
 
+    def set_temporal_tiles(self, rows, z_chunk):
+        check(L.lib.jc_set_temporal_tiles(self._ctx, int(rows), int(z_chunk)))
+
+    def temporal_info(self):
+        out = (ctypes.c_int64 * 3)()
+        check(L.lib.jc_temporal_info(self._ctx, out))
+        return dict(temporal=bool(out[0]), rows=out[1], z_chunk=out[2])
+
     def arena_view(self, byte_off, count, dtype=torch.float64):
         """A tensor view of `count` elements of the arena at `byte_off` (tests)."""
         esz = torch.empty((), dtype=dtype).element_size()

@@ -307,6 +307,25 @@ def test_temporal_option_needs_one_block():
     assert st == L.JC_ERR_INVALID and "temporal" in L.last_error()
 
 
+def test_temporal_tile_shape():
+    out = (ctypes.c_int64 * 3)()
+    st, ctx = create((40, 24, 100), (40, 24, 100), temporal=1, z_chunk=16)
+    assert st == 0
+    check(L.lib.jc_temporal_info(ctx, out))
+    assert tuple(out) == (1, 16, 32)              # follows z_chunk, at least 32 planes
+    check(L.lib.jc_set_temporal_tiles(ctx, 24, 7))
+    check(L.lib.jc_temporal_info(ctx, out))
+    assert tuple(out) == (1, 24, 7)
+    assert L.lib.jc_set_temporal_tiles(ctx, 8, 7) == L.JC_ERR_INVALID
+    assert L.lib.jc_set_temporal_tiles(ctx, 16, 0) == L.JC_ERR_INVALID
+    L.lib.jc_destroy(ctx)
+    st, ctx = create((40, 24, 100), (40, 24, 100))
+    assert L.lib.jc_set_temporal_tiles(ctx, 16, 32) == L.JC_ERR_STATE
+    check(L.lib.jc_temporal_info(ctx, out))
+    assert out[0] == 0
+    L.lib.jc_destroy(ctx)
+
+
 def test_default_tile_width_prefers_fewer_idle_lanes():
     out = (ctypes.c_int64 * 4)()
     for grid, bd, want in (((768, 768, 768), (96, 96, 96), 32), ((512, 512, 512), (256, 256, 256), 64),

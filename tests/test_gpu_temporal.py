@@ -20,27 +20,52 @@ def say(*a):
 
 
 @pytest.mark.parametrize("mode", ["staged", "fused"])
-@pytest.mark.parametrize("n,iters,src,zc", [
-    ((64, 64, 64), 10, False, 0),
-    ((70, 19, 37), 7, True, 0),          # ragged tile in x and y, odd count
-    ((130, 33, 97), 8, False, 32),       # three z chunks, three x tiles
-    ((1, 1, 1), 5, False, 0),
-    ((2, 3, 1), 4, True, 0),
-    ((65, 17, 70), 9, True, 16),         # z_chunk below the two-sweep minimum
-    ((127, 40, 33), 6, False, 0),        # odd nx: the last pair holds the x ghost
+@pytest.mark.parametrize("rows", [16, 24])
+@pytest.mark.parametrize("n,iters,src,zc,t2zc", [
+    ((64, 64, 64), 10, False, 0, 0),
+    ((70, 19, 37), 7, True, 0, 0),          # ragged tile in x and y, odd count
+    ((130, 33, 97), 8, False, 32, 0),       # three z chunks, three x tiles
+    ((130, 50, 97), 6, True, 0, 13),        # eight uneven chunks of 12..13 planes
+    ((1, 1, 1), 5, False, 0, 0),
+    ((2, 3, 1), 4, True, 0, 1),
+    ((65, 17, 70), 9, True, 16, 0),         # z_chunk below the two-sweep minimum
+    ((127, 40, 33), 6, False, 0, 2),        # odd nx: the last pair holds the x ghost
 ])
-def test_temporal_vs_oracle(mode, n, iters, src, zc):
-    say("temporal", mode, n, iters, "source" if src else "", "z_chunk", zc)
+def test_temporal_vs_oracle(mode, rows, n, iters, src, zc, t2zc):
+    say("temporal", mode, "rows", rows, n, iters, "source" if src else "", "z_chunk", zc, t2zc)
     u0 = synth.boundary_field(n, seed=7)
     b = synth.source_field(n, seed=7) if src else None
     ref, _ = oracle.c_jacobi(u0, iters, b)
     for graphs in (False, True):
         with Solver(n, mode=mode, with_source=src, temporal=True, z_chunk=zc, use_graphs=graphs) as s:
+            if rows != 16 or t2zc:
+                s.set_temporal_tiles(rows, t2zc or s.temporal_info()["z_chunk"])
+            assert s.temporal_info()["rows"] == rows
             s.load(u0, b)
             s.iterate(iters)
             got = s.store().cpu().numpy()
             assert s.iterations == iters
         assert np.array_equal(got, ref), (graphs, float(np.max(np.abs(got - ref))))
+
+
+def test_temporal_autotune_keeps_results():
+    """jc_autotune on a temporal context also picks the two-sweep shape;
+    the iterate is unchanged by the trials and later sweeps stay exact."""
+    n = (100, 72, 90)
+    say("temporal autotune")
+    u0 = synth.boundary_field(n, seed=9)
+    b = synth.source_field(n, seed=9)
+    ref, _ = oracle.c_jacobi(u0, 12, b)
+    with Solver(n, with_source=True, temporal=True) as s:
+        s.load(u0, b)
+        s.iterate(5)
+        s.autotune(reps=2)
+        info = s.temporal_info()
+        assert info["rows"] in (16, 24) and info["z_chunk"] >= 1
+        assert s.iterations == 5
+        s.iterate(7)
+        got = s.store().cpu().numpy()
+    assert np.array_equal(got, ref)
 
 
 def test_temporal_launch_counts():
@@ -85,7 +110,8 @@ def test_temporal_solve_matches_one_sweep_launches(src):
 def test_temporal_full_size_paper_share():
     """The per-GPU block of the paper's largest Jacobi3D run (512 x 768 x
     1536, one block) in the launch configuration the benchmark times with
-    temporal blocking (fused mode, graph replay): sampled cells after 6
+    temporal blocking (fused mode, its stored two-sweep shape, graph
+    replay): sampled cells after 6
     sweeps equal the oracle's local computation; after 41 sweeps the
     iterate equals the one-sweep launches bit for bit."""
     import torch
@@ -95,7 +121,10 @@ def test_temporal_full_size_paper_share():
     rng = np.random.default_rng(5)
     cells = [tuple(int(rng.integers(1, m + 1)) for m in (n[2], n[1], n[0])) for _ in range(16)]
     cells += [(1, 1, 1), (1536, 768, 512), (1, 768, 1), (1536, 1, 512), (768, 384, 256), (2, 17, 511)]
+    from bench import TUNED_TEMPORAL
+    rows, zc = TUNED_TEMPORAL["paper_share"]
     with Solver(n, mode="fused", temporal=True) as s:
+        s.set_temporal_tiles(rows, zc)
         s.load(synth_field(n, seed, 0))
         s.iterate(6)
         u = s.store()
