@@ -157,17 +157,36 @@ def recorded_traffic(workload, mode, tile):
     return rec.get("traffic_bytes_per_launch")
 
 
-def sweep_source_sha256():
-    """Fingerprint of the sweep kernel: its region of jc_kernels.hip plus
-    the shared table definitions it reads."""
+def sweep_source_sha256(kernel="k_sweep"):
+    """Fingerprint of a sweep kernel: its region of jc_kernels.hip (the
+    one-sweep kernel with the helpers it defines; the two-sweep kernel
+    also with those helpers) plus the shared table definitions it reads."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2102_12416_amd", "csrc")
     text = open(os.path.join(csrc, "jc_kernels.hip")).read()
     a = text.index("// ---- sweep kernel: begin")
     b = text.index("// ---- sweep kernel: end")
     h = hashlib.sha256(text[a:b].encode())
+    if kernel == "k_sweep2":
+        c = text.index("// ---- two-step sweep (temporal blocking): begin")
+        d = text.index("// ---- two-step sweep: end")
+        h.update(text[c:d].encode())
     h.update(open(os.path.join(csrc, "jc_types.h"), "rb").read())
     return h.hexdigest()
+
+
+def recorded_traffic_temporal(workload, shape):
+    """HBM bytes per two-sweep launch from the committed rocprofv3 counters,
+    if taken on the current kernel source and the same shape (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_sweep2_%s_fp64.counters.json" % workload)
+    try:
+        rec = json.load(open(path))
+        sha = sweep_source_sha256("k_sweep2")
+    except (OSError, ValueError):
+        return None
+    if rec.get("sweep_source_sha256") != sha or list(rec.get("temporal_tile", [])) != list(shape):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def exchange_ab(grid, bd, seed, iters, tiles):
@@ -263,6 +282,19 @@ def bench_refinement(args):
         rates["f64_plain"] = dict(glups=lups * k / (ms * 1e-3) / 1e9, gbs=24 * lups * k / (ms * 1e-3) / 1e9,
                                   ms_per_sweep=ms / k)
         s.set_timing(False)
+    # the same binary64 sweeps, two per launch (temporal blocking): 24 bytes
+    # per cell per launch (read u and b, write u), 12 per update
+    with Solver(grid, with_source=True, use_graphs=False, temporal=True) as s:
+        s.load(g, b)
+        s.autotune(reps=2)
+        s.iterate(4)
+        s.set_timing(True)
+        s.iterate(2 * (args.ir_sweeps // 2))
+        ms, k = s.kernel_time(L.JC_K_SWEEP2)
+        t2 = s.temporal_info()
+        rates["f64_temporal"] = dict(glups=2 * lups * k / (ms * 1e-3) / 1e9, gbs=24 * lups * k / (ms * 1e-3) / 1e9,
+                                     ms_per_sweep=ms / (2 * k), tile=[t2["rows"], t2["z_chunk"]])
+        s.set_timing(False)
     for dt, inner_bytes in (("f32", 12), ("bf16", 6)):
         with Solver(grid, with_source=True, ir_dtype=dt, use_graphs=False) as s:
             s.load(g, b)
@@ -305,6 +337,15 @@ def bench_refinement(args):
                                     rel=info["rel_resid"], converged=info["converged"])
             u64 = s.store()          # the FP64 path is bitwise the oracle's Jacobi (parity tests)
             scale = float(u64.abs().max())
+        with Solver(gm, with_source=True, temporal=True) as s:
+            s.load(gg, bb)
+            s.autotune(reps=2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.solve(rtol=1e-10, max_iter=2000000, check_every=50)
+            row["f64_temporal"] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
+                                       rel=info["rel_resid"], converged=info["converged"],
+                                       bitwise_equal_f64_plain=bool(torch.equal(s.store(), u64)))
         for dt in ("f32", "bf16"):
             with Solver(gm, with_source=True, ir_dtype=dt) as s:
                 s.load(gg, bb)
@@ -580,6 +621,7 @@ def main():
     print("[bench] timed region done: %.3f s wall, %.3f ms on the stream" % (wall, gpu_ms), file=sys.stderr,
           flush=True)
 
+    t2_shape = [s.temporal_info()["rows"], s.temporal_info()["z_chunk"]] if temporal else None
     nx, ny, nz = grid
     lups = float(nx) * ny * nz
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
@@ -614,8 +656,7 @@ def main():
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
                    "temporal": temporal,
-                   "temporal_tile": ([s.temporal_info()["rows"], s.temporal_info()["z_chunk"]]
-                                     if temporal else None),
+                   "temporal_tile": t2_shape,
                    "tile_source": tile_source,
                    "launch": "hipGraph replay of the timed window" if graphs else "eager, HIP events per launch",
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
@@ -625,7 +666,7 @@ def main():
                      "kernel": "k_sweep2" if temporal else "k_sweep" if mode == "staged" else "k_sweep(fused)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if temporal else recorded_traffic(
+                     "traffic": recorded_traffic_temporal(args.workload, t2_shape) if temporal else recorded_traffic(
                          args.workload, mode, [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]]),
                      "bytes_per_launch": kernel_bytes, "avg_launch_ms": round(avg_ms, 5),
                      "bytes_per_unit": ("16 B per cell per two-sweep launch (8 B per update)" if temporal else

@@ -656,7 +656,7 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
 
 // ---- sweep kernel: end ----
 
-// ---- two-step sweep (temporal blocking) ----
+// ---- two-step sweep (temporal blocking): begin (fingerprinted with recorded counters) ----
 // Two Jacobi sweeps of a single-block binary64 context per launch: iterate
 // k is read from copy p and iterate k + 2 written to copy p ^ 1; iterate
 // k + 1 lives only in LDS and registers.  Each cell's two updates take
@@ -853,6 +853,7 @@ k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tile
     if (s + 4 <= s_end) JC_STEP2(4);
 #undef JC_STEP2
 }
+// ---- two-step sweep: end ----
 
 // First inner sweep of a refinement step: d_1 = lo((0 + r_lo) / 6)
 // (d_0 = 0, so no neighbour is read); writes copy 1 of d and its faces.

@@ -145,3 +145,31 @@ def test_temporal_full_size_paper_share():
             one.load(synth_field(n, seed, 0))
             one.iterate(41)
             assert torch.equal(a, one.store())
+
+
+def test_temporal_full_size_1024_source_sampled():
+    """1024^3 with a source, two sweeps per launch in the configuration the
+    refinement benchmark times (shape from jc_autotune, eager launches):
+    sampled cells after 6 sweeps equal the oracle's local computation."""
+    import torch
+    from paper_2102_12416_amd import synth_field
+    n, seed = (1024, 1024, 1024), 12416
+    say("temporal 1024^3 with source, sampled")
+    rng = np.random.default_rng(1024)
+    cells = [(1, 1, 1), (1024, 1024, 1024), (1, 512, 1024), (1024, 1, 513), (512, 512, 512), (513, 1024, 1)]
+    cells += [tuple(int(v) for v in rng.integers(1, 1025, 3)) for _ in range(8)]
+    with Solver(n, with_source=True, use_graphs=False, temporal=True) as s:
+        s.load(synth_field(n, seed, 0), synth_field(n, seed, 1))
+        s.autotune(reps=2)
+        s.iterate(6)
+        u = s.store()
+        idx = torch.tensor(cells, device=u.device)
+        got = u[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    for c, v in zip(cells, got):
+        lo = [max(0, c[a] - 7) for a in range(3)]
+        hi = [min(1026, c[a] + 8) for a in range(3)]
+        box = synth.field_box(n, 0, lo, hi, seed=seed)
+        bb = synth.field_box(n, 1, lo, hi, seed=seed)
+        for _ in range(6):
+            box = oracle.sweep(box, bb)
+        assert v == box[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]], c
