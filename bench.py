@@ -295,14 +295,22 @@ def bench_refinement(args):
         rates["f64_temporal"] = dict(glups=2 * lups * k / (ms * 1e-3) / 1e9, gbs=24 * lups * k / (ms * 1e-3) / 1e9,
                                      ms_per_sweep=ms / (2 * k), tile=[t2["rows"], t2["z_chunk"]])
         s.set_timing(False)
-    for dt, inner_bytes in (("f32", 12), ("bf16", 6)):
-        with Solver(grid, with_source=True, ir_dtype=dt, use_graphs=False) as s:
+    # refinement, one inner sweep per launch (12 / 6 bytes per update with
+    # r_lo), then two per launch (temporal blocking: 12 / 6 bytes per cell
+    # per launch, 6 / 3 per update)
+    for dt, inner_bytes, temporal in (("f32", 12, False), ("bf16", 6, False), ("f32", 12, True),
+                                      ("bf16", 6, True)):
+        tag = dt + ("_temporal" if temporal else "")
+        with Solver(grid, with_source=True, ir_dtype=dt, use_graphs=False, temporal=temporal) as s:
             s.load(g, b)
-            if args.ir_tile:
+            if args.ir_tile and not temporal:
                 s.set_tiles(*[int(v) for v in args.ir_tile.split(",")])
             else:
                 s.autotune(reps=2)      # tunes the inner sweep of the correction
-            out["config"]["ir_tile_%s" % dt] = list(s.tile_info().values())[:3]
+            out["config"]["ir_tile_%s" % tag] = list(s.tile_info().values())[:3]
+            if temporal:
+                t2 = s.temporal_info()
+                out["config"]["ir_temporal_tile_%s" % dt] = [t2["rows"], t2["z_chunk"]]
             s.set_timing(True)
             t0 = time.perf_counter()
             info = s.solve_ir(inner=50, rtol=0.0, max_inner=args.ir_sweeps)
@@ -311,10 +319,12 @@ def bench_refinement(args):
             ms_out, k_out = s.kernel_time(L.JC_K_IR_OUTER)
             s.set_timing(False)
             total_ms = ms_in + ms_out
-            rates["%s_refined" % dt] = dict(
+            rates["%s_refined%s" % (dt, "_temporal" if temporal else "")] = dict(
                 glups=lups * info["iters"] / (total_ms * 1e-3) / 1e9,
+                # the first sweep of each step (no neighbour reads) is one of
+                # the launches timed; per launch bytes of the later sweeps
                 inner_gbs=inner_bytes * lups * k_in / (ms_in * 1e-3) / 1e9,
-                ms_per_inner_sweep=ms_in / max(k_in, 1), outer_ms_total=ms_out,
+                inner_launches=k_in, ms_per_inner_sweep=ms_in / max(info["iters"], 1), outer_ms_total=ms_out,
                 inner_sweeps=info["iters"], rel_resid=info["rel_resid"], wall_s=wall)
     del g, b
     torch.cuda.empty_cache()

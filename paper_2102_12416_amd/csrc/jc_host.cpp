@@ -511,6 +511,25 @@ hipError_t launch_two_step(jc_ctx* c, int rows, int zc)
                              c->opt.with_source != 0, c->stream);
 }
 
+// Two inner sweeps of the refinement correction in one launch (copy
+// qparity -> qparity ^ 1).
+hipError_t launch_ir_two_step(jc_ctx* c, int qparity, int rows, int zc)
+{
+    const HostBlock& b = c->blocks[0];
+    return jc::launch_ir_inner2(c->d_blocks(), (int)b.n[0], (int)b.n[1], (int)b.n[2], qparity, rows, zc,
+                                c->opt.ir_dtype, c->stream);
+}
+
+// Copy of d that holds the correction after m inner sweeps: the first
+// sweep writes copy 1 and every later launch flips it (a two-sweep
+// launch once).
+int ir_final_copy(const jc_ctx* c, int64_t m)
+{
+    const int64_t pairs = c->opt.temporal ? (m - 1) / 2 : 0;
+    const int64_t launches = pairs + (m - 1 - 2 * pairs);
+    return (int)((1 + launches) & 1);
+}
+
 // Two sweeps in one launch (temporal blocking; one block, no pairs).
 int do_sweep2(jc_ctx* c)
 {
@@ -689,9 +708,10 @@ void free_graphs(jc_ctx* c)
     c->graphs.clear();
 }
 
-// Times the two-sweep launch over tile rows {16, 24} x z-chunk counts and
-// keeps the fastest (temporal contexts; run by jc_autotune after its
-// one-sweep search, on a warm device).  Which shape wins depends on how
+// Times the two-sweep launch (of the correction on a refinement context)
+// over tile rows {16, 24} x z-chunk counts and keeps the fastest (temporal
+// contexts; run by jc_autotune after its one-sweep search, on a warm
+// device).  Which shape wins depends on how
 // the work-groups fill the compute units and on how close in time
 // neighbouring tiles read their shared halo rows (an L2 hit), so it is
 // measured rather than modelled.  Trial launches read copy `parity` and
@@ -719,13 +739,19 @@ int tune_two_step(jc_ctx* c, int reps)
         (void)hipEventDestroy(e0);
         return fail(JC_ERR_DEVICE, "autotune: hipEventCreate failed");
     }
+    // a refinement context is tuned for its inner sweeps (on the zeroed
+    // correction arrays, as the one-sweep search left them)
+    const bool ir = c->opt.ir_enable != 0;
+    auto launch = [&](const Cand& k) {
+        return ir ? launch_ir_two_step(c, 1, k.rows, k.zc) : launch_two_step(c, k.rows, k.zc);
+    };
     // milliseconds of n launches after one untimed launch
     auto time_one = [&](const Cand& k, int n, double& ms) -> int {
-        hipError_t e = launch_two_step(c, k.rows, k.zc);
+        hipError_t e = launch(k);
         if (e == hipSuccess)
             e = hipEventRecord(e0, c->stream);
         for (int i = 0; i < n && e == hipSuccess; ++i)
-            e = launch_two_step(c, k.rows, k.zc);
+            e = launch(k);
         if (e == hipSuccess)
             e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess)
@@ -1252,14 +1278,23 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
             break;
         const int64_t m = std::min<int64_t>(inner_sweeps, max_inner - done);
         // the m inner sweeps of a step: first sweep (d_0 = 0) into copy 1,
-        // then alternating copies; the result lands in copy m mod 2
-        const int q = (int)(m & 1);
+        // then alternating copies (two sweeps per launch with temporal
+        // blocking, and a last single sweep if one is left)
+        const int q = ir_final_copy(c, m);
         auto inner_window = [&]() -> int {
             int s2 = timed(c, JC_K_IR_INNER, [&] {
                 return jc::launch_ir_first(c->d_blocks(), c->nb(), c->max_rows(), lo, c->stream);
             });
             int qq = 1;
-            for (int64_t j = 1; j < m && s2 == JC_OK; ++j) {
+            int64_t j = 1;
+            if (c->opt.temporal) {
+                for (; j + 2 <= m && s2 == JC_OK; j += 2) {
+                    s2 = timed(c, JC_K_IR_INNER,
+                               [&] { return launch_ir_two_step(c, qq, c->t2_rows, two_step_chunk(c)); });
+                    qq ^= 1;
+                }
+            }
+            for (; j < m && s2 == JC_OK; ++j) {
                 s2 = timed(c, JC_K_IR_INNER, [&] {
                     return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), qq, c->tile_x,
                                                c->tile_y, lo, c->stream);

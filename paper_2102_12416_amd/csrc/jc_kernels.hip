@@ -657,12 +657,15 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
 // ---- sweep kernel: end ----
 
 // ---- two-step sweep (temporal blocking): begin (fingerprinted with recorded counters) ----
-// Two Jacobi sweeps of a single-block binary64 context per launch: iterate
-// k is read from copy p and iterate k + 2 written to copy p ^ 1; iterate
-// k + 1 lives only in LDS and registers.  Each cell's two updates take
-// the same sums in the same order as two one-step sweeps, so the result
-// is bitwise the same; HBM moves one read and one write per cell for two
-// sweeps instead of two of each.
+// Two Jacobi sweeps of the single block of a context without face pairs
+// per launch: iterate k is read from copy p and iterate k + 2 written to
+// copy p ^ 1; iterate k + 1 lives only in LDS and registers.  T / FIELD as
+// for k_sweep: the binary64 iterate u (source b), or the refinement
+// correction d in its storage format (source r_lo, zero ghosts), whose
+// iterate k + 1 is rounded to that format as a stored sweep would leave
+// it.  Each cell's two updates take the same sums in the same order as
+// two one-step sweeps, so the result is bitwise the same; HBM moves one
+// read and one write per cell for two sweeps instead of two of each.
 //
 // A work-group owns a tile of 2 TXP x cells by TY rows and a z range, and
 // marches along z as the one-step sweep does.  Iterate k + 1 is needed on
@@ -674,24 +677,32 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
 // step s every thread writes iterate k of its pair at plane s into LDS,
 // the work-group synchronises once, every thread computes iterate k + 1 of
 // its pair at plane s (a ghost cell keeps its value: the context has no
-// face pairs, so every ghost is a Dirichlet value) into a second LDS
+// face pairs, so every ghost is a fixed boundary value) into a second LDS
 // plane, and the tile threads compute iterate k + 2 at plane s - 1 from
 // the previous step's second plane.  Both LDS planes are double-buffered
 // by step parity.  Values at cells two steps out of the block (the
 // outermost ring of a tile on the block edge) are clamped loads that only
 // feed discarded results.
-template <int TXP, int TY, bool SRC>
+// A value of the arithmetic type rounded to the storage format and back:
+// iterate k + 1 is stored between the two sweeps of a one-sweep-per-launch
+// run, so the second sweep must read it at storage precision.
+template <typename T> __device__ __forceinline__ typename Tr<T>::C storage_round(typename Tr<T>::C v) { return v; }
+template <> __device__ __forceinline__ float storage_round<bf16>(float v) { return bf16_to_f32(f32_to_bf16(v)); }
+
+template <typename T, int FIELD, int TXP, int TY, bool SRC>
 __global__ void __launch_bounds__(((TXP + 2) * (TY + 4) + 63) / 64 * 64)
 k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tiles_y, int nch, int ntiles)
 {
+    using C = typename Tr<T>::C;
+    using F = Fld<T, FIELD>;
     constexpr int EP = TXP + 2;                   // pairs of an extended row
     constexpr int ER = TY + 4;                    // extended rows
     constexpr int NTILE = TXP * TY;               // tile threads
     static_assert(NTILE % 64 == 0, "tile threads are whole waves");
     constexpr int LW = 2 * EP + 2;                // LDS row: pad, 2 EP cells, pad
     constexpr int LN = (ER + 2) * LW;             // LDS plane: pad row, ER rows, pad row
-    __shared__ double A[2][LN + 1];               // iterate k; element LN: sink of idle lanes
-    __shared__ double Bn[2][LN + 1];              // iterate k + 1
+    __shared__ C A[2][LN + 1];                    // iterate k; element LN: sink of idle lanes
+    __shared__ C Bn[2][LN + 1];                   // iterate k + 1
 
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= ntiles)
@@ -739,12 +750,12 @@ k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tile
     const bool in_b = live && y_in && xs + 1 >= 1 && xs + 1 <= nx;
     const bool a_ok = tile && ye <= ny && xs <= nx;   // tile cells in the block: stored
     const bool b_ok = tile && ye <= ny && xs + 1 <= nx;
-    const int64_t pitch = B->pitch;
-    const int64_t plane = B->plane;
+    const int64_t pitch = F::pitch(B);
+    const int64_t plane = F::plane(B);
     const int64_t rowoff = (int64_t)ye_c * pitch + xs_c;
-    const double* __restrict__ col = B->u[p] + rowoff;
-    const double* __restrict__ scol = SRC ? B->b + rowoff : nullptr;
-    double* __restrict__ dst = B->u[p ^ 1] + rowoff;
+    const T* __restrict__ col = F::src(B, p) + rowoff;
+    const T* __restrict__ scol = SRC ? F::source(B) + rowoff : nullptr;
+    T* __restrict__ dst = F::dst(B, p) + rowoff;
 
     const int base = (r + 1) * LW + 2 * j + 1;    // LDS slot of cell xs
     const int wa = live ? base : LN;
@@ -756,18 +767,18 @@ k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tile
     constexpr int PD = 3;
     constexpr int RS = 6;
     const int zhi = min(zl + 2, nz + 1);          // last plane read
-    double ua[RS], ub[RS], ba[RS], bb[RS], va[3], vb[3];
+    C ua[RS], ub[RS], ba[RS], bb[RS], va[3], vb[3];
 #pragma unroll
     for (int k = 0; k < RS; ++k)
-        ba[k] = bb[k] = 0.0;
-    va[0] = vb[0] = va[1] = vb[1] = va[2] = vb[2] = 0.0;
-    Tr<double>::ld(col + (int64_t)max(zf - 2, 0) * plane, ua[RS - 1], ub[RS - 1]);
+        ba[k] = bb[k] = C(0);
+    va[0] = vb[0] = va[1] = vb[1] = va[2] = vb[2] = C(0);
+    Tr<T>::ld(col + (int64_t)max(zf - 2, 0) * plane, ua[RS - 1], ub[RS - 1]);
 #pragma unroll
     for (int k = 0; k < PD; ++k) {
         const int64_t zk = (int64_t)min(zf - 1 + k, zhi) * plane;
-        Tr<double>::ld(col + zk, ua[k], ub[k]);
+        Tr<T>::ld(col + zk, ua[k], ub[k]);
         if (SRC)
-            Tr<double>::ld(scol + zk, ba[k], bb[k]);
+            Tr<T>::ld(scol + zk, ba[k], bb[k]);
     }
 
     auto step = [&](int s, auto kc, auto two) {
@@ -777,48 +788,48 @@ k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tile
         constexpr int VC = K % 3, VM = (K + 2) % 3, VMM = (K + 1) % 3;
         constexpr int HC = K & 1;
         const int64_t zq = (int64_t)min(s + PD, zhi) * plane;
-        Tr<double>::ld(col + zq, ua[SQ], ub[SQ]);
+        Tr<T>::ld(col + zq, ua[SQ], ub[SQ]);
         if (SRC)
-            Tr<double>::ld(scol + zq, ba[SQ], bb[SQ]);
-        double* const Ak = A[HC];
+            Tr<T>::ld(scol + zq, ba[SQ], bb[SQ]);
+        C* const Ak = A[HC];
         Ak[wa] = ua[SC];
         Ak[wb] = ub[SC];
         __syncthreads();
         // iterate k + 1 at plane s
-        double sa = Ak[base - 1] + ub[SC];
+        C sa = Ak[base - 1] + ub[SC];
         sa = sa + Ak[base - LW];
         sa = sa + Ak[base + LW];
         sa = sa + ua[SM];
         sa = sa + ua[SP];
-        double sb = ua[SC] + Ak[base + 2];
+        C sb = ua[SC] + Ak[base + 2];
         sb = sb + Ak[base + 1 - LW];
         sb = sb + Ak[base + 1 + LW];
         sb = sb + ub[SM];
         sb = sb + ub[SP];
-        double na, nb;
+        C na, nb;
         if (SRC)
             div6_pair(sa + ba[SC], sb + bb[SC], na, nb);
         else
             div6_pair(sa, sb, na, nb);
         const bool z_in = s >= 1 && s <= nz;
-        va[VC] = (in_a && z_in) ? na : ua[SC];
-        vb[VC] = (in_b && z_in) ? nb : ub[SC];
+        va[VC] = (in_a && z_in) ? storage_round<T>(na) : ua[SC];
+        vb[VC] = (in_b && z_in) ? storage_round<T>(nb) : ub[SC];
         Bn[HC][wa] = va[VC];
         Bn[HC][wb] = vb[VC];
         // iterate k + 2 at plane s - 1
         if (TWO && tile) {
-            const double* const Bk = Bn[HC ^ 1];
-            double qa = Bk[base - 1] + vb[VM];
+            const C* const Bk = Bn[HC ^ 1];
+            C qa = Bk[base - 1] + vb[VM];
             qa = qa + Bk[base - LW];
             qa = qa + Bk[base + LW];
             qa = qa + va[VMM];
             qa = qa + va[VC];
-            double qb = va[VM] + Bk[base + 2];
+            C qb = va[VM] + Bk[base + 2];
             qb = qb + Bk[base + 1 - LW];
             qb = qb + Bk[base + 1 + LW];
             qb = qb + vb[VMM];
             qb = qb + vb[VC];
-            double wa2, wb2;
+            C wa2, wb2;
             if (SRC)
                 div6_pair(qa + ba[SM], qb + bb[SM], wa2, wb2);
             else
@@ -827,7 +838,7 @@ k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tile
             // x = nx + 1 ghost: write back the value it holds
             wb2 = b_ok ? wb2 : ub[SM];
             if (a_ok)
-                Tr<double>::stn(dst + (int64_t)(s - 1) * plane, wa2, wb2);
+                Tr<T>::stn(dst + (int64_t)(s - 1) * plane, wa2, wb2);
         }
     };
     using F_ = std::false_type;
@@ -1134,17 +1145,41 @@ hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int pa
     const int grid = (int)((n + 7) / 8 * 8);
 #define JC_SWEEP2_CASE(TY, SRC)                                                                               \
     if (tile_y == TY && src == SRC) {                                                                        \
-        hipLaunchKernelGGL((k_sweep2<32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, s, blocks, \
-                           parity, (int)tx, (int)ty, (int)nch, (int)n);                                      \
+        hipLaunchKernelGGL((k_sweep2<double, FIELD_U, 32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), \
+                           0, s, blocks, parity, (int)tx, (int)ty, (int)nch, (int)n);                        \
         return hipGetLastError();                                                                            \
     }
-    JC_SWEEP2_CASE(8, false)
-    JC_SWEEP2_CASE(8, true)
     JC_SWEEP2_CASE(16, false)
     JC_SWEEP2_CASE(16, true)
     JC_SWEEP2_CASE(24, false)
     JC_SWEEP2_CASE(24, true)
 #undef JC_SWEEP2_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int qparity, int tile_y, int z_chunk,
+                            int lo_dtype, hipStream_t s)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || z_chunk < 1)
+        return hipErrorInvalidValue;
+    const int64_t tx = (nx + 63) / 64, ty = (ny + tile_y - 1) / tile_y, nch = (nz + z_chunk - 1) / z_chunk;
+    const int64_t n = tx * ty * nch;
+    if (n > ((int64_t)1 << 30))
+        return hipErrorInvalidValue;
+    const int grid = (int)((n + 7) / 8 * 8);
+#define JC_IR2_CASE(TY, DT, T)                                                                                  \
+    if (tile_y == TY && lo_dtype == DT) {                                                                      \
+        hipLaunchKernelGGL((k_sweep2<T, FIELD_D, 32, TY, true>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, \
+                           s, blocks, qparity, (int)tx, (int)ty, (int)nch, (int)n);                            \
+        return hipGetLastError();                                                                              \
+    }
+    JC_IR2_CASE(16, 0, double)
+    JC_IR2_CASE(16, 1, float)
+    JC_IR2_CASE(16, 2, bf16)
+    JC_IR2_CASE(24, 0, double)
+    JC_IR2_CASE(24, 1, float)
+    JC_IR2_CASE(24, 2, bf16)
+#undef JC_IR2_CASE
     return hipErrorInvalidValue;
 }
 

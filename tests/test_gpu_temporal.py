@@ -173,3 +173,60 @@ def test_temporal_full_size_1024_source_sampled():
         for _ in range(6):
             box = oracle.sweep(box, bb)
         assert v == box[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]], c
+
+
+# ------------------------------------------------ refinement inner sweeps
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("rows", [16, 24])
+@pytest.mark.parametrize("n,inner,t2zc", [((20, 18, 16), 25, 0), ((70, 37, 41), 50, 13), ((2, 3, 1), 4, 1),
+                                          ((65, 26, 30), 9, 0)])
+def test_temporal_ir_vs_oracle(dtype, rows, n, inner, t2zc):
+    """Refinement with two inner sweeps per launch (iterate k + 1 rounded to
+    the storage format between them) equals the oracle's refinement bit
+    for bit; the last window is shorter than the others (7 sweeps)."""
+    say("temporal IR", dtype, "rows", rows, n, inner, t2zc)
+    u0 = synth.boundary_field(n, seed=21)
+    b = synth.source_field(n, seed=21)
+    total = 2 * inner + 7
+    ref, hist, done, _ = oracle.c_ir_solve(u0, b, storage=dtype, inner=inner, rtol=0.0, max_inner=total)
+    with Solver(n, with_source=True, ir_dtype=dtype, temporal=True) as s:
+        s.set_temporal_tiles(rows, t2zc or s.temporal_info()["z_chunk"])
+        s.load(u0, b)
+        info = s.solve_ir(inner=inner, rtol=0.0, max_inner=total, history=True)
+        got = s.store().cpu().numpy()
+    assert info["iters"] == done == total
+    rel = [h / info["history"][0] for h in info["history"]]
+    np.testing.assert_allclose(rel, hist, rtol=1e-9, atol=1e-15)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_temporal_ir_full_size_1024_sampled(dtype):
+    """1024^3 with a source, refinement with two inner sweeps per launch in
+    the configuration the refinement benchmark times (shape from
+    jc_autotune, eager launches): one outer step of 50 inner sweeps;
+    sampled cells equal the oracle's local refinement bit for bit."""
+    import torch
+    from paper_2102_12416_amd import synth_field
+    n, seed, inner = (1024, 1024, 1024), 12416, 50
+    say("temporal IR 1024^3", dtype)
+    rng = np.random.default_rng(77)
+    cells = [(1, 1, 1), (1024, 1024, 1024), (1, 512, 1024), (1024, 1, 513), (512, 512, 512)]
+    cells += [tuple(int(v) for v in rng.integers(1, 1025, 3)) for _ in range(5)]
+    with Solver(n, with_source=True, ir_dtype=dtype, use_graphs=False, temporal=True) as s:
+        s.load(synth_field(n, seed, 0), synth_field(n, seed, 1))
+        s.autotune(reps=2)
+        info = s.solve_ir(inner=inner, rtol=0.0, max_inner=inner)
+        u = s.store()
+        idx = torch.tensor(cells, device=u.device)
+        got = u[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    assert info["iters"] == inner
+    for c, v in zip(cells, got):
+        lo = [max(0, c[a] - inner - 2) for a in range(3)]
+        hi = [min(1026, c[a] + inner + 3) for a in range(3)]
+        u_box = synth.field_box(n, 0, lo, hi, seed=seed)
+        b_box = synth.field_box(n, 1, lo, hi, seed=seed)
+        ref, _, done, _ = oracle.c_ir_solve(u_box, b_box, storage=dtype, inner=inner, rtol=0.0, max_inner=inner)
+        assert done == inner
+        assert v == ref[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]], c
