@@ -356,14 +356,14 @@ def bench_refinement(args):
             row["f64_temporal"] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
                                        rel=info["rel_resid"], converged=info["converged"],
                                        bitwise_equal_f64_plain=bool(torch.equal(s.store(), u64)))
-        for dt in ("f32", "bf16"):
-            with Solver(gm, with_source=True, ir_dtype=dt) as s:
+        for dt, temporal in (("f32", False), ("bf16", False), ("f32", True), ("bf16", True)):
+            with Solver(gm, with_source=True, ir_dtype=dt, temporal=temporal) as s:
                 s.load(gg, bb)
                 s.autotune(reps=2)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 info = s.solve_ir(inner=50, rtol=1e-10, max_inner=2000000)
-                row["%s_refined" % dt] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
+                row["%s_refined%s" % (dt, "_temporal" if temporal else "")] = dict(seconds=time.perf_counter() - t0, sweeps=info["iters"],
                                               rel=info["rel_resid"], converged=info["converged"],
                                               max_rel_err_vs_f64=float((s.store() - u64).abs().max()) / scale)
         del u64
