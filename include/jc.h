@@ -97,13 +97,13 @@ typedef struct jc_options {
     int tile_x;          /* cells per tile row: 16, 32 or 64 (16 needs tile_y >= 8 or
                             auto); 0 = auto (64, or 32 where it idles fewer lanes) */
     int exchange;        /* JC_EXCHANGE_DEVICE (default), _HOST or _METADATA */
-    int temporal;        /* 1: temporal blocking -- jc_iterate and the windows of jc_solve
-                            advance two sweeps per launch (binary64; iterate k + 1 stays
-                            on chip, so each cell is read and written once per two
-                            sweeps; results bitwise equal to one-sweep launches).  Needs a
-                            context of one block (no face pairs); the residual sweeps of
-                            jc_solve, jc_sweep, refinement and groups run one sweep per
-                            launch.  0: one sweep per launch. */
+    int temporal;        /* 1: temporal blocking -- jc_iterate, the windows of jc_solve
+                            and the inner sweeps of jc_solve_ir advance two sweeps per
+                            launch (iterate k + 1 stays on chip, so each cell is read and
+                            written once per two sweeps; results bitwise equal to
+                            one-sweep launches).  Needs a context of one block (no face
+                            pairs); the residual sweeps of jc_solve, jc_sweep and groups
+                            run one sweep per launch.  0: one sweep per launch. */
 } jc_options;
 
 /* Result of a solve. */
@@ -335,10 +335,12 @@ int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
  * context with refinement buffers (ir_enable), the inner sweep of the
  * correction (the refinement arrays are zeroed first; every refinement
  * step rebuilds them; JC_ERR_STATE while a group's refinement step is in
- * progress on the context).  With temporal = 1 the two-sweep launch is
- * then timed over rows {16, 24} x z chunks of 1/1 .. 1/16 of the depth
- * (max(reps, 2) launches each, the three fastest again over three rounds)
- * and the fastest kept (jc_temporal_info).  The trial sweeps write only
+ * progress on the context).  With temporal = 1 the two-sweep launch (of
+ * the correction, on a context with refinement buffers) is then timed over
+ * rows {16, 24} x z chunks of 1/1 .. 1/16 of the depth (max(reps, 2)
+ * launches each, the three fastest again over three rounds) and the
+ * fastest kept (jc_temporal_info); the one shape serves both two-sweep
+ * launches of the context.  The trial sweeps write only
  * the other ping-pong copy and face slot, so the current iterate and
  * iteration count are unchanged.  Waits for the stream.  Needs a loaded
  * context. */
