@@ -96,7 +96,7 @@ def parse():
     ap.add_argument("--temporal", action="store_true",
                     help="one-block workloads: two sweeps per launch (temporal blocking)")
     ap.add_argument("--temporal-tile", default="",
-                    help="rows,z_chunk of the two-sweep launch (16 or 24 rows; default: stored or autotuned)")
+                    help="rows,z_chunk of the two-sweep launch (8, 16 or 24 rows; default: stored or autotuned)")
     ap.add_argument("--seed", type=int, default=12416)
     ap.add_argument("--tile-x", type=int, default=0, help="cells per tile row, 32 or 64 (0: library default)")
     ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")

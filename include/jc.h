@@ -317,7 +317,7 @@ int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed
 int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 
 /* Shape of the two-sweep launch of temporal blocking: rows of its tile
- * (16 or 24; the tile is 64 cells wide) and planes per work-group (>= 1).
+ * (8, 16 or 24; the tile is 64 cells wide) and planes per work-group (>= 1).
  * Results are bitwise independent of it.  JC_ERR_STATE unless the context
  * was created with temporal = 1. */
 int jc_set_temporal_tiles(jc_ctx* ctx, int rows, int z_chunk);
@@ -337,7 +337,7 @@ int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
  * step rebuilds them; JC_ERR_STATE while a group's refinement step is in
  * progress on the context).  With temporal = 1 the two-sweep launch (of
  * the correction, on a context with refinement buffers) is then timed over
- * rows {16, 24} x z chunks of 1/1 .. 1/16 of the depth (max(reps, 2)
+ * rows {8, 16, 24} x z chunks of 1/1 .. 1/16 of the depth (max(reps, 2)
  * launches each, the three fastest again over three rounds) and the
  * fastest kept (jc_temporal_info); the one shape serves both two-sweep
  * launches of the context.  The trial sweeps write only

@@ -86,11 +86,18 @@ inline bool tile_shape_ok(int tile_x, int tile_y)
 }
 constexpr int kMinZChunk = 16;
 // Temporal blocking: default rows of the two-sweep tile (64 cells wide;
-// 16 or 24) and the fewest planes per work-group when the chunk follows
+// 8, 16 or 24) and the fewest planes per work-group when the chunk follows
 // the one-sweep z_chunk (each work-group reads two planes beyond each end).
 constexpr int kTwoStepRows = 16;
 constexpr int kTwoStepMinZ = 32;
-inline bool two_step_rows_ok(int rows) { return rows == 16 || rows == 24; }
+constexpr int kTwoStepRowCandidates[] = {8, 16, 24};
+inline bool two_step_rows_ok(int rows)
+{
+    bool ok = false;
+    for (int r : kTwoStepRowCandidates)
+        ok = ok || r == rows;
+    return ok;
+}
 
 }  // namespace jc_rt
 

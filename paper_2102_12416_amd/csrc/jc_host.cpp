@@ -709,7 +709,7 @@ void free_graphs(jc_ctx* c)
 }
 
 // Times the two-sweep launch (of the correction on a refinement context)
-// over tile rows {16, 24} x z-chunk counts and keeps the fastest (temporal
+// over tile rows {8, 16, 24} x z-chunk counts and keeps the fastest (temporal
 // contexts; run by jc_autotune after its one-sweep search, on a warm
 // device).  Which shape wins depends on how
 // the work-groups fill the compute units and on how close in time
@@ -724,7 +724,7 @@ int tune_two_step(jc_ctx* c, int reps)
         double ms;
     };
     std::vector<Cand> cand;
-    for (int rows : {16, 24})
+    for (int rows : jc_rt::kTwoStepRowCandidates)
         for (int nch : {1, 2, 3, 4, 6, 8, 12, 16}) {
             const int zc = (int)((nz + nch - 1) / nch);
             bool dup = false;
@@ -1381,7 +1381,7 @@ int jc_set_temporal_tiles(jc_ctx* c, int rows, int z_chunk)
     if (!c->opt.temporal)
         return fail(JC_ERR_STATE, "the context was created without temporal blocking");
     if (!jc_rt::two_step_rows_ok(rows) || z_chunk < 1)
-        return fail(JC_ERR_INVALID, "rows must be 16 or 24 and z_chunk >= 1");
+        return fail(JC_ERR_INVALID, "rows must be 8, 16 or 24 and z_chunk >= 1");
     c->t2_rows = rows;
     c->t2_zc = z_chunk;
     free_graphs(c);                        // graphs hold the old launch shapes

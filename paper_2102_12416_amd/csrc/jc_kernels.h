@@ -21,11 +21,11 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 
 // Two sweeps of the single block of a context without face pairs in one
 // launch (binary64): iterate k from copy parity, iterate k + 2 into copy
-// parity ^ 1.  Tiles of 64 cells by tile_y (16 or 24) rows by z_chunk planes.
+// parity ^ 1.  Tiles of 64 cells by tile_y (8, 16 or 24) rows by z_chunk planes.
 hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
                          bool src, hipStream_t s);
 // The same for two inner sweeps of the refinement correction (copy
-// qparity -> qparity ^ 1, source r_lo; tile_y 16 or 24): iterate k + 1 is
+// qparity -> qparity ^ 1, source r_lo; tile_y 8, 16 or 24): iterate k + 1 is
 // rounded to the storage format between the two sweeps.
 hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int qparity, int tile_y, int z_chunk,
                             int lo_dtype, hipStream_t s);

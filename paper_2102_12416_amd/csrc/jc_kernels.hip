@@ -1149,6 +1149,8 @@ hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int pa
                            0, s, blocks, parity, (int)tx, (int)ty, (int)nch, (int)n);                        \
         return hipGetLastError();                                                                            \
     }
+    JC_SWEEP2_CASE(8, false)
+    JC_SWEEP2_CASE(8, true)
     JC_SWEEP2_CASE(16, false)
     JC_SWEEP2_CASE(16, true)
     JC_SWEEP2_CASE(24, false)
@@ -1173,6 +1175,9 @@ hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int
                            s, blocks, qparity, (int)tx, (int)ty, (int)nch, (int)n);                            \
         return hipGetLastError();                                                                              \
     }
+    JC_IR2_CASE(8, 0, double)
+    JC_IR2_CASE(8, 1, float)
+    JC_IR2_CASE(8, 2, bf16)
     JC_IR2_CASE(16, 0, double)
     JC_IR2_CASE(16, 1, float)
     JC_IR2_CASE(16, 2, bf16)

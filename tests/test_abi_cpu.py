@@ -316,7 +316,8 @@ def test_temporal_tile_shape():
     check(L.lib.jc_set_temporal_tiles(ctx, 24, 7))
     check(L.lib.jc_temporal_info(ctx, out))
     assert tuple(out) == (1, 24, 7)
-    assert L.lib.jc_set_temporal_tiles(ctx, 8, 7) == L.JC_ERR_INVALID
+    assert L.lib.jc_set_temporal_tiles(ctx, 12, 7) == L.JC_ERR_INVALID
+    check(L.lib.jc_set_temporal_tiles(ctx, 8, 7))
     assert L.lib.jc_set_temporal_tiles(ctx, 16, 0) == L.JC_ERR_INVALID
     L.lib.jc_destroy(ctx)
     st, ctx = create((40, 24, 100), (40, 24, 100))

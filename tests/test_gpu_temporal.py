@@ -20,7 +20,7 @@ def say(*a):
 
 
 @pytest.mark.parametrize("mode", ["staged", "fused"])
-@pytest.mark.parametrize("rows", [16, 24])
+@pytest.mark.parametrize("rows", [8, 16, 24])
 @pytest.mark.parametrize("n,iters,src,zc,t2zc", [
     ((64, 64, 64), 10, False, 0, 0),
     ((70, 19, 37), 7, True, 0, 0),          # ragged tile in x and y, odd count
@@ -61,7 +61,7 @@ def test_temporal_autotune_keeps_results():
         s.iterate(5)
         s.autotune(reps=2)
         info = s.temporal_info()
-        assert info["rows"] in (16, 24) and info["z_chunk"] >= 1
+        assert info["rows"] in (8, 16, 24) and info["z_chunk"] >= 1
         assert s.iterations == 5
         s.iterate(7)
         got = s.store().cpu().numpy()
@@ -178,7 +178,7 @@ def test_temporal_full_size_1024_source_sampled():
 # ------------------------------------------------ refinement inner sweeps
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("rows", [16, 24])
+@pytest.mark.parametrize("rows", [8, 16, 24])
 @pytest.mark.parametrize("n,inner,t2zc", [((20, 18, 16), 25, 0), ((70, 37, 41), 50, 13), ((2, 3, 1), 4, 1),
                                           ((65, 26, 30), 9, 0)])
 def test_temporal_ir_vs_oracle(dtype, rows, n, inner, t2zc):
@@ -230,3 +230,24 @@ def test_temporal_ir_full_size_1024_sampled(dtype):
         ref, _, done, _ = oracle.c_ir_solve(u_box, b_box, storage=dtype, inner=inner, rtol=0.0, max_inner=inner)
         assert done == inner
         assert v == ref[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]], c
+
+
+def test_temporal_shape_change_replaces_graphs():
+    """Windows captured as graphs with one two-sweep shape are dropped when
+    the shape changes: later windows use the new shape and stay exact."""
+    n = (90, 41, 50)
+    say("temporal shape change with graphs")
+    u0 = synth.boundary_field(n, seed=13)
+    ref, _ = oracle.c_jacobi(u0, 40, None)
+    with Solver(n, mode="fused", temporal=True, use_graphs=True) as s:
+        s.load(u0)
+        s.iterate(10)
+        s.iterate(10)                   # replays the captured 10-sweep window
+        s.set_temporal_tiles(24, 7)
+        assert s.temporal_info()["rows"] == 24
+        s.iterate(10)
+        s.set_temporal_tiles(8, 50)
+        s.iterate(10)
+        assert s.iterations == 40
+        got = s.store().cpu().numpy()
+    assert np.array_equal(got, ref)
