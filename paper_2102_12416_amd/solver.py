@@ -249,7 +249,8 @@ class Solver:
         check(L.lib.jc_set_tiles(self._ctx, int(tile_x), int(tile_y), int(z_chunk)))
 
     def autotune(self, reps=5):
-        """Pick the fastest tile shape for this context; returns
+        """Pick the fastest tile shape for this context (and, with temporal
+        blocking, the fastest two-sweep shape: temporal_info()); returns
         (tile_x, tile_y, z_chunk, microseconds per sweep)."""
         out = (ctypes.c_int64 * 4)()
         check(L.lib.jc_autotune(self._ctx, int(reps), out))
