@@ -391,14 +391,14 @@ def bench_batch(args):
     t0 = time.perf_counter()
     seq_iters = []
     for r in reqs:
-        with Solver((n, n, n), mode="fused", with_source=True) as s:
+        with Solver((n, n, n), mode="fused", with_source=True, temporal=bool(args.temporal)) as s:
             s.load(synth_field((n, n, n), r.seed, 0), synth_field((n, n, n), r.seed, 1))
             info = s.solve(rtol=rtol, max_iter=cap, check_every=window)
             seq_iters.append(info["iters"])
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t0
     print("[bench] one after another: %.3f s" % seq_s, file=sys.stderr, flush=True)
-    srv = Server(budget_bytes=1 << 40, window=window, rtol=rtol, max_iter=cap, lanes=())
+    srv = Server(budget_bytes=1 << 40, window=window, rtol=rtol, max_iter=cap, lanes=(), temporal=bool(args.temporal))
     t0 = time.perf_counter()
     res = srv.run(reqs, realtime=False)
     bat_s = time.perf_counter() - t0
@@ -407,6 +407,7 @@ def bench_batch(args):
            "value": round(seq_s / bat_s, 3), "unit": "x (speedup of batching)", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "dtype": "f64",
            "config": {"workload": "batch", "grids": count, "grid": [n, n, n], "rtol": rtol, "check_every": window,
+                      "temporal": bool(args.temporal),
                       "source": "U[-1,1) SplitMix64", "boundary": "U[0,1) SplitMix64"},
            "one_after_another_s": round(seq_s, 3), "batched_s": round(bat_s, 3),
            "sweeps_per_solve": [min(seq_iters), max(seq_iters)], "same_stop_as_alone": all(same),
@@ -435,8 +436,12 @@ def bench_grids(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "768_grids", "grids": count, "grid": [n, n, n], "tile": list(tile),
                       "mode": "group of independent single-block solves",
+                      "temporal": bool(args.temporal),
                       "launch": "hipGraph replay of the timed window"}}
-    with Group(solvers, use_graphs=True, tile=tile) as grp:
+    if args.temporal and args.steps % 2:
+        print("bench.py: --temporal needs an even --steps", file=sys.stderr)
+        sys.exit(2)
+    with Group(solvers, use_graphs=True, tile=tile, temporal=bool(args.temporal)) as grp:
         grp.iterate(args.warmup)
         # capture the timed window's graph outside the timed region (both
         # start parities when the window is odd)
@@ -456,10 +461,19 @@ def bench_grids(args):
     per = ms / args.steps
     out["ms_per_step"] = round(per, 5)
     out["value"] = round(lups / (per * 1e-3) / 1e9, 3)
-    out["roofline"] = {"bound": "hbm", "kernel": "k_sweep(group)", "achieved": round(16 * lups / (per * 1e-3) / 1e9, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(16 * lups / (per * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                       "bytes_per_launch": 16 * lups, "avg_launch_ms": round(per, 5)}
+    if args.temporal:
+        # one two-sweep launch per two iterations: 16 B per cell per launch
+        launch_ms = 2 * per
+        out["roofline"] = {"bound": "hbm", "kernel": "k_sweep2(group)",
+                           "achieved": round(16 * lups / (launch_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(16 * lups / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic": None, "bytes_per_launch": 16 * lups, "avg_launch_ms": round(launch_ms, 5),
+                           "bytes_per_unit": "16 B per cell per two-sweep launch (8 B per update)"}
+    else:
+        out["roofline"] = {"bound": "hbm", "kernel": "k_sweep(group)",
+                           "achieved": round(16 * lups / (per * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(16 * lups / (per * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic": None, "bytes_per_launch": 16 * lups, "avg_launch_ms": round(per, 5)}
     out["residual_norm_range"] = [min(norms), max(norms)]
     for s in solvers:
         s.close()
@@ -483,7 +497,7 @@ def bench_serve(args):
 
     def server():
         return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter,
-                      progress_every=15.0, lanes=lanes,
+                      progress_every=15.0, lanes=lanes, temporal=bool(args.temporal),
                       tile=[int(v) for v in args.serve_tile.split(",")] if args.serve_tile else None)
 
     cap = None

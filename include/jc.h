@@ -246,11 +246,15 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * ctxs is read during the call; the contexts must outlive the group and
  * must not be used on their own streams while the group exists.
  * flags: bit 0 = capture jc_group_iterate windows as HIP graphs (needs a
- * non-null stream).  tile: {cells per row 16|32|64, rows 4|8|16|32 (at
- * least 8 for 16-cell rows), planes >= 1} for every launch of the group,
- * or NULL for {64, 8, 32}; members' results do not depend on it, their
- * residual norms do in the last bits, so compare mixes within one tile
- * shape.  Host only until jc_group_bind. */
+ * non-null stream); bit 1 = two sweeps of every member per launch
+ * (temporal blocking; every member one block without refinement buffers,
+ * else JC_ERR_INVALID; tiles of 64 cells x 16 rows x max(planes, 32);
+ * results bitwise the same as one sweep per launch; an odd sweep count
+ * ends with one single-sweep launch).  tile: {cells per row 16|32|64,
+ * rows 4|8|16|32 (at least 8 for 16-cell rows), planes >= 1} for every
+ * launch of the group, or NULL for {64, 8, 32}; members' results do not
+ * depend on it, their residual norms do in the last bits, so compare
+ * mixes within one tile shape.  Host only until jc_group_bind. */
 int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, const int tile[3],
                     jc_group** out);
 /* Device scratch the group needs (joint tables, partial sums). */

@@ -36,8 +36,14 @@ struct Class {
     int64_t max_rows = 1;            // largest ny * nz of the class's blocks
     size_t item0 = 0;                // first joint item
     std::vector<Item> items;
+    size_t item2_0 = 0;              // first joint two-sweep item
+    std::vector<Item> items2;        // two-sweep tiles (groups that sweep twice per launch)
     std::vector<int> members;
 };
+
+// Two-sweep tiles of a group: 64 cells by kGroupTwoStepRows rows, and at
+// least kTwoStepMinZ planes (the group's own z chunk if larger).
+constexpr int kGroupTwoStepRows = 16;
 
 }  // namespace
 
@@ -49,9 +55,11 @@ struct jc_group {
     std::vector<Class> classes;
     std::vector<BlockDesc> desc;        // joint block table, class-major
     std::vector<Item> items;            // joint work list, class-major
+    std::vector<Item> items2;           // joint two-sweep work list, class-major
+    bool two_step = false;              // every launch sweeps every member twice
     std::vector<int32_t> lohi;          // per member: joint item range
     std::vector<int> member_bstart;     // per member: first joint block
-    size_t off_desc = 0, off_items = 0, off_partials = 0, off_lohi = 0, off_out = 0, footprint = 0;
+    size_t off_desc = 0, off_items = 0, off_items2 = 0, off_partials = 0, off_lohi = 0, off_out = 0, footprint = 0;
     char* scratch = nullptr;
     bool bound = false;
     double* h_out = nullptr;            // pinned, one per member
@@ -61,6 +69,7 @@ struct jc_group {
 
     BlockDesc* d_desc() const { return reinterpret_cast<BlockDesc*>(scratch + off_desc); }
     Item* d_items() const { return reinterpret_cast<Item*>(scratch + off_items); }
+    Item* d_items2() const { return reinterpret_cast<Item*>(scratch + off_items2); }
     double* d_partials() const { return reinterpret_cast<double*>(scratch + off_partials); }
     int32_t* d_lohi() const { return reinterpret_cast<int32_t*>(scratch + off_lohi); }
     double* d_out() const { return reinterpret_cast<double*>(scratch + off_out); }
@@ -141,6 +150,33 @@ int group_sweep(jc_group* g)
     return JC_OK;
 }
 
+// Two sweeps of every member in one launch per class (no refining
+// members, every member one block).
+int group_sweep2(jc_group* g)
+{
+    for (const Class& k : g->classes) {
+        const hipError_t e = jc::launch_sweep2_items(g->d_desc(), g->d_items2() + k.item2_0, (int)k.items2.size(),
+                                                     g->parity, kGroupTwoStepRows, k.src, g->stream);
+        if (e != hipSuccess)
+            return ghip(e, "group two-sweep launch");
+    }
+    return JC_OK;
+}
+
+// Bookkeeping after one two-sweep launch: every member advanced two
+// sweeps and its iterate moved to the other copy once, as the launch
+// parity did.
+void advance2(jc_group* g)
+{
+    g->parity ^= 1;
+    for (jc_ctx* c : g->members) {
+        c->iters += 2;
+        c->parity ^= 1;
+        c->ghost = GHOST_CURRENT;
+        c->fused_primed = false;
+    }
+}
+
 // Bookkeeping after n sweeps of every member.
 void advance(jc_group* g, int64_t n)
 {
@@ -166,6 +202,24 @@ void advance(jc_group* g, int64_t n)
     }
 }
 
+// n sweeps of every member as launches: two-sweep launches first when
+// the group sweeps twice per launch, then single sweeps.
+int group_run(jc_group* g, int64_t n)
+{
+    int64_t i = 0;
+    int st = JC_OK;
+    if (g->two_step)
+        for (; i + 2 <= n && st == JC_OK; i += 2) {
+            st = group_sweep2(g);
+            advance2(g);
+        }
+    for (; i < n && st == JC_OK; ++i) {
+        st = group_sweep(g);
+        advance(g, 1);
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -177,7 +231,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     *out = nullptr;
     if (!ctxs || n < 1)
         return fail(JC_ERR_INVALID, "a group needs at least one context");
-    if (flags & ~1)
+    if (flags & ~3)
         return fail(JC_ERR_INVALID, "unknown group flags");
     std::set<const jc_ctx*> seen;
     for (int i = 0; i < n; ++i) {
@@ -189,6 +243,9 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             return fail(JC_ERR_INVALID, "a context appears twice in the group");
         if (c->opt.ir_enable && c->parity != 0)
             return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
+        if ((flags & 2) && (c->opt.ir_enable || c->nb() != 1))
+            return fail(JC_ERR_INVALID, "two sweeps per launch (flag 2) needs members of one block without "
+                                        "refinement buffers");
     }
     if (tile) {
         const bool ok = jc_rt::tile_shape_ok(tile[0], tile[1]) && tile[2] >= 1;
@@ -204,6 +261,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     g->members.assign(ctxs, ctxs + n);
     g->stream = static_cast<hipStream_t>(hip_stream);
     g->use_graphs = (flags & 1) && g->stream != nullptr;
+    g->two_step = (flags & 2) != 0;
     // classes, in a fixed order
     std::map<std::tuple<int, int, int>, int> cls;
     for (int i = 0; i < n; ++i) {
@@ -234,20 +292,27 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             const size_t i0 = g->items.size();
             const size_t first = k.items.size();
             member_items(c, g->tile, (int)g->desc.size(), m, k.items);
+            if (g->two_step) {
+                const int t2[3] = {64, kGroupTwoStepRows, std::max(g->tile[2], jc_rt::kTwoStepMinZ)};
+                member_items(c, t2, (int)g->desc.size(), m, k.items2);
+            }
             g->desc.insert(g->desc.end(), c->hdesc.begin(), c->hdesc.end());
             g->items.insert(g->items.end(), k.items.begin() + first, k.items.end());
             g->lohi[2 * m] = (int32_t)i0;
             g->lohi[2 * m + 1] = (int32_t)g->items.size();
         }
         k.bend = (int)g->desc.size();
+        k.item2_0 = g->items2.size();
+        g->items2.insert(g->items2.end(), k.items2.begin(), k.items2.end());
     }
-    if (g->desc.size() > 65535 || g->items.size() > ((size_t)1 << 30)) {
+    if (g->desc.size() > 65535 || g->items.size() > ((size_t)1 << 30) || g->items2.size() > ((size_t)1 << 30)) {
         delete g;
         return fail(JC_ERR_INVALID, "group too large for one launch");
     }
     size_t off = 0;
     g->off_desc = off; off = align_up(off + sizeof(BlockDesc) * g->desc.size(), kAlign);
     g->off_items = off; off = align_up(off + sizeof(Item) * g->items.size(), kAlign);
+    g->off_items2 = off; off = align_up(off + sizeof(Item) * std::max<size_t>(1, g->items2.size()), kAlign);
     g->off_partials = off; off = align_up(off + sizeof(double) * g->items.size(), kAlign);
     g->off_lohi = off; off = align_up(off + sizeof(int32_t) * g->lohi.size(), kAlign);
     g->off_out = off; off = align_up(off + sizeof(double) * n, kAlign);
@@ -299,6 +364,9 @@ int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes)
     if (st == JC_OK)
         st = ghip(hipMemcpyAsync(g->d_items(), g->items.data(), sizeof(Item) * g->items.size(),
                                  hipMemcpyHostToDevice, g->stream), "upload items");
+    if (st == JC_OK && !g->items2.empty())
+        st = ghip(hipMemcpyAsync(g->d_items2(), g->items2.data(), sizeof(Item) * g->items2.size(),
+                                 hipMemcpyHostToDevice, g->stream), "upload two-sweep items");
     if (st == JC_OK)
         st = ghip(hipMemcpyAsync(g->d_lohi(), g->lohi.data(), sizeof(int32_t) * g->lohi.size(),
                                  hipMemcpyHostToDevice, g->stream), "upload ranges");
@@ -352,15 +420,8 @@ int jc_group_iterate(jc_group* g, int64_t n)
     const int64_t rest = n - done;
     if (rest <= 0)
         return JC_OK;
-    if (!g->use_graphs) {
-        for (int64_t i = 0; i < rest; ++i) {
-            st = group_sweep(g);
-            if (st != JC_OK)
-                return st;
-            advance(g, 1);
-        }
-        return JC_OK;
-    }
+    if (!g->use_graphs)
+        return group_run(g, rest);
     // graph of `rest` sweeps from the current launch parity; the d copy
     // of refinement members alternates with the launch parity
     int irq = 0;
@@ -387,10 +448,7 @@ int jc_group_iterate(jc_group* g, int64_t n)
         st = ghip(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         if (st != JC_OK)
             return st;
-        for (int64_t i = 0; i < rest && st == JC_OK; ++i) {
-            st = group_sweep(g);
-            advance(g, 1);
-        }
+        st = group_run(g, rest);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(g->stream, &graph);
         g->parity = gpar;
@@ -420,7 +478,14 @@ int jc_group_iterate(jc_group* g, int64_t n)
     st = ghip(hipGraphLaunch(found->second, g->stream), "hipGraphLaunch");
     if (st != JC_OK)
         return st;
-    advance(g, rest);
+    // the state after the replay, as the eager launches would leave it
+    if (g->two_step) {
+        for (int64_t i = 0; i + 2 <= rest; i += 2)
+            advance2(g);
+        advance(g, rest & 1);
+    } else {
+        advance(g, rest);
+    }
     return JC_OK;
 }
 

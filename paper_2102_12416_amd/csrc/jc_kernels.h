@@ -24,6 +24,10 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 // parity ^ 1.  Tiles of 64 cells by tile_y (8, 16 or 24) rows by z_chunk planes.
 hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
                          bool src, hipStream_t s);
+// The same over a work list of 64-cell by tile_y-row tiles of several
+// one-block contexts (groups): each item's block, its copy parity ^ flip.
+hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
+                               bool src, hipStream_t s);
 // The same for two inner sweeps of the refinement correction (copy
 // qparity -> qparity ^ 1, source r_lo; tile_y 8, 16 or 24): iterate k + 1 is
 // rounded to the storage format between the two sweeps.

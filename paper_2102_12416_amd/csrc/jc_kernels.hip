@@ -689,9 +689,15 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
 template <typename T> __device__ __forceinline__ typename Tr<T>::C storage_round(typename Tr<T>::C v) { return v; }
 template <> __device__ __forceinline__ float storage_round<bf16>(float v) { return bf16_to_f32(f32_to_bf16(v)); }
 
+//
+// Work: with items null, the tiles of blocks[0] (tiles_x by tiles_y per z
+// chunk, nch chunks, ntiles in all) numbered from the work-group index;
+// otherwise the work list items[0 .. ntiles), whose tiles must be 2 TXP
+// cells by TY rows, each with its block and ping-pong flip (groups).
 template <typename T, int FIELD, int TXP, int TY, bool SRC>
 __global__ void __launch_bounds__(((TXP + 2) * (TY + 4) + 63) / 64 * 64)
-k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tiles_y, int nch, int ntiles)
+k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int tiles_x,
+         int tiles_y, int nch, int ntiles)
 {
     using C = typename Tr<T>::C;
     using F = Fld<T, FIELD>;
@@ -708,15 +714,25 @@ k_sweep2(const BlockDesc* __restrict__ blocks, int parity, int tiles_x, int tile
     if (id >= ntiles)
         return;                                   // uniform over the work-group
     const BlockDesc* B = blocks;
-    const int p = parity;
+    int p = parity, x0, y0, zf, zl;
+    if (items) {
+        const Item it = items[id];
+        B = blocks + it.block;
+        p = parity ^ it.flip;
+        x0 = it.x0;
+        y0 = it.y0;
+        zf = it.z0 + 1;
+        zl = it.z0 + it.zlen;
+    } else {
+        const int per = tiles_x * tiles_y;
+        const int chunk = id / per;
+        const int nzb = B->n[2];
+        x0 = (id % tiles_x) * (2 * TXP);
+        y0 = ((id % per) / tiles_x) * TY;
+        zf = (int)((int64_t)chunk * nzb / nch) + 1;
+        zl = (int)((int64_t)(chunk + 1) * nzb / nch);
+    }
     const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
-    const int per = tiles_x * tiles_y;
-    const int chunk = id / per;
-    const int x0 = (id % tiles_x) * (2 * TXP);
-    const int y0 = ((id % per) / tiles_x) * TY;
-    const int z0 = (int)((int64_t)chunk * nz / nch);
-    const int zf = z0 + 1;
-    const int zl = (int)((int64_t)(chunk + 1) * nz / nch);
 
     // this thread's pair (j, r) of the extended region
     const int t = threadIdx.x;
@@ -1146,7 +1162,7 @@ hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int pa
 #define JC_SWEEP2_CASE(TY, SRC)                                                                               \
     if (tile_y == TY && src == SRC) {                                                                        \
         hipLaunchKernelGGL((k_sweep2<double, FIELD_U, 32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), \
-                           0, s, blocks, parity, (int)tx, (int)ty, (int)nch, (int)n);                        \
+                           0, s, blocks, nullptr, parity, (int)tx, (int)ty, (int)nch, (int)n);               \
         return hipGetLastError();                                                                            \
     }
     JC_SWEEP2_CASE(8, false)
@@ -1156,6 +1172,28 @@ hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int pa
     JC_SWEEP2_CASE(24, false)
     JC_SWEEP2_CASE(24, true)
 #undef JC_SWEEP2_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
+                               bool src, hipStream_t s)
+{
+    if (nitems <= 0)
+        return hipSuccess;
+    const int grid = ((nitems + 7) / 8) * 8;
+#define JC_SWEEP2_ITEMS_CASE(TY, SRC)                                                                          \
+    if (tile_y == TY && src == SRC) {                                                                         \
+        hipLaunchKernelGGL((k_sweep2<double, FIELD_U, 32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), \
+                           0, s, blocks, items, parity, 0, 0, 0, nitems);                                     \
+        return hipGetLastError();                                                                             \
+    }
+    JC_SWEEP2_ITEMS_CASE(8, false)
+    JC_SWEEP2_ITEMS_CASE(8, true)
+    JC_SWEEP2_ITEMS_CASE(16, false)
+    JC_SWEEP2_ITEMS_CASE(16, true)
+    JC_SWEEP2_ITEMS_CASE(24, false)
+    JC_SWEEP2_ITEMS_CASE(24, true)
+#undef JC_SWEEP2_ITEMS_CASE
     return hipErrorInvalidValue;
 }
 
@@ -1172,7 +1210,7 @@ hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int
 #define JC_IR2_CASE(TY, DT, T)                                                                                  \
     if (tile_y == TY && lo_dtype == DT) {                                                                      \
         hipLaunchKernelGGL((k_sweep2<T, FIELD_D, 32, TY, true>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, \
-                           s, blocks, qparity, (int)tx, (int)ty, (int)nch, (int)n);                            \
+                           s, blocks, nullptr, qparity, (int)tx, (int)ty, (int)nch, (int)n);                   \
         return hipGetLastError();                                                                              \
     }
     JC_IR2_CASE(8, 0, double)

@@ -126,7 +126,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
-                 progress_every: float = 0.0, lanes=(64, 160), tile=None):
+                 progress_every: float = 0.0, lanes=(64, 160), tile=None, temporal: bool = False):
         if window < 1 or max_iter % window:
             raise ValueError("max_iter must be a multiple of the window")
         bounds = [int(v) for v in lanes]
@@ -145,6 +145,11 @@ class Server:
         # residual norms, and so its stopping check, then do not depend on
         # who else is in the group
         self.tile = None if tile is None else tuple(int(v) for v in tile)
+        # temporal: a lane whose members are all binary64 (no refinement)
+        # is swept two sweeps per launch (bitwise the same results)
+        self.temporal = bool(temporal)
+        if self.temporal and self.window % 2:
+            raise ValueError("two sweeps per launch need an even window")
         self.max_members = 4096
         self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0, lane_windows=[])
         self.progress_every = float(progress_every)   # seconds between progress lines (0: none)
@@ -183,8 +188,9 @@ class Server:
     def _regroup(self, lane):
         lane.close()
         if lane.active:
+            two = self.temporal and all(l.req.precision != "f32" for l in lane.active)
             lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream,
-                               tile=self.tile)
+                               tile=self.tile, temporal=two)
             lane.key = tuple(l.req.id for l in lane.active)
             self.stats["group_builds"] += 1
 

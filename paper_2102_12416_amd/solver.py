@@ -290,7 +290,7 @@ class Group:
     The members must not be used on their own streams while the group
     exists; close() (or leaving a with-block) releases it."""
 
-    def __init__(self, solvers, use_graphs=True, stream=None, tile=None):
+    def __init__(self, solvers, use_graphs=True, stream=None, tile=None, temporal=False):
         self.solvers = list(solvers)
         dev = self.solvers[0].device
         self.device = dev
@@ -298,8 +298,9 @@ class Group:
         arr = (ctypes.c_void_p * len(self.solvers))(*[s._ctx.value for s in self.solvers])
         self._g = ctypes.c_void_p()
         tl = None if tile is None else (ctypes.c_int * 3)(*[int(v) for v in tile])
+        flags = (1 if use_graphs else 0) | (2 if temporal else 0)
         check(L.lib.jc_group_create(arr, len(self.solvers), ctypes.c_void_p(_stream_handle(self.stream)),
-                                    1 if use_graphs else 0, tl, ctypes.byref(self._g)))
+                                    flags, tl, ctypes.byref(self._g)))
         fp = ctypes.c_size_t()
         check(L.lib.jc_group_footprint(self._g, ctypes.byref(fp)))
         self.scratch = torch.empty(int(fp.value) + 256, dtype=torch.uint8, device=dev)

@@ -251,3 +251,72 @@ def test_temporal_shape_change_replaces_graphs():
         assert s.iterations == 40
         got = s.store().cpu().numpy()
     assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------------ groups
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_temporal_group_vs_oracle(graphs):
+    """A group that sweeps every member twice per launch: members of several
+    sizes, with and without a source (two kernel classes), starting from
+    different copies; each equals the oracle after its own sweep count, and
+    the group's residual norms equal a one-sweep-per-launch group's."""
+    from paper_2102_12416_amd import Group
+    specs = [((40, 36, 33), True, 3), ((17, 19, 23), False, 0), ((70, 20, 45), True, 1), ((1, 1, 1), False, 2),
+             ((130, 9, 66), False, 5)]
+    say("temporal group", "graphs" if graphs else "eager")
+    norms = []
+    for temporal in (True, False):
+        solvers, refs = [], []
+        for i, (n, src, pre) in enumerate(specs):
+            u0 = synth.boundary_field(n, seed=30 + i)
+            b = synth.source_field(n, seed=30 + i) if src else None
+            s = Solver(n, with_source=src)
+            s.load(u0, b)
+            s.iterate(pre)                       # members start in either copy
+            solvers.append(s)
+            refs.append(oracle.c_jacobi(u0, pre + 17, b)[0])
+        with Group(solvers, use_graphs=graphs, temporal=temporal) as g:
+            g.iterate(7)
+            g.iterate(10)
+            norms.append(g.residuals())
+        for s, ref, (n, src, pre) in zip(solvers, refs, specs):
+            assert s.iterations == pre + 17
+            assert np.array_equal(s.store().cpu().numpy(), ref), (temporal, n)
+            s.close()
+    assert norms[0] == norms[1]
+
+
+def test_temporal_group_needs_one_block_plain_members():
+    from paper_2102_12416_amd import Group, JcError, _lib as L
+    say("temporal group validation")
+    n = (24, 20, 18)
+    with Solver(n, block_dims=(12, 20, 18), mode="fused") as a, Solver(n, with_source=True, ir_dtype="f32") as b:
+        a.load(synth.boundary_field(n, seed=1))
+        b.load(synth.boundary_field(n, seed=1), synth.source_field(n, seed=1))
+        for s in (a, b):
+            with pytest.raises(JcError) as e:
+                Group([s], temporal=True)
+            assert e.value.code == L.JC_ERR_INVALID
+
+
+def test_temporal_server_same_results():
+    """A server whose all-binary64 lanes sweep twice per launch returns the
+    same iterates, sweep counts and residuals as one sweep per launch; a
+    lane mixing precisions keeps one sweep per launch."""
+    from paper_2102_12416_amd.server import Request, Server
+    say("temporal server")
+    reqs = [Request(id=0, arrival=0.0, n=24, precision="f64", seed=701),
+            Request(id=1, arrival=0.0, n=40, precision="f64", seed=702),
+            Request(id=2, arrival=0.0, n=90, precision="f64", seed=703),
+            Request(id=3, arrival=0.0, n=28, precision="f32", seed=704),
+            Request(id=4, arrival=0.0, n=16, precision="f64", seed=705)]
+    out = []
+    for temporal in (False, True):
+        srv = Server(budget_bytes=1 << 34, window=50, rtol=1e-10, max_iter=3000, keep_fields=True,
+                     lanes=(32, 64), temporal=temporal)
+        out.append(srv.run(reqs, realtime=False))
+    for a, b in zip(*out):
+        assert (a.id, a.iters, a.converged) == (b.id, b.iters, b.converged)
+        assert a.rel_resid == b.rel_resid
+        assert np.array_equal(a.field, b.field)
