@@ -327,7 +327,8 @@ int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 int jc_set_temporal_tiles(jc_ctx* ctx, int rows, int z_chunk);
 /* out = {temporal (0 or 1), rows, planes per work-group} of the two-sweep
  * launch.  Until set (jc_set_temporal_tiles or jc_autotune), the planes
- * follow the one-sweep z_chunk, at least 32. */
+ * follow the one-sweep z_chunk, at least 32, halved (down to 8) while a
+ * launch would have fewer than 1024 work-groups. */
 int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
 
 /* Time `reps` sweeps of every valid candidate shape (tile_x in {64, 32,

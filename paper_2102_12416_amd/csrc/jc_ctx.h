@@ -90,6 +90,8 @@ constexpr int kMinZChunk = 16;
 // the one-sweep z_chunk (each work-group reads two planes beyond each end).
 constexpr int kTwoStepRows = 16;
 constexpr int kTwoStepMinZ = 32;
+constexpr int kTwoStepFloorZ = 8;
+constexpr int64_t kTwoStepMinGroups = 1024;
 constexpr int kTwoStepRowCandidates[] = {8, 16, 24};
 inline bool two_step_rows_ok(int rows)
 {

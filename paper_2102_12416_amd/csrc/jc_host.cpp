@@ -499,9 +499,20 @@ int do_sweep(jc_ctx* c, bool fused, bool resid)
     return JC_OK;
 }
 
+// Planes per two-sweep work-group: the shape set or tuned, else the
+// one-sweep z_chunk (at least kTwoStepMinZ), halved down to
+// kTwoStepFloorZ while the launch would have fewer than
+// kTwoStepMinGroups work-groups (a small grid alone).
 int two_step_chunk(const jc_ctx* c)
 {
-    return c->t2_zc > 0 ? c->t2_zc : std::max(c->z_chunk, jc_rt::kTwoStepMinZ);
+    if (c->t2_zc > 0)
+        return c->t2_zc;
+    const HostBlock& b = c->blocks[0];
+    const int64_t per = ((b.n[0] + 63) / 64) * ((b.n[1] + c->t2_rows - 1) / c->t2_rows);
+    int64_t zc = std::max(c->z_chunk, jc_rt::kTwoStepMinZ);
+    while (zc > jc_rt::kTwoStepFloorZ && per * ((b.n[2] + zc - 1) / zc) < jc_rt::kTwoStepMinGroups)
+        zc = std::max<int64_t>((zc + 1) / 2, jc_rt::kTwoStepFloorZ);
+    return (int)zc;
 }
 
 hipError_t launch_two_step(jc_ctx* c, int rows, int zc)

@@ -312,7 +312,12 @@ def test_temporal_tile_shape():
     st, ctx = create((40, 24, 100), (40, 24, 100), temporal=1, z_chunk=16)
     assert st == 0
     check(L.lib.jc_temporal_info(ctx, out))
-    assert tuple(out) == (1, 16, 32)              # follows z_chunk, at least 32 planes
+    assert tuple(out) == (1, 16, 8)               # 2 tiles per plane: chunks halved to 8 planes
+    st2, big = create((1024, 1024, 1024), (1024, 1024, 1024), temporal=1, z_chunk=512)
+    assert st2 == 0
+    check(L.lib.jc_temporal_info(big, out))
+    assert tuple(out) == (1, 16, 512)             # 1024 tiles per plane x 2 chunks: kept
+    L.lib.jc_destroy(big)
     check(L.lib.jc_set_temporal_tiles(ctx, 24, 7))
     check(L.lib.jc_temporal_info(ctx, out))
     assert tuple(out) == (1, 24, 7)
