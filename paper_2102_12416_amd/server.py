@@ -122,7 +122,9 @@ class Server:
 
     lanes: ascending edge bounds of the size classes; a request of edge n
     joins the first lane with n <= bound, else the last (unbounded) lane.
-    An empty tuple serves everything in one group."""
+    An empty tuple serves everything in one group.  temporal: every size
+    class gets a lane per precision, and binary64 lanes sweep twice per
+    launch (results bitwise the same)."""
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
@@ -146,7 +148,8 @@ class Server:
         # who else is in the group
         self.tile = None if tile is None else tuple(int(v) for v in tile)
         # temporal: a lane whose members are all binary64 (no refinement)
-        # is swept two sweeps per launch (bitwise the same results)
+        # is swept two sweeps per launch (bitwise the same results); the
+        # size lanes are then kept per precision, so binary64 lanes always are
         self.temporal = bool(temporal)
         if self.temporal and self.window % 2:
             raise ValueError("two sweeps per launch need an even window")
@@ -239,7 +242,10 @@ class Server:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
         incoming = deque(reqs)
         queue: deque = deque()
-        lanes = [_Lane(b, self.device) for b in self.lane_bounds] + [_Lane(None, self.device)]
+        keys = ("f64", "f32") if self.temporal else (None,)
+        lane_sets = {k: [_Lane(b, self.device) for b in self.lane_bounds] + [_Lane(None, self.device)]
+                     for k in keys}
+        lanes = [lane for k in keys for lane in lane_sets[k]]
         done: list[Result] = []
         used = 0
         t0 = time.perf_counter()
@@ -273,7 +279,7 @@ class Server:
                 if used + need > self.budget:
                     break
                 queue.popleft()
-                lane = self._lane_of(lanes, head.n)
+                lane = self._lane_of(lane_sets[head.precision if self.temporal else None], head.n)
                 live = self._admit(head, clock(), lane.stream)
                 lane.pending.append(live)
                 used += live.bytes
