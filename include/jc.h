@@ -247,10 +247,10 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * must not be used on their own streams while the group exists.
  * flags: bit 0 = capture jc_group_iterate windows as HIP graphs (needs a
  * non-null stream); bit 1 = two sweeps of every member per launch
- * (temporal blocking; every member one block without refinement buffers,
- * else JC_ERR_INVALID; tiles of 64 cells x 16 rows x max(planes, 32);
- * results bitwise the same as one sweep per launch; an odd sweep count
- * ends with one single-sweep launch).  tile: {cells per row 16|32|64,
+ * (temporal blocking; every member one block, else JC_ERR_INVALID; tiles
+ * of 64 cells x 16 rows x max(planes, 32); the first inner sweep of a
+ * refinement step and the last of an odd count are single-sweep launches;
+ * results bitwise the same as one sweep per launch).  tile: {cells per row 16|32|64,
  * rows 4|8|16|32 (at least 8 for 16-cell rows), planes >= 1} for every
  * launch of the group, or NULL for {64, 8, 32}; members' results do not
  * depend on it, their residual norms do in the last bits, so compare

@@ -150,13 +150,18 @@ int group_sweep(jc_group* g)
     return JC_OK;
 }
 
-// Two sweeps of every member in one launch per class (no refining
-// members, every member one block).
+// Two sweeps of every member in one launch per class (every member one
+// block; refining members past the first inner sweep of their step).
 int group_sweep2(jc_group* g)
 {
     for (const Class& k : g->classes) {
-        const hipError_t e = jc::launch_sweep2_items(g->d_desc(), g->d_items2() + k.item2_0, (int)k.items2.size(),
-                                                     g->parity, kGroupTwoStepRows, k.src, g->stream);
+        hipError_t e;
+        if (!k.ir)
+            e = jc::launch_sweep2_items(g->d_desc(), g->d_items2() + k.item2_0, (int)k.items2.size(), g->parity,
+                                        kGroupTwoStepRows, k.src, g->stream);
+        else
+            e = jc::launch_ir_inner2_items(g->d_desc(), g->d_items2() + k.item2_0, (int)k.items2.size(),
+                                           g->members[k.members[0]]->ir_q, kGroupTwoStepRows, k.lo, g->stream);
         if (e != hipSuccess)
             return ghip(e, "group two-sweep launch");
     }
@@ -164,17 +169,24 @@ int group_sweep2(jc_group* g)
 }
 
 // Bookkeeping after one two-sweep launch: every member advanced two
-// sweeps and its iterate moved to the other copy once, as the launch
-// parity did.
+// sweeps and its iterate (a refining member: its correction) moved to the
+// other copy once, as the launch parity did.
 void advance2(jc_group* g)
 {
     g->parity ^= 1;
-    for (jc_ctx* c : g->members) {
-        c->iters += 2;
-        c->parity ^= 1;
-        c->ghost = GHOST_CURRENT;
-        c->fused_primed = false;
-    }
+    for (const Class& k : g->classes)
+        for (int m : k.members) {
+            jc_ctx* c = g->members[m];
+            c->iters += 2;
+            if (!k.ir) {
+                c->parity ^= 1;
+                c->ghost = GHOST_CURRENT;
+                c->fused_primed = false;
+            } else {
+                c->ir_q ^= 1;
+                c->ir_phase = 2;
+            }
+        }
 }
 
 // Bookkeeping after n sweeps of every member.
@@ -243,9 +255,8 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             return fail(JC_ERR_INVALID, "a context appears twice in the group");
         if (c->opt.ir_enable && c->parity != 0)
             return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
-        if ((flags & 2) && (c->opt.ir_enable || c->nb() != 1))
-            return fail(JC_ERR_INVALID, "two sweeps per launch (flag 2) needs members of one block without "
-                                        "refinement buffers");
+        if ((flags & 2) && c->nb() != 1)
+            return fail(JC_ERR_INVALID, "two sweeps per launch (flag 2) needs members of one block");
     }
     if (tile) {
         const bool ok = jc_rt::tile_shape_ok(tile[0], tile[1]) && tile[2] >= 1;

@@ -33,6 +33,10 @@ hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int n
 // rounded to the storage format between the two sweeps.
 hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int qparity, int tile_y, int z_chunk,
                             int lo_dtype, hipStream_t s);
+// The same over a work list of 64-cell by 16-row tiles (groups; each
+// item's flip must be 0: a refining member holds its iterate in copy 0).
+hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
+                                  int lo_dtype, hipStream_t s);
 
 // Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
 // of d and r_lo).  Residual: r of u[parity] with fused ghosts (face

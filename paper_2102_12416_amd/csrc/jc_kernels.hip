@@ -1197,6 +1197,25 @@ hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int n
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
+                                  int lo_dtype, hipStream_t s)
+{
+    if (nitems <= 0)
+        return hipSuccess;
+    const int grid = ((nitems + 7) / 8) * 8;
+#define JC_IR2_ITEMS_CASE(TY, DT, T)                                                                            \
+    if (tile_y == TY && lo_dtype == DT) {                                                                      \
+        hipLaunchKernelGGL((k_sweep2<T, FIELD_D, 32, TY, true>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, \
+                           s, blocks, items, qparity, 0, 0, 0, nitems);                                        \
+        return hipGetLastError();                                                                              \
+    }
+    JC_IR2_ITEMS_CASE(16, 0, double)
+    JC_IR2_ITEMS_CASE(16, 1, float)
+    JC_IR2_ITEMS_CASE(16, 2, bf16)
+#undef JC_IR2_ITEMS_CASE
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int qparity, int tile_y, int z_chunk,
                             int lo_dtype, hipStream_t s)
 {

@@ -123,8 +123,8 @@ class Server:
     lanes: ascending edge bounds of the size classes; a request of edge n
     joins the first lane with n <= bound, else the last (unbounded) lane.
     An empty tuple serves everything in one group.  temporal: every size
-    class gets a lane per precision, and binary64 lanes sweep twice per
-    launch (results bitwise the same)."""
+    class gets a lane per precision, and every lane sweeps twice per launch
+    (results bitwise the same)."""
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
@@ -147,9 +147,8 @@ class Server:
         # residual norms, and so its stopping check, then do not depend on
         # who else is in the group
         self.tile = None if tile is None else tuple(int(v) for v in tile)
-        # temporal: a lane whose members are all binary64 (no refinement)
-        # is swept two sweeps per launch (bitwise the same results); the
-        # size lanes are then kept per precision, so binary64 lanes always are
+        # temporal: every lane's group sweeps twice per launch (bitwise the
+        # same results), and the size lanes are kept per precision
         self.temporal = bool(temporal)
         if self.temporal and self.window % 2:
             raise ValueError("two sweeps per launch need an even window")
@@ -191,9 +190,8 @@ class Server:
     def _regroup(self, lane):
         lane.close()
         if lane.active:
-            two = self.temporal and all(l.req.precision != "f32" for l in lane.active)
             lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream,
-                               tile=self.tile, temporal=two)
+                               tile=self.tile, temporal=self.temporal)
             lane.key = tuple(l.req.id for l in lane.active)
             self.stats["group_builds"] += 1
 

@@ -287,17 +287,53 @@ def test_temporal_group_vs_oracle(graphs):
     assert norms[0] == norms[1]
 
 
-def test_temporal_group_needs_one_block_plain_members():
+def test_temporal_group_needs_one_block_members():
     from paper_2102_12416_amd import Group, JcError, _lib as L
     say("temporal group validation")
     n = (24, 20, 18)
-    with Solver(n, block_dims=(12, 20, 18), mode="fused") as a, Solver(n, with_source=True, ir_dtype="f32") as b:
+    with Solver(n, block_dims=(12, 20, 18), mode="fused") as a:
         a.load(synth.boundary_field(n, seed=1))
-        b.load(synth.boundary_field(n, seed=1), synth.source_field(n, seed=1))
-        for s in (a, b):
-            with pytest.raises(JcError) as e:
-                Group([s], temporal=True)
-            assert e.value.code == L.JC_ERR_INVALID
+        with pytest.raises(JcError) as e:
+            Group([a], temporal=True)
+        assert e.value.code == L.JC_ERR_INVALID
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_temporal_group_with_refinement_matches_one_sweep_group(graphs):
+    """Refining members (binary64, binary32, bfloat16 storage) beside plain
+    ones in a group that sweeps twice per launch: after outer steps with
+    odd and even window lengths, every member's iterate and residual norm
+    equal those of the same group sweeping once per launch."""
+    from paper_2102_12416_amd import Group
+    specs = [((40, 36, 33), dict(with_source=True)), ((24, 24, 24), dict(with_source=True, ir_dtype="f32")),
+             ((26, 22, 20), dict(with_source=True, ir_dtype="bf16")), ((64, 20, 12), dict(with_source=True,
+             ir_dtype="f64")), ((30, 18, 41), dict(with_source=True, ir_dtype="f32")), ((17, 19, 23), {})]
+    say("temporal group with refinement", "graphs" if graphs else "eager")
+    runs = []
+    for temporal in (False, True):
+        solvers = []
+        for i, (n, kw) in enumerate(specs):
+            s = Solver(n, **kw)
+            u0 = synth.boundary_field(n, seed=50 + i)
+            b = synth.source_field(n, seed=50 + i) if kw.get("with_source") else None
+            s.load(u0, b)
+            solvers.append(s)
+        norms = []
+        with Group(solvers, use_graphs=graphs, temporal=temporal) as g:
+            for window in (25, 50, 7, 50):
+                norms.append(g.residuals())
+                g.iterate(window)
+            norms.append(g.residuals())
+        fields = [s.store().cpu().numpy() for s in solvers]
+        iters = [s.iterations for s in solvers]
+        for s in solvers:
+            s.close()
+        runs.append((norms, fields, iters))
+    (n0, f0, i0), (n1, f1, i1) = runs
+    assert i0 == i1
+    assert n0 == n1
+    for a, b in zip(f0, f1):
+        assert np.array_equal(a, b)
 
 
 def test_temporal_server_same_results():
