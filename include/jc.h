@@ -102,8 +102,9 @@ typedef struct jc_options {
                             launch (iterate k + 1 stays on chip, so each cell is read and
                             written once per two sweeps; results bitwise equal to
                             one-sweep launches).  Needs a context of one block (no face
-                            pairs); the residual sweeps of jc_solve, jc_sweep and groups
-                            run one sweep per launch.  0: one sweep per launch. */
+                            pairs); the residual sweeps of jc_solve and jc_sweep run one
+                            sweep per launch, and groups follow their own flag
+                            (jc_group_create).  0: one sweep per launch. */
 } jc_options;
 
 /* Result of a solve. */
