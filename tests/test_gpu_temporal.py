@@ -255,8 +255,9 @@ def test_temporal_shape_change_replaces_graphs():
 
 # ------------------------------------------------------------------ groups
 
+@pytest.mark.parametrize("tile", [None, (32, 8, 16)])
 @pytest.mark.parametrize("graphs", [False, True])
-def test_temporal_group_vs_oracle(graphs):
+def test_temporal_group_vs_oracle(graphs, tile):
     """A group that sweeps every member twice per launch: members of several
     sizes, with and without a source (two kernel classes), starting from
     different copies; each equals the oracle after its own sweep count, and
@@ -264,7 +265,7 @@ def test_temporal_group_vs_oracle(graphs):
     from paper_2102_12416_amd import Group
     specs = [((40, 36, 33), True, 3), ((17, 19, 23), False, 0), ((70, 20, 45), True, 1), ((1, 1, 1), False, 2),
              ((130, 9, 66), False, 5)]
-    say("temporal group", "graphs" if graphs else "eager")
+    say("temporal group", "graphs" if graphs else "eager", "tile", tile)
     norms = []
     for temporal in (True, False):
         solvers, refs = [], []
@@ -276,7 +277,7 @@ def test_temporal_group_vs_oracle(graphs):
             s.iterate(pre)                       # members start in either copy
             solvers.append(s)
             refs.append(oracle.c_jacobi(u0, pre + 17, b)[0])
-        with Group(solvers, use_graphs=graphs, temporal=temporal) as g:
+        with Group(solvers, use_graphs=graphs, temporal=temporal, tile=tile) as g:
             g.iterate(7)
             g.iterate(10)
             norms.append(g.residuals())
@@ -298,8 +299,9 @@ def test_temporal_group_needs_one_block_members():
         assert e.value.code == L.JC_ERR_INVALID
 
 
+@pytest.mark.parametrize("tile", [None, (32, 8, 16)])
 @pytest.mark.parametrize("graphs", [False, True])
-def test_temporal_group_with_refinement_matches_one_sweep_group(graphs):
+def test_temporal_group_with_refinement_matches_one_sweep_group(graphs, tile):
     """Refining members (binary64, binary32, bfloat16 storage) beside plain
     ones in a group that sweeps twice per launch: after outer steps with
     odd and even window lengths, every member's iterate and residual norm
@@ -319,7 +321,7 @@ def test_temporal_group_with_refinement_matches_one_sweep_group(graphs):
             s.load(u0, b)
             solvers.append(s)
         norms = []
-        with Group(solvers, use_graphs=graphs, temporal=temporal) as g:
+        with Group(solvers, use_graphs=graphs, temporal=temporal, tile=tile) as g:
             for window in (25, 50, 7, 50):
                 norms.append(g.residuals())
                 g.iterate(window)
