@@ -107,6 +107,8 @@ def parse():
                     help="re-tune even where a tuned shape is recorded for the workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ab", action="store_true", help="skip the device / host-staged exchange comparison")
+    ap.add_argument("--no-temporal-context", action="store_true",
+                    help="512_2x2x2: skip the one-block, two-sweeps-per-launch context figure")
     ap.add_argument("--ab-iters", type=int, default=100)
     ap.add_argument("--graphs", choices=["auto", "on", "off"], default="auto",
                     help="time a hipGraph replay of the whole window (fused mode; the sweep's time is then the "
@@ -222,6 +224,38 @@ def exchange_ab(grid, bd, seed, iters, tiles):
         out[mode]["comm_speedup_of_device"] = round(out[mode]["comm_ms_per_iter"] / d["comm_ms_per_iter"], 2)
         out[mode]["iter_speedup_of_device"] = round(out[mode]["ms_per_iter"] / d["ms_per_iter"], 2)
     return out
+
+
+def temporal_one_block(grid, seed, iters=200):
+    """Context for the bench line: the grid as one block with temporal
+    blocking (two sweeps per launch, shape from jc_autotune), timed as one
+    graph replay of `iters` iterations after a warm-up, apart from the
+    headline measurement."""
+    import torch
+
+    from paper_2102_12416_amd import Solver, synth_field
+    with Solver(grid, mode="fused", temporal=True) as s:
+        s.load(synth_field(grid, seed, 0))
+        s.autotune(reps=3)
+        s.iterate(iters)
+        s.iterate(iters)                 # captures the window's graph
+        s.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.iterate(iters)
+        e1.record(s.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        t2 = s.temporal_info()
+    cells = float(grid[0]) * grid[1] * grid[2]
+    launch_ms = 2 * ms / iters
+    return {"grid": list(grid), "blocks": 1, "kernel": "k_sweep2", "temporal_tile": [t2["rows"], t2["z_chunk"]],
+            "iterations": iters, "glups": round(cells * iters / (ms * 1e-3) / 1e9, 1),
+            "ms_per_two_sweep_launch": round(launch_ms, 5),
+            "roofline_frac": round(16 * cells / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "two sweeps per launch on one block (no inter-block exchange): bitwise the same iterate; "
+                    "not the headline, which exchanges halos between 8 blocks every iteration"}
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -704,6 +738,9 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if args.workload == "512_2x2x2" and not args.no_temporal_context:
+        print("[bench] context: the same grid as one block, two sweeps per launch", file=sys.stderr, flush=True)
+        out["temporal_one_block"] = temporal_one_block(grid, args.seed)
     if not args.no_ab and bd is not None:
         print("[bench] exchange A/B: device pairing vs host staging vs host metadata", file=sys.stderr, flush=True)
         st_tiles = TUNED_TILES.get((args.workload, "staged"), (tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]))
