@@ -15,9 +15,11 @@ Two implementations of the same definitions live here:
 Method (paper section 4.3, "Proxy Application: Jacobi3D"): Jacobi iteration
 for the 3D 7-point stencil on one undecomposed grid, fixed iteration count;
 grid, boundary, source and residual conventions as documented in the C file.
-The bfloat16 iterates of the refinement have no textbook reference beyond
-the residual certificate: parity unpinned beyond the certificate and the
-stated error.
+The refinement form is split into its steps (``residual_lo``, ``lo_sweep``,
+``ir_correct``, ``ir_step``) so that each can be pinned on its own: the
+binary32 / bfloat16 inner sweep by fixed points, monotonicity and dense
+brute force, the outer step by hand-derived one-step cases for every
+rounding point and by convergence to the dense solution.
 """
 from __future__ import annotations
 
@@ -112,16 +114,63 @@ def store_lo(x32: np.ndarray, storage: str) -> np.ndarray:
     return np.asarray(x32, dtype=np.float32)
 
 
+def residual_lo(r: np.ndarray, storage: str) -> np.ndarray:
+    """Outer-step residual for the inner sweeps: binary64 r rounded to
+    binary32, and for 'bf16' from there to bfloat16 (round to nearest even
+    both times), kept as binary32 values."""
+    return store_lo(np.asarray(r, dtype=np.float64).astype(np.float32), storage)
+
+
+def lo_sweep(d: np.ndarray, rlo: np.ndarray, storage: str) -> np.ndarray:
+    """One inner sweep of the refinement on the padded binary32 correction d
+    (zero shell): d' = lo((s(d) + r_lo) / 6) with the neighbour sum s, the
+    addition of r_lo (interior-shaped) and the division in binary32, the
+    result rounded to the storage format."""
+    s = neighbour_sum(d)
+    e = d.copy()
+    e[1:-1, 1:-1, 1:-1] = store_lo((s + rlo) / np.float32(6.0), storage)
+    return e
+
+
+def ir_correct(u: np.ndarray, r: np.ndarray, storage: str, m: int) -> np.ndarray:
+    """The correction part of one outer step: from the binary64 residual r
+    (interior-shaped), m inner Jacobi sweeps on A d = r from d = 0 with zero
+    ghosts, then u + d in binary64.  storage 'f64' keeps d and r in binary64
+    (plain sweeps with r as the source)."""
+    shape = u.shape
+    v = u.copy()
+    if storage == "f64":
+        rr = np.zeros(shape)
+        rr[1:-1, 1:-1, 1:-1] = r
+        d = np.zeros(shape)
+        for _ in range(m):
+            d = sweep(d, rr)
+        v[1:-1, 1:-1, 1:-1] = interior(u) + interior(d)
+    else:
+        rlo = residual_lo(r, storage)
+        d = np.zeros(shape, dtype=np.float32)
+        for _ in range(m):
+            d = lo_sweep(d, rlo, storage)
+        v[1:-1, 1:-1, 1:-1] = interior(u) + interior(d).astype(np.float64)
+    return v
+
+
+def ir_step(u: np.ndarray, b: np.ndarray | None, storage: str, m: int) -> np.ndarray:
+    """One outer step: binary64 residual of u, then :func:`ir_correct`."""
+    return ir_correct(u, residual_field(u, b), storage, m)
+
+
 def ir_solve(u0: np.ndarray, b: np.ndarray | None, storage: str = "f32", inner: int = 50,
              rtol: float = 1e-10, max_inner: int = 20000):
     """Mixed-precision iterative refinement with Jacobi inner sweeps.
 
     storage 'f64' keeps d and r in binary64 (no rounding); 'f32' and 'bf16'
     round r to the storage format (through binary32) and run the inner
-    sweeps with binary32 sums and division.  Returns
+    sweeps with binary32 sums and division.  Each outer step computes the
+    binary64 residual and its norm, stops when |r|/|r_0| <= rtol or the cap
+    (counted in inner sweeps) is reached, else corrects u.  Returns
     (u, rel history per outer check, inner sweeps done, status 0/1)."""
     u = u0.copy()
-    shape = u.shape
     r0 = None
     hist = []
     done = 0
@@ -139,22 +188,7 @@ def ir_solve(u0: np.ndarray, b: np.ndarray | None, storage: str = "f32", inner: 
         if done >= max_inner:
             break
         m = min(inner, max_inner - done)
-        if storage == "f64":
-            rr = np.zeros(shape)
-            rr[1:-1, 1:-1, 1:-1] = r
-            d = np.zeros(shape)
-            for _ in range(m):
-                d = sweep(d, rr)
-            u[1:-1, 1:-1, 1:-1] = interior(u) + interior(d)
-        else:
-            rlo = store_lo(r.astype(np.float32), storage)
-            d = np.zeros(shape, dtype=np.float32)
-            for _ in range(m):
-                s = neighbour_sum(d)
-                e = d.copy()
-                e[1:-1, 1:-1, 1:-1] = store_lo((s + rlo) / np.float32(6.0), storage)
-                d = e
-            u[1:-1, 1:-1, 1:-1] = interior(u) + interior(d).astype(np.float64)
+        u = ir_correct(u, r, storage, m)
         done += m
     return u, hist, done, status
 

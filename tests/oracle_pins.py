@@ -191,3 +191,166 @@ def check_residual_decay(sweep_fn):
 
 ALL_CHECKS = (check_constant, check_harmonic, check_manufactured, check_sine_mode,
               check_dense, check_monotone, check_residual_decay)
+
+
+# ------------------------------------------- refinement in low precision --
+#
+# The refinement's inner sweep runs on the correction d in binary32 or
+# bfloat16 storage with binary32 sums and division; its outer step takes a
+# binary64 residual and updates u in binary64.  The checks below take
+#   lo_sweep_fn(d, rlo, storage) -> d'   (padded binary32 d, interior r_lo)
+#   step_fn(u, b, storage, m) -> u'      (one outer step, m inner sweeps)
+# and pin them to facts that do not come from the oracle.
+
+def bf16_nearest(x32):
+    """binary32 values rounded to the nearest bfloat16 value, ties to the
+    one with an even last bit, returned as binary32.  Written as a choice
+    between the two bfloat16 neighbours by distance (exact in binary64),
+    independently of the oracle's bit arithmetic; finite inputs only."""
+    x = np.ascontiguousarray(x32, dtype=np.float32)
+    bits = x.view(np.uint32)
+    down = (bits & np.uint32(0xFFFF0000)).view(np.float32)
+    up_bits = (bits & np.uint32(0xFFFF0000)) + np.uint32(0x10000)
+    up = up_bits.view(np.float32)
+    xd, dd, ud = x.astype(np.float64), down.astype(np.float64), up.astype(np.float64)
+    dist_down, dist_up = np.abs(xd - dd), np.abs(ud - xd)
+    down_even = ((bits >> np.uint32(16)) & np.uint32(1)) == 0
+    take_up = (dist_up < dist_down) | ((dist_up == dist_down) & ~down_even)
+    exact = (bits & np.uint32(0xFFFF)) == 0
+    return np.where(exact, x, np.where(take_up, up, down)).astype(np.float32)
+
+
+def to_storage(x, storage):
+    """binary32 (or binary64) values rounded to the storage format, as binary32."""
+    x32 = np.asarray(x, dtype=np.float64).astype(np.float32)
+    return bf16_nearest(x32) if storage == "bf16" else x32
+
+
+def exact_in(x, storage):
+    x = np.asarray(x, dtype=np.float64)
+    return np.array_equal(to_storage(x, storage).astype(np.float64), x)
+
+
+def lo_as_sweep(lo_sweep_fn, storage):
+    """The inner sweep as a sweep_fn(u, b) of the binary64 checks above, for
+    fields whose every value is exact in the storage format (refused
+    otherwise, so that a check never tests a rounded copy of its field)."""
+    def f(u, b):
+        if not exact_in(u, storage) or (b is not None and not exact_in(b, storage)):
+            raise ValueError("field not exact in %s" % storage)
+        d = np.asarray(u, dtype=np.float32)
+        nz, ny, nx = (n - 2 for n in u.shape)
+        rlo = np.zeros((nz, ny, nx), np.float32) if b is None else \
+            np.ascontiguousarray(b[1:-1, 1:-1, 1:-1], dtype=np.float32)
+        return np.asarray(lo_sweep_fn(d, rlo, storage), dtype=np.float64)
+    return f
+
+
+def check_lo_fixed_points(lo_sweep_fn, storage):
+    """Constant, discrete-harmonic and manufactured (u = x^2, r_lo = -2)
+    fields are fixed points of the inner sweep too: their values and every
+    neighbour sum are small integers or short dyadic fractions, exact in
+    binary32 and in bfloat16, and s/6 is exact."""
+    f = lo_as_sweep(lo_sweep_fn, storage)
+    for check in (check_constant, check_harmonic, check_manufactured):
+        ok, detail = check(f)
+        if not ok:
+            return False, "%s (%s)" % (detail, storage)
+    return True, ""
+
+
+def check_lo_monotone(lo_sweep_fn, storage):
+    """Zero source, shell g >= 0 in the storage format, d0 = 0: the inner
+    iterates are pointwise non-decreasing and bounded by max g, bitwise
+    (sums, the division and rounding to nearest are monotone, max g is a
+    storage value)."""
+    f = lo_as_sweep(lo_sweep_fn, storage)
+    rng = np.random.default_rng(13)
+    g = to_storage(rng.random((7 + 2, 9 + 2, 8 + 2)), storage).astype(np.float64)
+    u = g.copy()
+    u[1:-1, 1:-1, 1:-1] = 0.0
+    for _ in range(25):
+        v = f(u, None)
+        if not (np.all(v >= u) and np.all(v <= g.max())):
+            return False, "monotonicity/maximum principle violated (%s)" % storage
+        u = v
+    return True, ""
+
+
+def check_lo_dense(lo_sweep_fn, storage):
+    """Brute force on tiny grids with zero ghosts (the correction equation):
+    for small-integer d and r_lo every binary32 sum is exact, so one inner
+    sweep is the binary32 quotient of the dense product ((D - A) d + r_lo)
+    by 6, rounded to the storage format; and the inner iterates approach
+    A^-1 r_lo to within the storage precision."""
+    rng = np.random.default_rng(17)
+    limit_tol = {"f32": 2e-6, "bf16": 4e-2}[storage]
+    for (nx, ny, nz) in ((1, 1, 1), (2, 2, 2), (3, 2, 4), (4, 4, 4)):
+        zero = np.zeros((nz + 2, ny + 2, nx + 2))
+        A, _ = dense_system(nx, ny, nz, zero, None)
+        offdiag = -(A - np.diag(np.diag(A)))
+        d = zero.astype(np.float32)
+        d[1:-1, 1:-1, 1:-1] = rng.integers(-8, 9, (nz, ny, nx))
+        r = rng.integers(-40, 41, (nz, ny, nx)).astype(np.float32)
+        num = offdiag @ d[1:-1, 1:-1, 1:-1].ravel().astype(np.float64) + r.ravel()
+        ref = to_storage(np.float32(num) / np.float32(6.0), storage)
+        got = np.asarray(lo_sweep_fn(d, r, storage))[1:-1, 1:-1, 1:-1].ravel()
+        if not np.array_equal(got, ref):
+            return False, "dense inner sweep mismatch at %s (%s)" % ((nx, ny, nz), storage)
+        exact = np.linalg.solve(A, r.ravel().astype(np.float64))
+        e = zero.astype(np.float32)
+        for _ in range(300):
+            e = lo_sweep_fn(e, r, storage)
+        err = np.max(np.abs(np.asarray(e, np.float64)[1:-1, 1:-1, 1:-1].ravel() - exact))
+        if not err <= limit_tol * np.max(np.abs(exact)):
+            return False, "inner limit off by %.3g at %s (%s)" % (err, (nx, ny, nz), storage)
+    return True, ""
+
+
+def check_ir_limit(step_fn, storage):
+    """Refinement with a binary64 outer residual and update converges to the
+    exact solution A^-1 b_eff (numpy.linalg.solve of the dense system) to
+    binary64 accuracy, whatever the inner storage: each outer step cuts the
+    error by the inner solve's accuracy."""
+    rng = np.random.default_rng(19)
+    for (nx, ny, nz) in ((1, 1, 1), (2, 2, 2), (3, 2, 4), (4, 4, 4)):
+        g = rng.random((nz + 2, ny + 2, nx + 2))
+        b = np.zeros_like(g)
+        b[1:-1, 1:-1, 1:-1] = rng.random((nz, ny, nx)) * 2 - 1
+        A, beff = dense_system(nx, ny, nz, g, b)
+        exact = np.linalg.solve(A, beff)
+        u = g.copy()
+        u[1:-1, 1:-1, 1:-1] = 0.0
+        for _ in range(30):
+            u = step_fn(u, b, storage, 50)
+        if not np.array_equal(u[0], g[0]) or not np.array_equal(u[:, 0], g[:, 0]):
+            return False, "shell changed (%s)" % storage
+        err = np.max(np.abs(u[1:-1, 1:-1, 1:-1].ravel() - exact))
+        if not err <= 1e-12 * max(1.0, np.max(np.abs(exact))):
+            return False, "refinement limit off by %.3g at %s (%s)" % (err, (nx, ny, nz), storage)
+    return True, ""
+
+
+def load_refinement_cases(path):
+    import json
+    with open(path) as f:
+        return json.load(f)["cases"]
+
+
+def check_ir_goldens(step_fn, storage, cases):
+    """Hand-derived one-outer-step cases (tests/golden/refinement_cases.json):
+    the rounding of r through binary32 to the storage format, the correction
+    rounded to storage between inner sweeps, binary32 neighbour sums in the
+    stencil's order, and the binary64 update; bitwise."""
+    for case in cases:
+        if case["storage"] != storage:
+            continue
+        nx, ny, nz = case["n"]
+        u0 = np.array(case["u0"], dtype=np.float64).reshape(nz + 2, ny + 2, nx + 2)
+        b = np.array(case["b"], dtype=np.float64).reshape(nz + 2, ny + 2, nx + 2)
+        got = step_fn(u0, b, storage, case["inner"])[1:-1, 1:-1, 1:-1].ravel()
+        exp = np.array([float.fromhex(h) for h in case["expected_hex"]])
+        if not np.array_equal(got, exp):
+            return False, "golden %s: %s vs %s" % (case["name"], [v.hex() for v in got],
+                                                    case["expected_hex"])
+    return True, ""

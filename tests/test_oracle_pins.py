@@ -185,6 +185,114 @@ def test_ir_low_precision_converges_and_certifies(storage):
     assert np.array_equal(uc, u) and dc == done and sc == st
 
 
+# ---------------------------------------- refinement in low precision: pins
+
+REFINE_CASES = pins.load_refinement_cases(os.path.join(GOLDEN, "refinement_cases.json"))
+
+
+def c_ir_step(u, b, storage, m):
+    """One outer step of the C oracle: a solve capped at m inner sweeps with
+    rtol = 0, which stops after the first correction (or before it, when the
+    residual is exactly zero and the correction would be zero too)."""
+    u2, hist, done, _ = oracle.c_ir_solve(np.ascontiguousarray(u), None if b is None else
+                                          np.ascontiguousarray(b), storage=storage, inner=m,
+                                          rtol=0.0, max_inner=m)
+    assert done == m or (done == 0 and hist == [0.0])
+    return u2
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("check", [pins.check_lo_fixed_points, pins.check_lo_monotone,
+                                   pins.check_lo_dense], ids=lambda c: c.__name__)
+def test_oracle_inner_sweep_passes_pin(storage, check):
+    ok, detail = check(oracle.lo_sweep, storage)
+    assert ok, detail
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("impl", [oracle.ir_step, c_ir_step], ids=["numpy", "c"])
+def test_oracle_refinement_step_passes_pins(impl, storage):
+    ok, detail = pins.check_ir_goldens(impl, storage, REFINE_CASES)
+    assert ok, detail
+    ok, detail = pins.check_ir_limit(impl, storage)
+    assert ok, detail
+
+
+def test_refinement_goldens_cover_both_storages():
+    kinds = {c["storage"] for c in REFINE_CASES}
+    assert kinds == {"f32", "bf16"} and len(REFINE_CASES) >= 7
+
+
+def _bf16_direct(x64):
+    """binary64 values rounded once to 8 significand bits (nearest, ties to
+    even): the reading the refinement does NOT take (it goes through binary32)."""
+    m, e = np.frexp(np.asarray(x64, dtype=np.float64))
+    return np.ldexp(np.rint(m * 256.0), e - 8).astype(np.float32)
+
+
+def _ir_mutant(kind):
+    """One outer step of the refinement with one plausible mistake."""
+    def step(u, b, storage, m):
+        if kind == "f32_outer":
+            u32 = u.astype(np.float32)
+            b32 = None if b is None else b.astype(np.float32)
+            r = oracle.residual_field(u32, b32).astype(np.float64)
+        else:
+            r = oracle.residual_field(u, b)
+        if kind == "direct_bf16":
+            rlo = _bf16_direct(r)
+        elif kind == "rlo_unrounded":
+            rlo = r.astype(np.float32) if storage == "bf16" else r
+        else:
+            rlo = oracle.residual_lo(r, storage)
+        d = np.zeros(u.shape, dtype=np.float32)
+        if kind == "inhomogeneous_ghosts":
+            d = u.astype(np.float32)
+            d[1:-1, 1:-1, 1:-1] = 0.0
+        for _ in range(m):
+            e = d.copy()
+            if kind == "f64_sums":
+                s = oracle.neighbour_sum(d.astype(np.float64))
+                v = ((s + rlo.astype(np.float64)) / 6.0).astype(np.float32)
+            else:
+                s = oracle.neighbour_sum(d)
+                v = ((s - rlo) if kind == "rlo_sign" else (s + rlo)) / np.float32(6.0)
+            e[1:-1, 1:-1, 1:-1] = v if kind == "d_unrounded" else oracle.store_lo(v, storage)
+            d = e
+        dd = oracle.store_lo(oracle.interior(d), storage).astype(np.float64)
+        v = u.copy()
+        if kind == "update_sign":
+            v[1:-1, 1:-1, 1:-1] = oracle.interior(u) - dd
+        elif kind == "f32_update":
+            v[1:-1, 1:-1, 1:-1] = (oracle.interior(u).astype(np.float32)
+                                   + dd.astype(np.float32)).astype(np.float64)
+        else:
+            v[1:-1, 1:-1, 1:-1] = oracle.interior(u) + dd
+        return v
+    return step
+
+
+IR_MUTANTS = [(k, s) for k in ("rlo_unrounded", "f64_sums", "rlo_sign", "update_sign", "f32_outer",
+                               "f32_update", "inhomogeneous_ghosts") for s in ("f32", "bf16")] + \
+    [("direct_bf16", "bf16"), ("d_unrounded", "bf16")]
+
+
+def test_ir_mutant_harness_without_mistake_passes():
+    """The mutant builder with no mistake is the oracle's step, bit for bit."""
+    rng = np.random.default_rng(5)
+    u = rng.random((6, 5, 7))
+    b = rng.random((6, 5, 7)) * 2 - 1
+    for storage in ("f32", "bf16"):
+        assert np.array_equal(_ir_mutant("none")(u, b, storage, 7), oracle.ir_step(u, b, storage, 7))
+
+
+@pytest.mark.parametrize("kind,storage", IR_MUTANTS, ids=["%s-%s" % m for m in IR_MUTANTS])
+def test_ir_planted_mistake_fails_a_pin(kind, storage):
+    bad = _ir_mutant(kind)
+    results = [pins.check_ir_goldens(bad, storage, REFINE_CASES), pins.check_ir_limit(bad, storage)]
+    assert any(not ok for ok, _ in results), "refinement mutant %s/%s passed every pin" % (kind, storage)
+
+
 def test_ir_cap_counts_inner_sweeps():
     n = (8, 8, 8)
     u0 = synth.boundary_field(n, seed=1)
