@@ -56,6 +56,8 @@ PAPER_COMM_SPEEDUPS = {
 TUNED_TILES = {
     ("512_2x2x2", "fused"): (64, 32, 256),
     ("512_2x2x2", "staged"): (64, 32, 64),
+    ("768_8x8x8", "fused"): (32, 32, 16),
+    ("768_uneven", "fused"): (32, 16, 16),
 }
 
 # two-sweep launch shape (rows, planes per work-group) from jc_autotune on
@@ -162,7 +164,8 @@ def recorded_traffic(workload, mode, tile):
 def sweep_source_sha256(kernel="k_sweep"):
     """Fingerprint of a sweep kernel: its region of jc_kernels.hip (the
     one-sweep kernel with the helpers it defines; the two-sweep kernel
-    also with those helpers) plus the shared table definitions it reads."""
+    also with those helpers) plus the shared table definitions and the
+    division helpers it includes."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2102_12416_amd", "csrc")
     text = open(os.path.join(csrc, "jc_kernels.hip")).read()
@@ -174,6 +177,7 @@ def sweep_source_sha256(kernel="k_sweep"):
         d = text.index("// ---- two-step sweep: end")
         h.update(text[c:d].encode())
     h.update(open(os.path.join(csrc, "jc_types.h"), "rb").read())
+    h.update(open(os.path.join(csrc, "jc_div6.h"), "rb").read())
     return h.hexdigest()
 
 

@@ -10,7 +10,7 @@
 // per cell update in FP64).
 //
 // Bit-exactness: the neighbour sum is formed in one fixed order and
-// divided by 6 with an IEEE division; the library is built with
+// divided by 6, correctly rounded (jc_div6.h); the library is built with
 // -ffp-contract=off, so no multiply-add is fused and every block of every
 // decomposition computes the same bits for the same cell.
 
@@ -18,6 +18,7 @@
 
 #include <type_traits>
 
+#include "jc_div6.h"
 #include "jc_kernels.h"
 
 namespace jc {
@@ -206,63 +207,6 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int o = 32; o > 0; o >>= 1)
         v = v + __shfl_xor(v, o, 64);
     return v;
-}
-
-// Correctly rounded s / 6 without the general division sequence
-// (Markstein, IBM J. Res. Dev. 34(1), 1990): with y = RN(1/6), q = RN(s y)
-// is a faithful quotient, r = s - 6q is exact through an FMA, and
-// RN(q + r y) is the correctly rounded quotient whenever it is not
-// subnormal.  Tiny s (and zero, for the sign of the result) take the IEEE
-// division; the result is bit-identical to s / 6 either way.
-__device__ __forceinline__ double div6(double s)
-{
-    const double y = 0x1.5555555555555p-3;
-    const double q = s * y;
-    const double r = __builtin_fma(-6.0, q, s);
-    double v = __builtin_fma(r, y, q);
-    if (__builtin_expect(__builtin_fabs(s) < 0x1p-1000, 0))
-        v = s / 6.0;
-    return v;
-}
-
-__device__ __forceinline__ float div6(float s)
-{
-    const float y = 0x1.555556p-3f;
-    const float q = s * y;
-    const float r = __builtin_fmaf(-6.0f, q, s);
-    float v = __builtin_fmaf(r, y, q);
-    if (__builtin_expect(__builtin_fabsf(s) < 0x1p-100f, 0))
-        v = s / 6.0f;
-    return v;
-}
-
-// The same for a pair, with one (rarely taken) branch to the IEEE division.
-__device__ __forceinline__ double div6_fast(double s)
-{
-    const double y = 0x1.5555555555555p-3;
-    const double q = s * y;
-    return __builtin_fma(__builtin_fma(-6.0, q, s), y, q);
-}
-
-__device__ __forceinline__ float div6_fast(float s)
-{
-    const float y = 0x1.555556p-3f;
-    const float q = s * y;
-    return __builtin_fmaf(__builtin_fmaf(-6.0f, q, s), y, q);
-}
-
-__device__ __forceinline__ bool div6_tiny(double s) { return __builtin_fabs(s) < 0x1p-1000; }
-__device__ __forceinline__ bool div6_tiny(float s) { return __builtin_fabsf(s) < 0x1p-100f; }
-
-template <typename C>
-__device__ __forceinline__ void div6_pair(C sa, C sb, C& va, C& vb)
-{
-    va = div6_fast(sa);
-    vb = div6_fast(sb);
-    if (__builtin_expect(div6_tiny(sa) || div6_tiny(sb), 0)) {
-        va = div6_tiny(sa) ? sa / C(6) : va;
-        vb = div6_tiny(sb) ? sb / C(6) : vb;
-    }
 }
 
 // Planes of loads a sweep keeps in flight ahead of the plane it computes.

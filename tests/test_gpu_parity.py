@@ -257,17 +257,32 @@ def test_kernel_timing_counts():
 
 # --------------------------------------------------------- full-size cases
 
+_FULL_ORACLE = {}
+
+
+def full_oracle(n, iters):
+    """The C oracle's iterate after `iters` sweeps of the undecomposed grid
+    with the seed-12416 boundary (computed once per module: 512^3 x 1000
+    and 768^3 x 500 take 10-25 s on the host's cores)."""
+    key = (n, iters)
+    if key not in _FULL_ORACLE:
+        _FULL_ORACLE.clear()
+        say("oracle", n, iters, "sweeps on", oracle.num_threads(), "threads")
+        _FULL_ORACLE[key] = oracle.c_jacobi(synth.boundary_field(n, seed=12416), iters)[0]
+    return _FULL_ORACLE[key]
+
+
 @pytest.mark.parametrize("mode", ["fused", "staged"])
 def test_512_decomposed_full_size(mode):
     """512^3 as 2x2x2 blocks of 256^3 in the launch configuration the
     benchmark times for each mode (its stored tile shape): sampled cells
-    after 6 iterations equal the oracle's local computation; 1000
-    iterations equal the single-block run bit for bit and obey the maximum
-    principle."""
+    after 6 iterations equal the oracle's local computation; after 1000
+    iterations the whole iterate equals the oracle's bit for bit (and the
+    single-block run's)."""
     from bench import TUNED_TILES
     n = (512, 512, 512)
     tx, ty, zc = TUNED_TILES[("512_2x2x2", mode)]
-    say("512^3 2x2x2", mode, "tile", tx, ty, zc, "sampled + bitwise vs single block")
+    say("512^3 2x2x2", mode, "tile", tx, ty, zc, "sampled, then 1000 iterations vs the oracle")
     u0 = synth.boundary_field(n, seed=12416)
     with Solver(n, block_dims=(256, 256, 256), mode=mode, use_graphs=False, tile_x=tx, tile_y=ty,
                 z_chunk=zc) as s:
@@ -282,9 +297,10 @@ def test_512_decomposed_full_size(mode):
                   (1, 256, 257), (257, 1, 512), (256, 512, 1)]
         for c in cells:
             assert got[c] == local_oracle(u0, None, c, 6), c
+        del got
         s.iterate(994)
         dec = s.store().cpu().numpy()
-    assert dec.max() <= u0.max() and dec[1:-1, 1:-1, 1:-1].min() >= 0.0
+    assert np.array_equal(dec, full_oracle(n, 1000))
     with Solver(n, mode="staged") as one:
         one.load(u0)
         one.iterate(1000)
@@ -295,17 +311,21 @@ def test_512_decomposed_full_size(mode):
 @pytest.mark.parametrize("variant", ["uniform", "uneven"])
 def test_768_overdecomposed_full_size(variant):
     """768^3 in 512 blocks of 96^3 (or the seeded uneven rectilinear cuts),
-    fused, 500 iterations: bitwise equal to one block of the same grid."""
+    fused, in the benchmark's tile shape, 500 iterations: the whole iterate
+    equals the oracle's bit for bit (and one block of the same grid)."""
+    from bench import TUNED_TILES
     n = (768, 768, 768)
-    say("768^3", variant)
+    wl = "768_8x8x8" if variant == "uniform" else "768_uneven"
+    tx, ty, zc = TUNED_TILES[(wl, "fused")]
+    say("768^3", variant, "tile", tx, ty, zc, "500 iterations vs the oracle")
     u0 = synth.boundary_field(n, seed=12416)
     kw = dict(block_dims=(96, 96, 96)) if variant == "uniform" else \
         dict(cuts=[synth.uneven_cuts(768, 32, 160, seed=12416, axis=a) for a in range(3)])
-    # the shape jc_autotune keeps for these workloads at start-up
-    with Solver(n, mode="fused", tile_x=32, tile_y=32, z_chunk=16, **kw) as s:
+    with Solver(n, mode="fused", tile_x=tx, tile_y=ty, z_chunk=zc, **kw) as s:
         s.load(u0)
         s.iterate(500)
         dec = s.store().cpu().numpy()
+    assert np.array_equal(dec, full_oracle(n, 500))
     with Solver(n, mode="staged") as one:
         one.load(u0)
         one.iterate(500)
@@ -342,28 +362,81 @@ def test_autotune_keeps_iterate_and_results(mode):
         assert np.array_equal(s.store().cpu().numpy(), ref)
 
 
-def test_division_edge_values_bitwise():
-    """Dirichlet values that make neighbour sums zero, negative zero,
-    subnormal or huge: the sweep's quotient is the correctly rounded s / 6
-    bit for bit, signs of zero included."""
-    n = (9, 8, 7)
-    say("division edge values")
-    rng = np.random.default_rng(31)
-    special = np.array([0.0, -0.0, 5e-324, -5e-324, 1e-310, 2.2250738585072014e-308, 1e-300, -3.5e-320,
-                        1e300, -2.5e307, 6.0, -6.0, 1.0 / 3.0])
+def same_bits_or_nan(a, b):
+    """Bitwise equality where either side is a number (signs of zero and
+    infinities included); a NaN must face a NaN, of any payload (IEEE 754
+    fixes no payload for the NaN an operation returns, and the host and the
+    GPU produce different ones for inf - inf)."""
+    na, nb = np.isnan(a), np.isnan(b)
+    return bool(np.array_equal(na, nb) and np.array_equal(a[~na].view(np.uint64), b[~nb].view(np.uint64)))
+
+
+EDGE_VALUES = np.array([0.0, -0.0, 5e-324, -5e-324, 1e-310, 2.2250738585072014e-308, 1e-300, -3.5e-320,
+                        1e300, -1.7e308, 1.7e308, np.inf, -np.inf, 6.0, -6.0, 1.0 / 3.0])
+
+
+def edge_field(n, seed):
+    rng = np.random.default_rng(seed)
     u0 = np.zeros((n[2] + 2, n[1] + 2, n[0] + 2))
     shell = np.ones(u0.shape, bool)
     shell[1:-1, 1:-1, 1:-1] = False
-    u0[shell] = rng.choice(special, size=int(shell.sum()))
+    u0[shell] = rng.choice(EDGE_VALUES, size=int(shell.sum()))
     u0[1:-1, 1:-1, 1:-1] = -0.0
+    return u0
+
+
+@pytest.mark.parametrize("path", ["staged", "fused", "one_block", "temporal"])
+def test_division_edge_values_bitwise(path):
+    """Dirichlet values that make neighbour sums zero, negative zero,
+    subnormal, huge, overflowing to +-inf, infinite and NaN (inf - inf):
+    the sweep's quotient is s / 6 bit for bit, signs of zero and infinities
+    included, on every sweep path (staged and fused blocks, one block, two
+    sweeps per launch)."""
+    n = (9, 8, 7)
+    say("division edge values", path)
+    u0 = edge_field(n, 31)
     ref = u0
-    for _ in range(3):
-        ref = oracle.sweep(ref)
-    with Solver(n, block_dims=(5, 4, 7)) as s:
+    with np.errstate(all="ignore"):
+        for _ in range(3):
+            ref = oracle.sweep(ref)
+    kw = dict(staged=dict(block_dims=(5, 4, 7)), fused=dict(block_dims=(5, 4, 7), mode="fused"),
+              one_block={}, temporal=dict(temporal=True))[path]
+    with Solver(n, **kw) as s:
         s.load(u0)
         s.iterate(3)
         got = s.store().cpu().numpy()
-    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    assert np.isinf(ref).any() and np.isnan(ref).any()
+    assert same_bits_or_nan(got, ref)
+
+
+@pytest.mark.parametrize("temporal", [False, True])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_refinement_overflow_bitwise(dtype, temporal):
+    """Refinement in binary32 arithmetic where the residual overflows the
+    storage format (r_lo = +inf) and the inner sweeps' neighbour sums
+    overflow binary32: the correction is +inf there, as the oracle's
+    binary32 division gives, and the updated iterate matches the oracle's
+    outer step bit for bit (NaN where both have one).  The next residual is
+    not finite, so the solve ends with JC_ERR_NONFINITE."""
+    n = (9, 8, 12)
+    say("refinement overflow", dtype, "temporal" if temporal else "")
+    u0 = np.zeros((n[2] + 2, n[1] + 2, n[0] + 2))
+    u0[0] = 1e38
+    b = np.zeros_like(u0)
+    b[1:-1, 1:-1, 1:-1] = np.random.default_rng(3).random((n[2], n[1], n[0]))
+    b[1, 1:-1, 1:-1] += 3e38        # r = b + 1e38 from the z = 0 shell: beyond binary32, r_lo = +inf
+    b[6, 1:-1, 1:-1] += 3.3e38      # r_lo finite; the second sweep's neighbour sums overflow binary32
+    m = 3
+    with np.errstate(all="ignore"):
+        ref = oracle.ir_step(u0, b, dtype, m)
+    assert np.isinf(ref).any() and np.isfinite(ref[1:-1, 1:-1, 1:-1]).any()
+    with Solver(n, with_source=True, ir_dtype=dtype, temporal=temporal) as s:
+        s.load(u0, b)
+        with pytest.raises(JcError) as e:
+            s.solve_ir(inner=m, rtol=0.0, max_inner=m)
+        assert e.value.code == L.JC_ERR_NONFINITE
+        got = s.store().cpu().numpy()
+    assert same_bits_or_nan(got, ref)
 
 
 @pytest.mark.parametrize("exchange", ["host", "metadata"])
