@@ -78,3 +78,55 @@ def test_admission_respects_budget_and_rejects_oversize():
     assert res[-1].rejected and not any(r.rejected for r in res[:-1])
     s = summarize(res, makespan=1.0)
     assert s["served"] == len(REQS) and s["rejected"] == 1
+
+
+# Requests that join while others are mid-solve: a mix of sizes and
+# precisions, admitted one by one as memory frees up (a budget that holds
+# only two or three solves) or arriving over time on the wall clock.
+JOIN_REQS = [Request(id=i, arrival=0.0, n=n, precision=p, seed=600 + i) for i, (n, p) in enumerate(
+    [(40, "f64"), (24, "f32"), (32, "f64"), (20, "f32"), (36, "f32"), (16, "f64"), (28, "f64"), (44, "f32")])]
+
+
+def joined_mid_solve(res):
+    """Ids of requests admitted while another request was on the GPU."""
+    return [r.id for r in res if any(o.id != r.id and o.admitted < r.admitted < o.finished for o in res)]
+
+
+@pytest.mark.parametrize("how", ["budget", "staggered"])
+def test_requests_joining_mid_solve_same_as_alone(how):
+    """Continuous batching proper: requests admitted while others are
+    mid-solve (as memory frees up, or as they arrive) give each the same
+    iterate, sweep count, stop and residual as when served alone, and the
+    iterate is the oracle's (plain Jacobi, or the refinement) stopped at the
+    same check."""
+    import dataclasses
+    say("server joins mid-solve", how)
+    max_iter = 3000
+    if how == "budget":
+        sizes = sorted(request_footprint(r.n, r.precision) for r in JOIN_REQS)
+        budget = sizes[-1] + sizes[-2]
+        reqs = JOIN_REQS
+        srv = Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=max_iter, keep_fields=True)
+        res = srv.run(reqs, realtime=False)
+        assert srv.stats["peak_bytes"] <= budget
+    else:
+        reqs = [dataclasses.replace(r, arrival=0.02 * i) for i, r in enumerate(JOIN_REQS)]
+        srv = Server(budget_bytes=1 << 34, window=50, rtol=1e-10, max_iter=max_iter, keep_fields=True)
+        res = srv.run(reqs, realtime=True)
+    assert not any(r.rejected for r in res)
+    joined = joined_mid_solve(res)
+    assert len(joined) >= 3, joined
+    for r in reqs:
+        _, alone = serve([r], max_iter=max_iter)
+        a, m = alone[0], res[r.id]
+        assert (a.iters, a.converged, a.rel_resid) == (m.iters, m.converged, m.rel_resid), r.id
+        assert np.array_equal(a.field, m.field), r.id
+        n = (r.n,) * 3
+        u0 = synth.boundary_field(n, seed=r.seed)
+        b = synth.source_field(n, seed=r.seed)
+        if r.precision == "f64":
+            ref, _ = oracle.c_jacobi(u0, m.iters, b)
+        else:
+            ref, _, done, st = oracle.c_ir_solve(u0, b, storage="f32", inner=50, rtol=1e-10, max_inner=max_iter)
+            assert done == m.iters and (st == 0) == m.converged, r.id
+        assert np.array_equal(m.field, ref), r.id

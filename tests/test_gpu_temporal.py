@@ -339,9 +339,10 @@ def test_temporal_group_with_refinement_matches_one_sweep_group(graphs, tile):
 
 
 def test_temporal_server_same_results():
-    """A server whose all-binary64 lanes sweep twice per launch returns the
-    same iterates, sweep counts and residuals as one sweep per launch; a
-    lane mixing precisions keeps one sweep per launch."""
+    """A server whose lanes sweep twice per launch (temporal=True keeps its
+    size lanes per precision, binary64 and binary32-refined, and every lane
+    takes two sweeps per launch) returns the same iterates, sweep counts and
+    residuals as one sweep per launch."""
     from paper_2102_12416_amd.server import Request, Server
     say("temporal server")
     reqs = [Request(id=0, arrival=0.0, n=24, precision="f64", seed=701),
