@@ -263,6 +263,26 @@ int jc_group_footprint(const jc_group* g, size_t* bytes);
 /* Attach caller-owned scratch (>= footprint, 256-byte aligned); orders the
  * group stream after every member's queued work; uploads the tables. */
 int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes);
+/* For callers that cannot allocate memory -- code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation: jc_group_bind with
+ * the library's own device scratch instead of caller memory.  Each device
+ * holds one static array of JC_STATIC_SCRATCH_BYTES (16 MiB, kept until
+ * the process ends); the group's scratch (jc_group_footprint) must fit in
+ * it, else JC_ERR_NOMEM.  The array of the current device (hipGetDevice;
+ * the members' arenas must be on it) is held by this group until
+ * jc_group_destroy: binding a second group on the same device meanwhile
+ * returns JC_ERR_STATE.  The used range is cleared before the tables are
+ * uploaded (the array keeps the previous group's contents otherwise).
+ * Allocates nothing: no device or pinned memory and no events -- the
+ * group stream is ordered after the members' streams by waiting for them
+ * on the host, and residuals come back through a pageable host buffer
+ * made at jc_group_create.  Everything else is as after jc_group_bind.
+ * Graph capture (flags bit 0) instantiates graphs in jc_group_iterate,
+ * which allocates: create the group without it for an allocation-free
+ * loop.  Overlapping use of one device's array by two groups would race;
+ * the ownership rule above rejects it.  Waits for the group stream. */
+#define JC_STATIC_SCRATCH_BYTES 16777216
+int jc_group_bind_static(jc_group* g);
 /* n sweeps of every member (inner sweeps for refining members).
  * JC_ERR_STATE if a refining member's residual is due, or if refining
  * members of one storage format are at different points of their step

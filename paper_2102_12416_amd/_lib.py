@@ -20,6 +20,7 @@ JC_ERR_NOMEM = -2
 JC_ERR_DEVICE = -3
 JC_ERR_STATE = -4
 JC_ERR_NONFINITE = -5
+JC_STATIC_SCRATCH_BYTES = 16 << 20     # jc_group_bind_static: per-device static scratch
 
 JC_F64, JC_F32, JC_BF16, JC_NONE = 0, 1, 2, -1
 JC_FIELD_U, JC_FIELD_B = 0, 1
@@ -84,6 +85,7 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(VP)]),
     "jc_group_footprint": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_size_t)]),
     "jc_group_bind": (ctypes.c_int, [VP, VP, ctypes.c_size_t]),
+    "jc_group_bind_static": (ctypes.c_int, [VP]),
     "jc_group_iterate": (ctypes.c_int, [VP, I64]),
     "jc_group_residuals": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
     "jc_group_destroy": (None, [VP]),

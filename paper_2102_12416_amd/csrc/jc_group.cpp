@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -62,7 +63,9 @@ struct jc_group {
     size_t off_desc = 0, off_items = 0, off_items2 = 0, off_partials = 0, off_lohi = 0, off_out = 0, footprint = 0;
     char* scratch = nullptr;
     bool bound = false;
-    double* h_out = nullptr;            // pinned, one per member
+    double* h_out = nullptr;            // pinned, one per member (or h_out_plain)
+    std::vector<double> h_out_plain;    // pageable, one per member: the static-scratch binding
+    int static_dev = -1;                // device whose static scratch the group holds (-1: none)
     int parity = 0;                     // launch parity; items hold member flips
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> events;
@@ -328,6 +331,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     g->off_lohi = off; off = align_up(off + sizeof(int32_t) * g->lohi.size(), kAlign);
     g->off_out = off; off = align_up(off + sizeof(double) * n, kAlign);
     g->footprint = off;
+    g->h_out_plain.assign(n, 0.0);
     *out = g;
     return JC_OK;
 }
@@ -340,36 +344,44 @@ int jc_group_footprint(const jc_group* g, size_t* bytes)
     return JC_OK;
 }
 
-int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes)
+namespace {
+
+// Attach scratch and upload the tables.  plain: the allocation-free
+// binding -- residuals come back through the group's pageable host buffer
+// and the group stream is ordered after the members' streams by waiting
+// for those streams on the host, so no pinned memory or event is created.
+int bind_common(jc_group* g, char* scratch, bool plain)
 {
-    if (!g)
-        return fail(JC_ERR_INVALID, "NULL group");
-    if (g->bound)
-        return fail(JC_ERR_STATE, "group is already bound");
-    if (!dev_scratch || reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
-        return fail(JC_ERR_INVALID, "scratch must be a 256-byte aligned device pointer");
-    if (bytes < g->footprint)
-        return fail(JC_ERR_NOMEM, "scratch smaller than jc_group_footprint");
-    g->scratch = static_cast<char*>(dev_scratch);
-    int st = ghip(hipHostMalloc(reinterpret_cast<void**>(&g->h_out), sizeof(double) * g->members.size(),
+    g->scratch = scratch;
+    int st = JC_OK;
+    if (plain) {
+        g->h_out = g->h_out_plain.data();
+        for (jc_ctx* c : g->members)
+            if (c->stream != g->stream && st == JC_OK)
+                st = ghip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        // the static scratch keeps the last group's contents: clear the
+        // range this group uses before its tables go in
+        if (st == JC_OK)
+            st = ghip(jc::launch_zero(scratch, g->footprint, g->stream), "clear scratch");
+    } else {
+        st = ghip(hipHostMalloc(reinterpret_cast<void**>(&g->h_out), sizeof(double) * g->members.size(),
                                 hipHostMallocDefault), "hipHostMalloc");
+        // order the group stream after every member's queued work
+        for (jc_ctx* c : g->members) {
+            if (c->stream == g->stream || st != JC_OK)
+                continue;
+            hipEvent_t e = nullptr;
+            st = ghip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+            if (st != JC_OK)
+                break;
+            g->events.push_back(e);
+            st = ghip(hipEventRecord(e, c->stream), "hipEventRecord");
+            if (st == JC_OK)
+                st = ghip(hipStreamWaitEvent(g->stream, e, 0), "hipStreamWaitEvent");
+        }
+    }
     if (st != JC_OK)
         return st;
-    // order the group stream after every member's queued work
-    for (jc_ctx* c : g->members) {
-        if (c->stream == g->stream)
-            continue;
-        hipEvent_t e = nullptr;
-        st = ghip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
-        if (st != JC_OK)
-            return st;
-        g->events.push_back(e);
-        st = ghip(hipEventRecord(e, c->stream), "hipEventRecord");
-        if (st == JC_OK)
-            st = ghip(hipStreamWaitEvent(g->stream, e, 0), "hipStreamWaitEvent");
-        if (st != JC_OK)
-            return st;
-    }
     st = ghip(hipMemcpyAsync(g->d_desc(), g->desc.data(), sizeof(BlockDesc) * g->desc.size(),
                              hipMemcpyHostToDevice, g->stream), "upload blocks");
     if (st == JC_OK)
@@ -387,6 +399,77 @@ int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes)
         return st;
     g->bound = true;
     return JC_OK;
+}
+
+// ---- the library's static group scratch (jc_group_bind_static) ----------
+//
+// One array per device, in this file: in host code its name stands for a
+// host-side symbol, so every use goes through the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept in static_base.  A bound group holds its device's array
+// until jc_group_destroy (static_owner).
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[JC_STATIC_SCRATCH_BYTES];
+std::mutex static_mu;
+char* static_base[kMaxDevices] = {};
+const jc_group* static_owner[kMaxDevices] = {};
+
+}  // namespace
+
+int jc_group_bind(jc_group* g, void* dev_scratch, size_t bytes)
+{
+    if (!g)
+        return fail(JC_ERR_INVALID, "NULL group");
+    if (g->bound)
+        return fail(JC_ERR_STATE, "group is already bound");
+    if (!dev_scratch || reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
+        return fail(JC_ERR_INVALID, "scratch must be a 256-byte aligned device pointer");
+    if (bytes < g->footprint)
+        return fail(JC_ERR_NOMEM, "scratch smaller than jc_group_footprint");
+    return bind_common(g, static_cast<char*>(dev_scratch), false);
+}
+
+int jc_group_bind_static(jc_group* g)
+{
+    if (!g)
+        return fail(JC_ERR_INVALID, "NULL group");
+    if (g->bound)
+        return fail(JC_ERR_STATE, "group is already bound");
+    if (g->footprint > (size_t)JC_STATIC_SCRATCH_BYTES)
+        return fail(JC_ERR_NOMEM, "group needs " + std::to_string(g->footprint) +
+                                      " bytes of scratch, more than the static scratch (" +
+                                      std::to_string((size_t)JC_STATIC_SCRATCH_BYTES) + " bytes)");
+    int dev = -1;
+    int st = ghip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != JC_OK)
+        return st;
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(JC_ERR_DEVICE, "device index out of range for the static scratch");
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(static_mu);
+        if (static_owner[dev])
+            return fail(JC_ERR_STATE, "the static scratch of device " + std::to_string(dev) +
+                                          " is held by another bound group (jc_group_destroy it first)");
+        if (!static_base[dev]) {
+            void* p = nullptr;
+            st = ghip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+            if (st != JC_OK)
+                return st;
+            static_base[dev] = static_cast<char*>(p);
+        }
+        base = static_base[dev];
+        static_owner[dev] = g;
+    }
+    g->static_dev = dev;
+    st = bind_common(g, base, true);
+    if (st != JC_OK) {
+        std::lock_guard<std::mutex> lock(static_mu);
+        static_owner[dev] = nullptr;
+        g->static_dev = -1;
+        g->bound = false;
+    }
+    return st;
 }
 
 int jc_group_iterate(jc_group* g, int64_t n)
@@ -567,14 +650,18 @@ void jc_group_destroy(jc_group* g)
 {
     if (!g)
         return;
-    if (g->bound) {
+    if (g->bound)
         (void)hipStreamSynchronize(g->stream);
-        for (auto& kv : g->graphs)
-            (void)hipGraphExecDestroy(kv.second);
-        for (hipEvent_t e : g->events)
-            (void)hipEventDestroy(e);
-        if (g->h_out)
-            (void)hipHostFree(g->h_out);
+    for (auto& kv : g->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : g->events)
+        (void)hipEventDestroy(e);
+    if (g->h_out && g->h_out != g->h_out_plain.data())
+        (void)hipHostFree(g->h_out);
+    if (g->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(static_mu);
+        if (static_owner[g->static_dev] == g)
+            static_owner[g->static_dev] = nullptr;
     }
     delete g;
 }

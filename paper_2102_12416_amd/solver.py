@@ -288,9 +288,12 @@ class Group:
     """Several bound, loaded Solvers swept by shared launches (libjc group).
 
     The members must not be used on their own streams while the group
-    exists; close() (or leaving a with-block) releases it."""
+    exists; close() (or leaving a with-block) releases it.
+    static_scratch: bind to the library's static device scratch
+    (jc_group_bind_static, no allocation; one such group per device at a
+    time) instead of a torch-allocated buffer."""
 
-    def __init__(self, solvers, use_graphs=True, stream=None, tile=None, temporal=False):
+    def __init__(self, solvers, use_graphs=True, stream=None, tile=None, temporal=False, static_scratch=False):
         self.solvers = list(solvers)
         dev = self.solvers[0].device
         self.device = dev
@@ -303,6 +306,15 @@ class Group:
                                     flags, tl, ctypes.byref(self._g)))
         fp = ctypes.c_size_t()
         check(L.lib.jc_group_footprint(self._g, ctypes.byref(fp)))
+        self.footprint = int(fp.value)
+        if static_scratch:
+            self.scratch = None
+            try:
+                check(L.lib.jc_group_bind_static(self._g))
+            except Exception:
+                self.close()
+                raise
+            return
         self.scratch = torch.empty(int(fp.value) + 256, dtype=torch.uint8, device=dev)
         base = self.scratch.data_ptr()
         off = (-base) % 256
