@@ -103,6 +103,9 @@ def parse():
     ap.add_argument("--tile-x", type=int, default=0, help="cells per tile row, 32 or 64 (0: library default)")
     ap.add_argument("--tile-y", type=int, default=0, help="rows per tile (0: library default)")
     ap.add_argument("--z-chunk", type=int, default=0, help="planes per tile (0: library default)")
+    ap.add_argument("--pace", type=int, default=-1,
+                    help="pace of the one-sweep launch in ticks of the 100 MHz clock (-1: tune it at start-up; "
+                         "0: none)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default tile shape instead of timing the candidates")
     ap.add_argument("--autotune", action="store_true",
@@ -146,10 +149,11 @@ def copy_probe():
                       "copy_gbs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}))
 
 
-def recorded_traffic(workload, mode, tile):
+def recorded_traffic(workload, mode, tile, pace=0):
     """HBM bytes per sweep launch from the committed rocprofv3 counters, if
     they were taken on the current kernel source and the same launch shape
-    (else None)."""
+    and pace (a pace within 5 % of the recorded one: it is tuned on each
+    device) -- else None."""
     path = os.path.join(ROOT, "profiles", "k_sweep_%s_%s_fp64.counters.json" % (workload, mode))
     try:
         rec = json.load(open(path))
@@ -157,6 +161,9 @@ def recorded_traffic(workload, mode, tile):
     except (OSError, ValueError):
         return None
     if rec.get("sweep_source_sha256") != sha or rec.get("mode") != mode or list(rec.get("tile", [])) != list(tile):
+        return None
+    rp = rec.get("pace", 0)
+    if (rp == 0) != (pace == 0) or abs(pace - rp) > 0.05 * max(rp, 1):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -644,17 +651,31 @@ def main():
             tile_source = "jc_autotune at start-up"
             print("[bench] autotuned tile_x=%d tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr,
                   flush=True)
+    pace = None
+    if not temporal:
+        # the pace of the one-sweep launch, for the shape just set: tuned at
+        # start-up (it depends on the device as much as on the shape)
+        if args.pace >= 0:
+            s.set_pace(args.pace)
+            pace = {"ticks": s.pace, "source": "given"}
+        elif tile_source == "jc_autotune at start-up":
+            pace = {"ticks": s.pace, "source": "jc_autotune at start-up"}
+        else:
+            p_ticks, us_paced, us_free = s.autotune_pace(reps=10)
+            pace = {"ticks": p_ticks, "source": "jc_autotune_pace at start-up", "us_per_sweep_paced": us_paced,
+                    "us_per_sweep_unpaced": us_free}
+        print("[bench] pace %s" % pace, file=sys.stderr, flush=True)
     tiles = s.tile_info()
-    s.iterate(args.warmup)
     if graphs:
         # capture the timed window's graph outside the timed region (both
         # start parities when the window is odd)
         s.iterate(args.steps)
         if args.steps % 2:
             s.iterate(args.steps)
+    # the warm-up steps run last, right before the timed window: an idle
+    # device slows the next launches (a 20 ms gap measured 6 % slower)
+    s.iterate(args.warmup)
     s.synchronize()
-    print("[bench] warmup done (%d iterations); timing %d%s" % (args.warmup, args.steps,
-          " as one graph replay" if graphs else ""), file=sys.stderr, flush=True)
 
     if not graphs:
         s.set_timing(True)
@@ -680,7 +701,8 @@ def main():
     else:
         ktime = {k: s.kernel_time(v) for k, v in kinds.items()}
         s.set_timing(False)
-    print("[bench] timed region done: %.3f s wall, %.3f ms on the stream" % (wall, gpu_ms), file=sys.stderr,
+    print("[bench] %d warm-up iterations, then %d timed%s: %.3f s wall, %.3f ms on the stream"
+          % (args.warmup, args.steps, " as one graph replay" if graphs else "", wall, gpu_ms), file=sys.stderr,
           flush=True)
 
     t2_shape = [s.temporal_info()["rows"], s.temporal_info()["z_chunk"]] if temporal else None
@@ -719,6 +741,7 @@ def main():
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
                    "temporal": temporal,
                    "temporal_tile": t2_shape,
+                   "pace": pace,
                    "tile_source": tile_source,
                    "launch": "hipGraph replay of the timed window" if graphs else "eager, HIP events per launch",
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
@@ -729,7 +752,8 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic_temporal(args.workload, t2_shape) if temporal else recorded_traffic(
-                         args.workload, mode, [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]]),
+                         args.workload, mode, [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
+                         pace["ticks"] if pace else 0),
                      "bytes_per_launch": kernel_bytes, "avg_launch_ms": round(avg_ms, 5),
                      "bytes_per_unit": ("16 B per cell per two-sweep launch (8 B per update)" if temporal else
                                         "16 B per update" + (" + 16 B per exchanged face value (%d values)"

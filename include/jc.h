@@ -366,11 +366,36 @@ int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
  * rows {8, 16, 24} x z chunks of 1/1 .. 1/16 of the depth (max(reps, 2)
  * launches each, the three fastest again over three rounds) and the
  * fastest kept (jc_temporal_info); the one shape serves both two-sweep
- * launches of the context.  The trial sweeps write only
+ * launches of the context.  The pace of the one-sweep launch is tuned for
+ * the chosen shape (jc_autotune_pace); out[3] is then the time with it.  The trial sweeps write only
  * the other ping-pong copy and face slot, so the current iterate and
  * iteration count are unchanged.  Waits for the stream.  Needs a loaded
  * context. */
 int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);
+
+/* Pace of the context's one-sweep launches (the sweep its solve loop runs:
+ * the plain sweep, or the inner sweep on a context with refinement
+ * buffers).  The work-groups of a launch advance at different rates and
+ * the launch lasts as long as the slowest, so the compute units of the
+ * fast ones idle at its end.  With a pace of p ticks of the GPU's constant
+ * 100 MHz clock, a work-group that reaches plane step k of its tile before
+ * k * p ticks have passed since it started waits (a bounded sleep) until
+ * then: the fast work-groups are held to a common rate and all finish
+ * together.  Results are bitwise independent of the pace; 0 = none
+ * (default).  0 <= ticks <= 10000, else JC_ERR_INVALID.  jc_set_tiles
+ * resets the pace to 0 (a pace belongs to a tile shape). */
+int jc_set_pace(jc_ctx* ctx, int64_t ticks);
+int64_t jc_get_pace(const jc_ctx* ctx);
+/* Time the context's solve-loop sweep, in its current tile shape, with no
+ * pace and with paces of 90, 91, .. 98 % of its measured time per plane step
+ * (only where the launch runs its work-groups in one or two rounds on the
+ * device's compute units; otherwise the pace stays 0), `reps` sweeps each
+ * in three interleaved rounds after 150 ms of warm-up, and keep the
+ * fastest.  out = {pace, microseconds per sweep with it, microseconds per
+ * sweep without a pace}.  Trial sweeps leave the iterate as it is.  Waits
+ * for the stream.  jc_autotune runs the same tuning after it has picked
+ * the tile shape. */
+int jc_autotune_pace(jc_ctx* ctx, int reps, int64_t out[3]);
 
 /* ---- measurement ----------------------------------------------------- */
 

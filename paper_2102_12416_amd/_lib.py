@@ -86,6 +86,9 @@ SIGNATURES = {
     "jc_group_footprint": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_size_t)]),
     "jc_group_bind": (ctypes.c_int, [VP, VP, ctypes.c_size_t]),
     "jc_group_bind_static": (ctypes.c_int, [VP]),
+    "jc_set_pace": (ctypes.c_int, [CTX, I64]),
+    "jc_get_pace": (I64, [CTX]),
+    "jc_autotune_pace": (ctypes.c_int, [CTX, ctypes.c_int, I64P]),
     "jc_group_iterate": (ctypes.c_int, [VP, I64]),
     "jc_group_residuals": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
     "jc_group_destroy": (None, [VP]),

@@ -85,6 +85,9 @@ inline bool tile_shape_ok(int tile_x, int tile_y)
     return ok_x && ok_y && (tile_x / 2) * tile_y >= 64;
 }
 constexpr int kMinZChunk = 16;
+// largest pace (ticks of the 100 MHz clock per plane step): each wait of a
+// work-group is bounded by 4096 sleeps of 64 cycles, about 100 us
+constexpr int64_t kMaxPace = 10000;
 // Temporal blocking: default rows of the two-sweep tile (64 cells wide;
 // 8, 16 or 24) and the fewest planes per work-group when the chunk follows
 // the one-sweep z_chunk (each work-group reads two planes beyond each end).
@@ -124,6 +127,9 @@ struct jc_ctx {
     // (t2_zc 0: the one-sweep z_chunk, at least kTwoStepMinZ)
     int t2_rows = jc_rt::kTwoStepRows;
     int t2_zc = 0;
+    // pace of the one-sweep launches of the solve loop (jc_set_pace): ticks
+    // of the 100 MHz constant clock per plane step; 0 = none
+    uint32_t pace = 0;
     std::vector<Item> items;
     int64_t max_items = 0;
     // arena layout

@@ -483,7 +483,8 @@ int do_sweep(jc_ctx* c, bool fused, bool resid)
 {
     int st = timed(c, fused ? JC_K_FUSED : JC_K_SWEEP, [&] {
         return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_x, c->tile_y,
-                                fused, resid, true, c->opt.with_source != 0, c->d_partials(), c->stream);
+                                fused, resid, true, c->opt.with_source != 0, c->d_partials(), c->stream,
+                                c->opt.ir_enable ? 0u : c->pace);
     });
     if (st != JC_OK)
         return st;
@@ -1308,7 +1309,7 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
             for (; j < m && s2 == JC_OK; ++j) {
                 s2 = timed(c, JC_K_IR_INNER, [&] {
                     return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), qq, c->tile_x,
-                                               c->tile_y, lo, c->stream);
+                                               c->tile_y, lo, c->stream, c->pace);
                 });
                 qq ^= 1;
             }
@@ -1373,6 +1374,7 @@ int jc_set_tiles(jc_ctx* c, int tile_x, int tile_y, int z_chunk)
     c->tile_x = tile_x;
     c->tile_y = tile_y;
     c->z_chunk = z_chunk;
+    c->pace = 0;                           // a pace belongs to a shape
     build_items(c);
     c->hranges[1] = (int32_t)c->items.size();
     free_graphs(c);                        // graphs hold the old launch shapes
@@ -1407,6 +1409,160 @@ int jc_temporal_info(const jc_ctx* c, int64_t out[3])
     out[1] = c->t2_rows;
     out[2] = two_step_chunk(c);
     return JC_OK;
+}
+
+int jc_set_pace(jc_ctx* c, int64_t ticks)
+{
+    if (!c)
+        return fail(JC_ERR_INVALID, "NULL context");
+    if (ticks < 0 || ticks > kMaxPace)
+        return fail(JC_ERR_INVALID, "pace must be in 0 .. " + std::to_string(kMaxPace) + " ticks");
+    if ((uint32_t)ticks != c->pace) {
+        c->pace = (uint32_t)ticks;
+        free_graphs(c);                    // graphs hold the launch arguments
+    }
+    return JC_OK;
+}
+
+int64_t jc_get_pace(const jc_ctx* c) { return c ? (int64_t)c->pace : 0; }
+
+namespace {
+
+// Tune the pace of the context's solve-loop sweep for its current tile
+// shape (see pace_wait in jc_kernels.hip).  A pace only helps a launch
+// whose work-groups all run at once, or in two rounds: it holds the fast
+// ones to a common rate so that none is left running alone at the end.
+// The candidates are fractions of the plane-step time of the unpaced
+// launch (its time over the planes one work-group marches); each is timed
+// over `reps` sweeps in three interleaved rounds after `warm_ms` of
+// warm-up, and the fastest is kept, pace 0 included.
+// out = {pace, microseconds per sweep with it, without it}.
+int tune_pace(jc_ctx* c, int reps, double warm_ms, int64_t out[3])
+{
+    const bool fused = c->opt.mode == JC_MODE_FUSED && c->np() > 0;
+    const bool ir = c->opt.ir_enable != 0;
+    int dev = 0, ncu = 0;
+    JC_HIP(hipGetDevice(&dev));
+    JC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t zmax = 0;
+    for (const Item& it : c->items)
+        zmax = std::max<int64_t>(zmax, it.zlen);
+    const int64_t nit = (int64_t)c->items.size();
+    const int64_t rounds = ncu > 0 ? (nit + ncu - 1) / ncu : 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    JC_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(JC_ERR_DEVICE, "pace tuning: hipEventCreate failed");
+    }
+    const bool was_timing = c->timing;
+    c->timing = false;
+    // trial sweeps read copy `parity` (copy 1 of the zeroed correction)
+    // and write the other copy and face slot: the iterate is unchanged
+    auto time_at = [&](uint32_t pace, int n, double& ms) -> int {
+        auto one = [&]() -> hipError_t {
+            return ir ? jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)nit, 1, c->tile_x, c->tile_y,
+                                            c->opt.ir_dtype, c->stream, pace)
+                      : jc::launch_sweep(c->d_blocks(), c->d_items(), (int)nit, c->parity, c->tile_x, c->tile_y,
+                                         fused, false, true, c->opt.with_source != 0, nullptr, c->stream, pace);
+        };
+        if (one() != hipSuccess || hipEventRecord(e0, c->stream) != hipSuccess)
+            return fail(JC_ERR_DEVICE, "pace tuning launch failed");
+        for (int i = 0; i < n; ++i)
+            if (one() != hipSuccess)
+                return fail(JC_ERR_DEVICE, "pace tuning launch failed");
+        float tm = 0;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&tm, e0, e1) != hipSuccess)
+            return fail(JC_ERR_DEVICE, "pace tuning: timing failed");
+        ms = tm;
+        return JC_OK;
+    };
+    int st = JC_OK;
+    double warm = 0;
+    for (int b = 0; b < 1000 && warm < warm_ms && st == JC_OK; ++b) {
+        double ms = 0;
+        st = time_at(0, 8, ms);
+        warm += ms;
+    }
+    double base = 0;
+    if (st == JC_OK)
+        st = time_at(0, reps, base);
+    std::vector<uint32_t> cand{0};
+    if (st == JC_OK && rounds <= 2 && zmax >= 16) {
+        const double step_ticks = base / reps * 1e5 / (double)(rounds * zmax);   // 100 ticks per microsecond
+        for (double f : {0.90, 0.91, 0.92, 0.93, 0.94, 0.95, 0.96, 0.97, 0.98}) {
+            const double p = step_ticks * f;
+            if (p >= 1.0 && p <= (double)kMaxPace && (uint32_t)p != cand.back())
+                cand.push_back((uint32_t)p);
+        }
+    }
+    std::vector<double> tot(cand.size(), 0.0);
+    for (int r = 0; r < 3 && st == JC_OK && cand.size() > 1; ++r)
+        for (size_t i = 0; i < cand.size() && st == JC_OK; ++i) {
+            double ms = 0;
+            st = time_at(cand[i], reps, ms);
+            tot[i] += ms;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = was_timing;
+    if (st != JC_OK)
+        return st;
+    size_t best = 0;
+    if (cand.size() > 1) {
+        for (size_t i = 1; i < cand.size(); ++i)
+            if (tot[i] < tot[best])
+                best = i;
+        base = tot[0] / 3.0;
+    }
+    st = jc_set_pace(c, cand[best]);
+    if (st != JC_OK)
+        return st;
+    out[0] = cand[best];
+    out[1] = (int64_t)((cand.size() > 1 ? tot[best] / 3.0 : base) * 1000.0 / reps);
+    out[2] = (int64_t)(base * 1000.0 / reps);
+    return JC_OK;
+}
+
+// Common preconditions of the tuners: a loaded context whose trial sweeps
+// leave the iterate as it is.
+int prepare_tuning(jc_ctx* c)
+{
+    const bool fused = c->opt.mode == JC_MODE_FUSED && c->np() > 0;
+    const bool ir = c->opt.ir_enable != 0;
+    if (ir && c->ir_phase != 0)
+        return fail(JC_ERR_STATE, "autotune: a group's refinement step is in progress on this context "
+                                  "(its r_lo or correction is still to be used)");
+    if (ir) {
+        // every refinement step rebuilds d from r_lo and no sweep writes a
+        // ghost, so trial sweeps on zeroed arrays leave no trace in a solve
+        return jc::launch_zero(c->arena + c->lo_begin, c->lo_end - c->lo_begin, c->stream) == hipSuccess
+                   ? JC_OK
+                   : fail(JC_ERR_DEVICE, "autotune: zeroing the refinement arrays failed");
+    }
+    if (fused && !c->fused_primed) {
+        const int st = do_pack(c, c->parity);
+        if (st != JC_OK)
+            return st;
+        c->fused_primed = true;
+    }
+    return JC_OK;
+}
+
+}  // namespace
+
+int jc_autotune_pace(jc_ctx* c, int reps, int64_t out[3])
+{
+    int st = check_ready(c);
+    if (st != JC_OK)
+        return st;
+    if (reps < 1 || !out)
+        return fail(JC_ERR_INVALID, "reps must be >= 1 and out not NULL");
+    st = prepare_tuning(c);
+    if (st != JC_OK)
+        return st;
+    return tune_pace(c, reps, 150.0, out);
 }
 
 int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
@@ -1528,6 +1684,9 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
     const Shape best = *std::min_element(cand.begin(), cand.end(),
                                          [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
     st = jc_set_tiles(c, best.x, best.y, best.z);
+    int64_t pace_out[3] = {0, 0, 0};
+    if (st == JC_OK)
+        st = tune_pace(c, reps, 0.0, pace_out);
     if (st == JC_OK && c->opt.temporal) {
         c->timing = false;
         st = tune_two_step(c, std::max(reps, 2));
@@ -1538,7 +1697,7 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
     out[0] = best.x;
     out[1] = best.y;
     out[2] = best.z;
-    out[3] = (int64_t)(best.ms * 1000.0 / (3.0 * reps));     // microseconds per sweep
+    out[3] = pace_out[0] ? pace_out[1] : (int64_t)(best.ms * 1000.0 / (3.0 * reps));   // microseconds per sweep
     return JC_OK;
 }
 

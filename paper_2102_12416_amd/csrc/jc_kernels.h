@@ -15,9 +15,11 @@ constexpr int kTileX = 64;
 // the face buffers of the input slot and write face values to the output
 // slot.  resid: write one partial sum of r^2 per item into partials.
 // store: write the new iterate (false = residual only).
+// pace: ticks of the constant 100 MHz clock per plane step below which a
+// work-group waits (0 = none; see pace_wait in jc_kernels.hip).
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
                         int tile_x, int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t pace = 0);
 
 // Two sweeps of the single block of a context without face pairs in one
 // launch (binary64): iterate k from copy parity, iterate k + 2 into copy
@@ -47,7 +49,7 @@ hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, in
 hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_x,
                               int tile_y, bool src, int lo_dtype, double* partials, hipStream_t s);
 hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_x,
-                           int tile_y, int lo_dtype, hipStream_t s);
+                           int tile_y, int lo_dtype, hipStream_t s, uint32_t pace = 0);
 // max_rows: the largest ny * nz over the blocks (sizes the grid).
 hipError_t launch_ir_first(const BlockDesc* blocks, int nblocks, int64_t max_rows, int lo_dtype, hipStream_t s);
 hipError_t launch_ir_update(const BlockDesc* blocks, int nblocks, int64_t max_rows, int p, int q, int lo_dtype,

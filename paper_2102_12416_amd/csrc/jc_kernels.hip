@@ -209,6 +209,24 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Pacing.  The work-groups of a launch advance at different rates (a tile
+// on a Dirichlet face reads its ghosts from a compact column, other tiles
+// read their x halo from the neighbour tile's lines, work-groups sit at
+// different distances from the memory they stream), and the launch ends
+// with the slowest: measured on the 512^3 launch of 256 tiles, they took
+// 359-396 us, so the compute units of the fast ones idled through the
+// tail.  With a pace, a work-group waits before plane step k until k *
+// pace ticks of the chip's constant 100 MHz clock have passed since it
+// started: the fast ones are held to the pace and the memory traffic of
+// the slow ones runs without their competition, so all finish together.
+// The pace is tuned by timing (jc_autotune); 0 = none.  Each wait is
+// bounded (4096 short sleeps), and results do not depend on it.
+__device__ __forceinline__ void pace_wait(uint64_t due)
+{
+    for (int i = 0; i < 4096 && __builtin_amdgcn_s_memrealtime() < due; ++i)
+        __builtin_amdgcn_s_sleep(1);
+}
+
 // Planes of loads a sweep keeps in flight ahead of the plane it computes.
 // Three for binary64 fields: at one 16-wave work-group per CU (the 64 x 32
 // tile) two planes of 16-byte loads are too few bytes in flight to cover
@@ -248,7 +266,7 @@ template <typename T> constexpr int prefetch_planes() { return sizeof(T) == 8 ? 
 template <typename T, int FIELD, int TXP, int TY, bool FUSED, bool RES, bool STORE, bool SRC, typename R>
 __global__ void __launch_bounds__(TXP * TY)
 k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int nitems,
-        int parity, double* __restrict__ partials)
+        int parity, double* __restrict__ partials, uint32_t pace)
 {
     static_assert(TY >= 4 && TXP * TY >= 2 * TXP + 2 * TY && (TXP * TY) % 64 == 0,
                   "halo roles need 2 TXP + 2 TY threads; whole waves");
@@ -264,6 +282,7 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= nitems)
         return;                                   // uniform over the work-group
+    const uint64_t pace_t0 = pace ? __builtin_amdgcn_s_memrealtime() : 0;
     const Item it = items[id];
     const BlockDesc* B = blocks + it.block;
     const int p = parity ^ it.flip;
@@ -424,6 +443,8 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
         constexpr int SM = (K + RS - 1) % RS, SC = K, SP = (K + 1) % RS, SQ = (K + PD) % RS;
         static_assert(K >= 0 && K < RS, "ring slot");
         constexpr int HC = K & 1;                 // LDS buffer of this plane
+        if (pace)
+            pace_wait(pace_t0 + (uint64_t)(z - zf) * pace);
         // plane z + PD goes in flight first; the last steps re-read planes
         // they already hold (cache hits) instead of branching
         const int zh = min(z + PD, zl);
@@ -542,14 +563,14 @@ k_sweep(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, in
 
 template <typename T, int FIELD, int TXP, int TY, bool SRC, typename R>
 hipError_t sweep_flags(const BlockDesc* blocks, const Item* items, int nitems, int parity, bool fused,
-                       bool resid, bool store, double* partials, hipStream_t s)
+                       bool resid, bool store, double* partials, hipStream_t s, uint32_t pace)
 {
     const int grid = ((nitems + 7) / 8) * 8;
     const dim3 bs(TXP * TY);
 #define JC_SWEEP_CASE(FU, RE, ST)                                                                         \
     if (fused == FU && resid == RE && store == ST) {                                                     \
         hipLaunchKernelGGL((k_sweep<T, FIELD, TXP, TY, FU, RE, ST, SRC, R>), dim3(grid), bs, 0, s, blocks, \
-                           items, nitems, parity, partials);                                             \
+                           items, nitems, parity, partials, pace);                                       \
         return hipGetLastError();                                                                        \
     }
     if constexpr (std::is_same<R, NoRlo>::value) {
@@ -570,30 +591,30 @@ hipError_t sweep_flags(const BlockDesc* blocks, const Item* items, int nitems, i
 
 template <typename T, int FIELD, int TXP, bool SRC, typename R>
 hipError_t sweep_rows(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
-                      bool fused, bool resid, bool store, double* partials, hipStream_t s)
+                      bool fused, bool resid, bool store, double* partials, hipStream_t s, uint32_t pace)
 {
     switch (tile_y) {
     case 4:
         // a 16-cell tile needs 8 rows for whole waves
         if constexpr (TXP * 4 >= 64)
-            return sweep_flags<T, FIELD, TXP, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+            return sweep_flags<T, FIELD, TXP, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
         else
             return hipErrorInvalidValue;
-    case 8: return sweep_flags<T, FIELD, TXP, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 16: return sweep_flags<T, FIELD, TXP, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
-    case 32: return sweep_flags<T, FIELD, TXP, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s);
+    case 8: return sweep_flags<T, FIELD, TXP, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
+    case 16: return sweep_flags<T, FIELD, TXP, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
+    case 32: return sweep_flags<T, FIELD, TXP, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T, int FIELD, bool SRC, typename R>
 hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_x, int tile_y,
-                       bool fused, bool resid, bool store, double* partials, hipStream_t s)
+                       bool fused, bool resid, bool store, double* partials, hipStream_t s, uint32_t pace)
 {
     switch (tile_x) {
-    case 16: return sweep_rows<T, FIELD, 8, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
-    case 32: return sweep_rows<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
-    case 64: return sweep_rows<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s);
+    case 16: return sweep_rows<T, FIELD, 8, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
+    case 32: return sweep_rows<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
+    case 64: return sweep_rows<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1083,14 +1104,14 @@ dim3 row_grid(int nblocks, int64_t max_rows)
 
 hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, int parity,
                         int tile_x, int tile_y, bool fused, bool resid, bool store, bool src, double* partials,
-                        hipStream_t s)
+                        hipStream_t s, uint32_t pace)
 {
     if (nitems <= 0)
         return hipSuccess;
     return src ? sweep_tiles<double, FIELD_U, true, NoRlo>(blocks, items, nitems, parity, tile_x, tile_y, fused,
-                                                             resid, store, partials, s)
+                                                             resid, store, partials, s, pace)
                : sweep_tiles<double, FIELD_U, false, NoRlo>(blocks, items, nitems, parity, tile_x, tile_y, fused,
-                                                              resid, store, partials, s);
+                                                              resid, store, partials, s, pace);
 }
 
 hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
@@ -1196,9 +1217,9 @@ hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int ni
         return hipSuccess;
 #define JC_IR_RES(RT)                                                                                  \
     return src ? sweep_tiles<double, FIELD_U, true, RT>(blocks, items, nitems, parity, tile_x, tile_y, true,   \
-                                                        true, false, partials, s)                           \
+                                                        true, false, partials, s, 0)                        \
                : sweep_tiles<double, FIELD_U, false, RT>(blocks, items, nitems, parity, tile_x, tile_y, true,  \
-                                                         true, false, partials, s);
+                                                         true, false, partials, s, 0);
     switch (lo_dtype) {
     case 0: JC_IR_RES(double)
     case 1: JC_IR_RES(float)
@@ -1209,17 +1230,17 @@ hipError_t launch_ir_residual(const BlockDesc* blocks, const Item* items, int ni
 }
 
 hipError_t launch_ir_inner(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_x,
-                           int tile_y, int lo_dtype, hipStream_t s)
+                           int tile_y, int lo_dtype, hipStream_t s, uint32_t pace)
 {
     if (nitems <= 0)
         return hipSuccess;
     switch (lo_dtype) {
     case 0: return sweep_tiles<double, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_x, tile_y, true,
-                                                             false, true, nullptr, s);
+                                                             false, true, nullptr, s, pace);
     case 1: return sweep_tiles<float, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_x, tile_y, true,
-                                                            false, true, nullptr, s);
+                                                            false, true, nullptr, s, pace);
     case 2: return sweep_tiles<bf16, FIELD_D, true, NoRlo>(blocks, items, nitems, qparity, tile_x, tile_y, true,
-                                                           false, true, nullptr, s);
+                                                           false, true, nullptr, s, pace);
     default: return hipErrorInvalidValue;
     }
 }

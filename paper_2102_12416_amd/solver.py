@@ -257,6 +257,22 @@ class Solver:
         return tuple(out)
 
     # -------------------------------------------------------------- timing
+    def set_pace(self, ticks):
+        """Pace of the solve-loop sweep (jc_set_pace): ticks of the GPU's
+        100 MHz clock per plane step; 0 = none."""
+        check(L.lib.jc_set_pace(self._ctx, int(ticks)))
+
+    @property
+    def pace(self):
+        return int(L.lib.jc_get_pace(self._ctx))
+
+    def autotune_pace(self, reps=10):
+        """Tune the pace for the current tile shape (jc_autotune_pace);
+        returns (pace, us per sweep with it, us per sweep without)."""
+        out = (ctypes.c_int64 * 3)()
+        check(L.lib.jc_autotune_pace(self._ctx, int(reps), out))
+        return tuple(int(v) for v in out)
+
     def set_timing(self, enable=True):
         check(L.lib.jc_set_timing(self._ctx, int(bool(enable))))
 

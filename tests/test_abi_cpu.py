@@ -286,6 +286,24 @@ def test_set_tiles_validation_and_items():
     L.lib.jc_destroy(ctx)
 
 
+def test_pace_validation_and_reset_by_tiles():
+    st, ctx = create((64, 64, 64), (32, 64, 64))
+    assert st == 0
+    assert L.lib.jc_get_pace(ctx) == 0
+    assert L.lib.jc_set_pace(ctx, -1) == L.JC_ERR_INVALID
+    assert L.lib.jc_set_pace(ctx, 10001) == L.JC_ERR_INVALID
+    check(L.lib.jc_set_pace(ctx, 10000))
+    check(L.lib.jc_set_pace(ctx, 148))
+    assert L.lib.jc_get_pace(ctx) == 148
+    # a pace belongs to a tile shape
+    check(L.lib.jc_set_tiles(ctx, 64, 16, 32))
+    assert L.lib.jc_get_pace(ctx) == 0
+    out = (ctypes.c_int64 * 3)()
+    assert L.lib.jc_autotune_pace(ctx, 3, out) == L.JC_ERR_STATE      # not bound
+    assert L.lib.jc_autotune_pace(ctx, 0, out) < 0
+    L.lib.jc_destroy(ctx)
+
+
 def test_sixteen_cell_tile_options():
     st, ctx = create((40, 24, 24), (40, 24, 24), tile_x=16, tile_y=4)
     assert st == L.JC_ERR_INVALID

@@ -175,6 +175,46 @@ def test_tile_shapes_bitwise(tile_x, tile_y, z_chunk, mode):
 
 
 @pytest.mark.parametrize("mode", ["staged", "fused"])
+def test_pace_keeps_results_bitwise(mode):
+    """A pace only delays work-groups: iterates are bitwise those of the
+    oracle with a pace that binds (0.4 us per plane step on a small grid),
+    with the tuned pace, and in graph replays captured with either."""
+    n = (100, 70, 66)
+    say("pace", mode)
+    u0 = synth.boundary_field(n, seed=8)
+    b = synth.source_field(n, seed=8)
+    ref9, _ = oracle.c_jacobi(u0, 9, b)
+    ref18, _ = oracle.c_jacobi(u0, 18, b)
+    with Solver(n, block_dims=(50, 35, 66), mode=mode, with_source=True, tile_x=64, tile_y=8, z_chunk=66) as s:
+        s.load(u0, b)
+        s.set_pace(40)
+        assert s.pace == 40
+        s.iterate(9)
+        assert np.array_equal(s.store().cpu().numpy(), ref9)
+        p, us_paced, us_free = s.autotune_pace(reps=3)
+        assert s.pace == p and 0 <= p <= 10000 and us_paced > 0 and us_free > 0
+        assert np.array_equal(s.store().cpu().numpy(), ref9)      # trial sweeps leave the iterate
+        s.iterate(9)
+        assert np.array_equal(s.store().cpu().numpy(), ref18)
+
+
+def test_pace_on_refinement_inner_sweep_bitwise():
+    """The pace of a refinement context applies to its inner sweeps: the
+    solve is still the oracle's refinement, bit for bit."""
+    n = (40, 36, 64)
+    say("pace refinement")
+    u0 = synth.boundary_field(n, seed=9)
+    b = synth.source_field(n, seed=9)
+    ref, _, done, _ = oracle.c_ir_solve(u0, b, storage="f32", inner=20, rtol=0.0, max_inner=60)
+    with Solver(n, with_source=True, ir_dtype="f32", tile_x=64, tile_y=8, z_chunk=64) as s:
+        s.load(u0, b)
+        s.set_pace(60)
+        info = s.solve_ir(inner=20, rtol=0.0, max_inner=60)
+        assert info["iters"] == done
+        assert np.array_equal(s.store().cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("mode", ["staged", "fused"])
 def test_graph_replays_match_eager(mode):
     """Each window replay, interleaved with eager work and synchronisation,
     matches the eager run."""
