@@ -112,6 +112,10 @@ def parse():
                     help="re-tune even where a tuned shape is recorded for the workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ab", action="store_true", help="skip the device / host-staged exchange comparison")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="512_2x2x2: skip the reduced runs of the added forms (refinement, serving)")
+    ap.add_argument("--forms-serve-requests", type=int, default=32)
+    ap.add_argument("--forms-serve-max-edge", type=int, default=128)
     ap.add_argument("--no-temporal-context", action="store_true",
                     help="512_2x2x2: skip the one-block, two-sweeps-per-launch context figure")
     ap.add_argument("--ab-iters", type=int, default=100)
@@ -292,11 +296,168 @@ def cpu_baseline(grid, seed, seconds):
     dt = time.perf_counter() - t0
     lups = float(nx) * ny * nz * sweeps
     del u, v
-    return dict(value=lups / dt / 1e9, unit="GLUP/s", cores=oracle.num_threads(),
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=lups / dt / 1e9, unit="GLUP/s", cores=oracle.num_threads(), cpu_model=model,
                 kind="oracle",
                 sample="%d sweeps of the undecomposed %dx%dx%d grid (C oracle, OpenMP) in %.1f s"
                        % (sweeps, nx, ny, nz, dt),
                 host_cpus=len(os.sched_getaffinity(0)))
+
+
+# tile shapes of the per-sweep refinement rates at 1024^3 in the default run
+# (the inner sweep of the correction for the refined forms), from jc_autotune
+# on MI355X; the pace is tuned at start-up
+FORM_TILES = {"f64": (64, 32, 1024), "f32": (64, 32, 1024), "bf16": (64, 8, 128)}
+
+
+def host_residual_norm(u, b):
+    """|b + s(u) - 6u|_2 over the interior in binary64 on the host (numpy):
+    the certificate of a served result, computed apart from the GPU path."""
+    import numpy as np
+    c = u[1:-1, 1:-1, 1:-1]
+    s = u[1:-1, 1:-1, :-2] + u[1:-1, 1:-1, 2:]
+    s = s + u[1:-1, :-2, 1:-1]
+    s = s + u[1:-1, 2:, 1:-1]
+    s = s + u[:-2, 1:-1, 1:-1]
+    s = s + u[2:, 1:-1, 1:-1]
+    r = (b[1:-1, 1:-1, 1:-1] + s) - 6.0 * c
+    return float(np.sqrt(np.sum(r * r)))
+
+
+def forms(args):
+    """The added forms in reduced configurations, for the default run (each
+    named in its own config): mixed precision at 1024^3 (per-sweep rates of
+    the binary64 sweep with a source and of the binary32- and
+    bfloat16-stored refinement, one outer step of 50 inner sweeps), time to
+    a 1e-10 relative residual at 128^3 for binary64 and the refined forms
+    (error against binary64 per result), and a served Poisson run with a
+    host certificate of every result."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2102_12416_amd import Solver, _lib as L, synth_field
+    from paper_2102_12416_amd.server import Request, Server, summarize
+    res = {}
+    # ---- mixed precision, per sweep, 1024^3 with a source
+    n = 1024
+    grid = (n, n, n)
+    lups = float(n) ** 3
+    g = synth_field(grid, args.seed, 0)
+    b = synth_field(grid, args.seed, 1)
+    rates = {}
+    for dt in ("f64", "f32", "bf16"):
+        ir = None if dt == "f64" else dt
+        with Solver(grid, with_source=True, ir_dtype=ir, use_graphs=False) as s:
+            s.load(g, b)
+            s.set_tiles(*FORM_TILES[dt])
+            pace = s.autotune_pace(reps=4)[0]
+            s.set_timing(True)
+            if ir is None:
+                s.iterate(50)
+                ms, k = s.kernel_time(L.JC_K_SWEEP)
+                rates["f64_plain"] = dict(glups=round(lups * k / (ms * 1e-3) / 1e9, 1),
+                                          gbs=round(24 * lups * k / (ms * 1e-3) / 1e9, 1),
+                                          ms_per_sweep=round(ms / k, 4), tile=list(FORM_TILES[dt]), pace=pace,
+                                          bytes_per_update=24)
+            else:
+                info = s.solve_ir(inner=50, rtol=0.0, max_inner=50)
+                ms_in, k_in = s.kernel_time(L.JC_K_IR_INNER)
+                ms_out, _ = s.kernel_time(L.JC_K_IR_OUTER)
+                rates["%s_refined" % dt] = dict(
+                    glups=round(lups * info["iters"] / ((ms_in + ms_out) * 1e-3) / 1e9, 1),
+                    inner_gbs=round((12 if dt == "f32" else 6) * lups * k_in / (ms_in * 1e-3) / 1e9, 1),
+                    ms_per_sweep_with_outer=round((ms_in + ms_out) / info["iters"], 4), tile=list(FORM_TILES[dt]),
+                    pace=pace, bytes_per_update=12 if dt == "f32" else 6)
+            s.set_timing(False)
+    del g, b
+    torch.cuda.empty_cache()
+    for k in ("f32_refined", "bf16_refined"):
+        rates[k]["speedup_vs_f64"] = round(rates[k]["glups"] / rates["f64_plain"]["glups"], 2)
+    res["refinement_1024"] = dict(config="1024^3 interior, source U[-1,1), boundary U[0,1); refinement: one outer "
+                                         "step of 50 inner sweeps (binary64 residual, update and norm included)",
+                                  per_sweep=rates)
+    print("[bench] forms: refinement per sweep %s" % json.dumps(rates), file=sys.stderr, flush=True)
+    # ---- time to 1e-10 at 128^3: binary64 vs the refined forms (two sweeps per launch)
+    m = 128
+    gm = (m, m, m)
+    gg = synth_field(gm, args.seed, 0)
+    bb = synth_field(gm, args.seed, 1)
+    row = {}
+    for tag, ir, temporal in (("f64", None, False), ("f64_temporal", None, True), ("f32_refined_temporal", "f32", True),
+                              ("bf16_refined_temporal", "bf16", True)):
+        with Solver(gm, with_source=True, ir_dtype=ir, temporal=temporal) as s:
+            s.load(gg, bb)
+            s.autotune(reps=2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.solve(rtol=1e-10, max_iter=2000000, check_every=50) if ir is None else \
+                s.solve_ir(inner=50, rtol=1e-10, max_inner=2000000)
+            sec = time.perf_counter() - t0
+            u = s.store()
+            if tag == "f64":
+                u64, scale = u, float(u.abs().max())
+            row[tag] = dict(seconds=round(sec, 3), sweeps=info["iters"], rel_resid=info["rel_resid"],
+                            converged=info["converged"],
+                            max_rel_err_vs_f64=float((u - u64).abs().max()) / scale)
+    for tag in row:
+        row[tag]["speedup_vs_f64"] = round(row["f64"]["seconds"] / row[tag]["seconds"], 2)
+    res["time_to_1e-10_128"] = row
+    del gg, bb, u, u64
+    print("[bench] forms: time to 1e-10 at 128^3 %s" % json.dumps(row), file=sys.stderr, flush=True)
+    # ---- serving: Poisson arrivals, continuous batching, certificates
+    nreq, hi = args.forms_serve_requests, args.forms_serve_max_edge
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def reqs(rate):
+        return [Request(id=r["id"], arrival=r["arrival"], n=r["n"], precision=r["precision"], seed=r["seed"])
+                for r in synth.serving_requests(nreq, rate, seed=args.seed, lo=32, hi=hi)]
+
+    def server(keep):
+        return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter, lanes=(64, 160),
+                      temporal=True, keep_fields=keep)
+    t0 = time.perf_counter()
+    cap = summarize(server(False).run(reqs(0.0), realtime=False), 1.0)
+    cap_s = time.perf_counter() - t0
+    capacity = cap["served"] / cap_s
+    rate = 0.7 * capacity
+    run = reqs(rate)
+    srv = server(True)
+    t0 = time.perf_counter()
+    out = srv.run(run, realtime=True)
+    span = time.perf_counter() - t0
+    summ = summarize(out, span)
+    worst, certified = 0.0, 0
+    for rq, r in zip(run, out):
+        if r.rejected:
+            continue
+        nn = (rq.n, rq.n, rq.n)
+        u0 = synth.boundary_field(nn, seed=rq.seed)
+        bs = synth.source_field(nn, seed=rq.seed)
+        rel = host_residual_norm(r.field, bs) / host_residual_norm(u0, bs)
+        worst = max(worst, abs(rel - r.rel_resid) / max(rel, 1e-300))
+        certified += int((rel <= 1e-10 * (1 + 1e-9)) == r.converged)
+        r.field = None
+    res["serving"] = dict(
+        config=dict(requests=nreq, edges="log-uniform [32, %d]" % hi, precision="Bernoulli(0.5) f64 / f32-refined",
+                    rtol=1e-10, max_iter=args.serve_max_iter, window=50, lanes=[64, 160],
+                    two_sweeps_per_launch=True, budget_gb=args.serve_budget_gb,
+                    rate_per_s=round(rate, 3), rate_source="0.7 x closed-loop capacity of the same requests"),
+        solves_per_s=round(summ["solves_per_s"], 3), p50_s=round(summ["p50_s"], 4), p99_s=round(summ["p99_s"], 4),
+        mean_s=round(summ["mean_s"], 4), converged=summ["converged"], capped=summ["capped"],
+        rejected=summ["rejected"], closed_loop_capacity_per_s=round(capacity, 3),
+        certificate=dict(checked=summ["served"], stop_confirmed=certified,
+                         max_rel_diff_host_vs_gpu_residual=worst,
+                         how="numpy binary64 residual of every returned iterate over that of the initial one"))
+    print("[bench] forms: serving %s" % json.dumps(res["serving"]), file=sys.stderr, flush=True)
+    return res
 
 
 def bench_refinement(args):
@@ -774,6 +935,9 @@ def main():
         st_tiles = TUNED_TILES.get((args.workload, "staged"), (tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]))
         out["exchange_ab"] = exchange_ab(grid, bd, args.seed, args.ab_iters, st_tiles)
         out["exchange_ab"]["paper_context"] = PAPER_COMM_SPEEDUPS
+    if args.workload == "512_2x2x2" and not args.no_forms:
+        print("[bench] forms: refinement at 1024^3, time to 1e-10 at 128^3, serving", file=sys.stderr, flush=True)
+        out["forms"] = forms(args)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline (%.0f s budget)" % args.cpu_seconds, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(grid, args.seed, args.cpu_seconds)
