@@ -217,18 +217,23 @@ def exchange_ab(grid, bd, seed, iters, tiles):
     from paper_2102_12416_amd import Solver, _lib as L
     u0 = synth.boundary_field(grid, seed=seed)
     out = {}
-    for mode in ("device", "host", "metadata"):
-        with Solver(grid, block_dims=bd, mode="staged", use_graphs=False, exchange=mode) as s:
+    for mode in ("device", "host", "metadata", "device_overlap"):
+        overlap = mode == "device_overlap"
+        with Solver(grid, block_dims=bd, mode="staged", use_graphs=False, exchange=mode.split("_")[0],
+                    overlap=overlap) as s:
             s.set_tiles(*tiles)
             s.load(u0)
-            s.iterate(5)
+            s.iterate(20)
+            # the iteration time with no per-kernel events, eager launches
             s.synchronize()
-            s.set_timing(True)
-            torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.iterate(iters)
             s.synchronize()
             wall = time.perf_counter() - t0
+            # then the kernels, each bracketed by events
+            s.set_timing(True)
+            s.iterate(iters)
+            s.synchronize()
             comm = sum(s.kernel_time(k)[0] for k in (L.JC_K_PACK, L.JC_K_EXCHANGE, L.JC_K_UNPACK))
             sweep = s.kernel_time(L.JC_K_SWEEP)[0]
             s.set_timing(False)
@@ -238,6 +243,10 @@ def exchange_ab(grid, bd, seed, iters, tiles):
     for mode in ("host", "metadata"):
         out[mode]["comm_speedup_of_device"] = round(out[mode]["comm_ms_per_iter"] / d["comm_ms_per_iter"], 2)
         out[mode]["iter_speedup_of_device"] = round(out[mode]["ms_per_iter"] / d["ms_per_iter"], 2)
+    o = out["device_overlap"]
+    o["note"] = ("boundary tiles first, then pack / exchange / unpack of the new iterate on a second stream while "
+                 "the interior tiles sweep; comm and sweep times overlap, the iteration is ms_per_iter")
+    o["iter_speedup_over_device"] = round(d["ms_per_iter"] / o["ms_per_iter"], 3)
     return out
 
 

@@ -105,6 +105,16 @@ typedef struct jc_options {
                             pairs); the residual sweeps of jc_solve and jc_sweep run one
                             sweep per launch, and groups follow their own flag
                             (jc_group_create).  0: one sweep per launch. */
+    int overlap;         /* staged mode with the device exchange: 1 = boundary-first
+                            iterations -- the tiles that hold a paired face plane sweep
+                            first; then, on a second stream of the library (default
+                            priority), the faces of the new iterate are packed, exchanged
+                            and unpacked while the interior tiles sweep on the bound
+                            stream, which waits for the halo before the next iteration
+                            (the computation-communication overlap that
+                            overdecomposition allows, sections 2.3 and 6).  Results are
+                            bitwise the same as without.  0: pack, exchange, unpack,
+                            then the whole sweep. */
 } jc_options;
 
 /* Result of a solve. */

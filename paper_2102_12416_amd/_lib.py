@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("with_source", ctypes.c_int), ("ir_dtype", ctypes.c_int),
                 ("ir_enable", ctypes.c_int), ("tile_y", ctypes.c_int), ("z_chunk", ctypes.c_int),
                 ("use_graphs", ctypes.c_int), ("debug_epochs", ctypes.c_int), ("tile_x", ctypes.c_int),
-                ("exchange", ctypes.c_int), ("temporal", ctypes.c_int)]
+                ("exchange", ctypes.c_int), ("temporal", ctypes.c_int), ("overlap", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

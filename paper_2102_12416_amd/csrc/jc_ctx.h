@@ -130,6 +130,12 @@ struct jc_ctx {
     // pace of the one-sweep launches of the solve loop (jc_set_pace): ticks
     // of the 100 MHz constant clock per plane step; 0 = none
     uint32_t pace = 0;
+    // boundary-first iterations (options.overlap): the work list holds the
+    // n_bnd tiles with a paired face plane first; the halo of the new
+    // iterate moves on `side` between ev_fork and ev_join
+    int64_t n_bnd = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<Item> items;
     int64_t max_items = 0;
     // arena layout

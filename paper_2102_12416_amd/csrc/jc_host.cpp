@@ -109,6 +109,20 @@ void build_items(jc_ctx* c)
                     c->items.push_back(it);
                 }
     }
+    // boundary-first iterations: the tiles holding a cell of a paired face
+    // plane go first (their sweep writes every face value of the new
+    // iterate), the interior tiles after them
+    c->n_bnd = 0;
+    if (c->opt.overlap && c->np()) {
+        auto boundary = [c](const Item& it) {
+            const HostBlock& b = c->blocks[it.block];
+            return (b.nbr[jc::XM] >= 0 && it.x0 == 0) || (b.nbr[jc::XP] >= 0 && it.x0 + c->tile_x >= b.n[0]) ||
+                   (b.nbr[jc::YM] >= 0 && it.y0 == 0) || (b.nbr[jc::YP] >= 0 && it.y0 + c->tile_y >= b.n[1]) ||
+                   (b.nbr[jc::ZM] >= 0 && it.z0 == 0) || (b.nbr[jc::ZP] >= 0 && it.z0 + it.zlen >= b.n[2]);
+        };
+        const auto mid = std::stable_partition(c->items.begin(), c->items.end(), boundary);
+        c->n_bnd = mid - c->items.begin();
+    }
 }
 
 int validate_options(const jc_options* opt)
@@ -139,6 +153,10 @@ int validate_options(const jc_options* opt)
         return fail(JC_ERR_INVALID, "options.z_chunk must be >= 0");
     if (opt->temporal != 0 && opt->temporal != 1)
         return fail(JC_ERR_INVALID, "options.temporal must be 0 or 1");
+    if (opt->overlap != 0 && opt->overlap != 1)
+        return fail(JC_ERR_INVALID, "options.overlap must be 0 or 1");
+    if (opt->overlap && (opt->mode != JC_MODE_STAGED || opt->exchange != JC_EXCHANGE_DEVICE))
+        return fail(JC_ERR_INVALID, "options.overlap needs the staged mode with the device exchange");
     if (opt->ir_enable && opt->ir_dtype != JC_F64 && opt->ir_dtype != JC_F32 && opt->ir_dtype != JC_BF16)
         return fail(JC_ERR_INVALID, "options.ir_dtype must be JC_F64, JC_F32 or JC_BF16 when ir_enable is set");
     return JC_OK;
@@ -571,10 +589,69 @@ int do_halo(jc_ctx* c)
     return st;
 }
 
+// One staged iteration, boundary first: the tiles that hold a paired face
+// plane sweep on the bound stream while the interior tiles sweep on the
+// side stream at the same time; as soon as the boundary tiles are done,
+// the faces of the new iterate are packed, exchanged and unpacked on the
+// bound stream, overlapping the rest of the interior sweep, and the bound
+// stream then waits for the interior.  Every cell is computed by the same
+// kernel from the same inputs as in one launch, so the iterate is bitwise
+// the same.  Hazards: both sweeps read the old copy and write disjoint
+// cells of the new one; the halo steps read the new iterate's face planes
+// (written by boundary tiles only) and write its ghost planes (which the
+// interior tiles neither read nor write: a pair store that reaches the
+// x = nx + 1 ghost of a paired face belongs to a boundary tile).
+int overlapped_iteration(jc_ctx* c, bool resid)
+{
+    if (c->ghost != GHOST_CURRENT) {
+        int st = do_halo(c);
+        if (st != JC_OK)
+            return st;
+    }
+    const bool src = c->opt.with_source != 0;
+    const int nb = (int)c->n_bnd, ni = (int)c->items.size() - nb;
+    JC_HIP(hipEventRecord(c->ev_fork, c->stream));
+    JC_HIP(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    int st = timed(c, JC_K_SWEEP, [&] {
+        return jc::launch_sweep(c->d_blocks(), c->d_items(), nb, c->parity, c->tile_x, c->tile_y, false, resid, true,
+                                src, c->d_partials(), c->stream);
+    });
+    if (st != JC_OK)
+        return st;
+    // the interior tiles, on the side stream
+    std::swap(c->stream, c->side);
+    st = timed(c, JC_K_SWEEP, [&] {
+        return jc::launch_sweep(c->d_blocks(), c->d_items() + nb, ni, c->parity, c->tile_x, c->tile_y, false, resid,
+                                true, src, c->d_partials() + nb, c->stream);
+    });
+    std::swap(c->stream, c->side);
+    if (st != JC_OK)
+        return st;
+    JC_HIP(hipEventRecord(c->ev_join, c->side));
+    // the halo of the new iterate (copy parity ^ 1)
+    c->parity ^= 1;
+    st = do_pack(c, 0);
+    if (st == JC_OK)
+        st = do_exchange(c);
+    if (st == JC_OK)
+        st = do_unpack(c);
+    c->parity ^= 1;
+    if (st != JC_OK)
+        return st;
+    JC_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    c->parity ^= 1;
+    c->iters += 1;
+    c->ghost = GHOST_CURRENT;
+    c->fused_primed = false;
+    return JC_OK;
+}
+
 // One full iteration of the context's mode; resid: the sweep also sums
 // r^2 of its input iterate into the partials.
 int one_iteration(jc_ctx* c, bool resid)
 {
+    if (c->side && c->opt.mode == JC_MODE_STAGED)
+        return overlapped_iteration(c, resid);
     if (c->opt.mode == JC_MODE_FUSED) {
         if (!c->fused_primed && c->np()) {
             int st = do_pack(c, c->parity);
@@ -922,6 +999,14 @@ void jc_destroy(jc_ctx* c)
         if (c->h_stage)
             (void)hipHostFree(c->h_stage);
     }
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork)
+        (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join)
+        (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -942,6 +1027,12 @@ int jc_bind(jc_ctx* c, void* dev_arena, size_t bytes, void* hip_stream)
     c->arena_bytes = bytes;
     c->stream = static_cast<hipStream_t>(hip_stream);
     JC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(double) * 4, hipHostMallocDefault));
+    if (c->opt.overlap && c->np()) {
+        // the halo stream of boundary-first iterations (default priority)
+        JC_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        JC_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        JC_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
     if (c->opt.exchange == JC_EXCHANGE_HOST && c->np()) {
         size_t off = 0;
         c->h_stage_off.assign(c->np(), 0);

@@ -27,11 +27,13 @@ class Solver:
     block edges, a rectilinear decomposition) chooses the blocks; neither
     means one block.  mode: 'staged' (pack, exchange, unpack, sweep
     kernels) or 'fused' (one launch per iteration).  temporal: a one-block
-    context advances iterate/solve windows two sweeps per launch."""
+    context advances iterate/solve windows two sweeps per launch.  overlap
+    (staged mode): boundary tiles sweep first, then the halo of the new
+    iterate moves on a second stream while the interior tiles sweep."""
 
     def __init__(self, grid, block_dims=None, cuts=None, mode="staged", with_source=False,
                  tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None,
-                 tile_x=0, exchange="device", temporal=False):
+                 tile_x=0, exchange="device", temporal=False, overlap=False):
         self.grid = tuple(int(v) for v in grid)
         self.device = torch.device(device)
         self.opt = L.Options()
@@ -48,6 +50,7 @@ class Solver:
         self.opt.z_chunk = int(z_chunk)
         self.opt.use_graphs = int(bool(use_graphs))
         self.opt.temporal = int(bool(temporal))
+        self.opt.overlap = int(bool(overlap))
         self.with_source = bool(with_source)
         self._ctx = ctypes.c_void_p()
         g = L.i64(self.grid)

@@ -304,6 +304,27 @@ def test_pace_validation_and_reset_by_tiles():
     L.lib.jc_destroy(ctx)
 
 
+def test_overlap_option_validation():
+    opt = L.Options()
+    opt.ir_dtype = L.JC_NONE
+    opt.overlap = 1
+    ctx = ctypes.c_void_p()
+    opt.mode = L.JC_MODE_FUSED
+    assert L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    opt.mode = L.JC_MODE_STAGED
+    opt.exchange = L.JC_EXCHANGE_HOST
+    assert L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    opt.exchange = L.JC_EXCHANGE_DEVICE
+    opt.overlap = 2
+    assert L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    opt.overlap = 1
+    check(L.lib.jc_create(L.i64((8, 8, 8)), L.i64((4, 8, 8)), ctypes.byref(opt), ctypes.byref(ctx)))
+    L.lib.jc_destroy(ctx)
+
+
 def test_sixteen_cell_tile_options():
     st, ctx = create((40, 24, 24), (40, 24, 24), tile_x=16, tile_y=4)
     assert st == L.JC_ERR_INVALID

@@ -174,6 +174,53 @@ def test_tile_shapes_bitwise(tile_x, tile_y, z_chunk, mode):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("graphs", [False, True])
+@pytest.mark.parametrize("n,bd,tile", [((37, 29, 23), (16, 8, 10), (64, 8, 16)),
+                                       ((64, 48, 40), (32, 24, 20), (32, 8, 7)),
+                                       ((131, 70, 66), (65, 35, 33), (64, 16, 16)),
+                                       ((5, 70, 3), (5, 7, 1), (16, 8, 16))])
+def test_overlap_boundary_first_bitwise(n, bd, tile, graphs):
+    """Boundary-first staged iterations (the halo of the new iterate moves
+    on a second stream while the interior tiles sweep): iterates bitwise
+    the oracle's after odd and even counts, odd block widths included (the
+    pair store that rewrites an x = nx + 1 ghost), and the residual history
+    of a solve the oracle's to 1e-12."""
+    say("overlap", n, bd, tile, "graphs" if graphs else "eager")
+    u0 = synth.boundary_field(n, seed=13)
+    b = synth.source_field(n, seed=13)
+    ref7, _ = oracle.c_jacobi(u0, 7, b)
+    ref20, hist = oracle.c_jacobi(u0, 20, b, every=5)
+    with Solver(n, block_dims=bd, mode="staged", with_source=True, overlap=True, use_graphs=graphs,
+                tile_x=tile[0], tile_y=tile[1], z_chunk=tile[2]) as s:
+        s.load(u0, b)
+        s.iterate(7)
+        assert np.array_equal(s.store().cpu().numpy(), ref7)
+        s.iterate(6)
+        s.iterate(7)
+        assert np.array_equal(s.store().cpu().numpy(), ref20)
+        s.load(u0, b)
+        info = s.solve(rtol=0.0, max_iter=20, check_every=5, history=True)
+        assert np.array_equal(s.store().cpu().numpy(), ref20)
+    np.testing.assert_allclose(info["history"], hist, rtol=1e-12, atol=0)
+
+
+def test_overlap_timing_counts_every_launch():
+    """With kernel timing on, an overlapped iteration launches two sweeps
+    and one pack, exchange and unpack, all timed."""
+    n = (64, 48, 40)
+    say("overlap timing")
+    u0 = synth.boundary_field(n, seed=14)
+    ref, _ = oracle.c_jacobi(u0, 5, None)
+    with Solver(n, block_dims=(32, 24, 20), mode="staged", overlap=True, use_graphs=False) as s:
+        s.load(u0)
+        s.set_timing(True)
+        s.iterate(5)
+        assert s.kernel_time(L.JC_K_SWEEP)[1] == 10
+        assert s.kernel_time(L.JC_K_PACK)[1] == 5 and s.kernel_time(L.JC_K_UNPACK)[1] == 5
+        s.set_timing(False)
+        assert np.array_equal(s.store().cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("mode", ["staged", "fused"])
 def test_pace_keeps_results_bitwise(mode):
     """A pace only delays work-groups: iterates are bitwise those of the
