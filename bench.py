@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--mode", default=None, choices=["staged", "fused"])
     ap.add_argument("--temporal", action="store_true",
                     help="one-block workloads: two sweeps per launch (temporal blocking)")
+    ap.add_argument("--sweeps-per-launch", type=int, default=2, choices=[2, 3],
+                    help="with --temporal: sweeps per launch (two or three)")
     ap.add_argument("--temporal-tile", default="",
                     help="rows,z_chunk of the two-sweep launch (8, 16 or 24 rows; default: stored or autotuned)")
     ap.add_argument("--seed", type=int, default=12416)
@@ -127,6 +129,14 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+def tmode(args):
+    """The temporal argument of Solver / Group / Server for --temporal and
+    --sweeps-per-launch: False, True (two sweeps per launch) or 3."""
+    if not args.temporal:
+        return False
+    return 3 if args.sweeps_per_launch == 3 else True
 
 
 def copy_probe():
@@ -250,36 +260,40 @@ def exchange_ab(grid, bd, seed, iters, tiles):
     return out
 
 
-def temporal_one_block(grid, seed, iters=200):
+def temporal_one_block(grid, seed, iters=198):
     """Context for the bench line: the grid as one block with temporal
-    blocking (two sweeps per launch, shape from jc_autotune), timed as one
-    graph replay of `iters` iterations after a warm-up, apart from the
-    headline measurement."""
+    blocking, two and three sweeps per launch (shapes from jc_autotune),
+    each timed as one graph replay of `iters` iterations after a warm-up,
+    apart from the headline measurement."""
     import torch
 
     from paper_2102_12416_amd import Solver, synth_field
-    with Solver(grid, mode="fused", temporal=True) as s:
-        s.load(synth_field(grid, seed, 0))
-        s.autotune(reps=3)
-        s.iterate(iters)
-        s.iterate(iters)                 # captures the window's graph
-        s.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(s.stream)
-        s.iterate(iters)
-        e1.record(s.stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1)
-        t2 = s.temporal_info()
-    cells = float(grid[0]) * grid[1] * grid[2]
-    launch_ms = 2 * ms / iters
-    return {"grid": list(grid), "blocks": 1, "kernel": "k_sweep2", "temporal_tile": [t2["rows"], t2["z_chunk"]],
-            "iterations": iters, "glups": round(cells * iters / (ms * 1e-3) / 1e9, 1),
-            "ms_per_two_sweep_launch": round(launch_ms, 5),
+    out = {"grid": list(grid), "blocks": 1, "iterations": iters,
+           "note": "the same grid as one block (no inter-block exchange), several sweeps per launch: bitwise the "
+                   "same iterate; not the headline, which exchanges halos between 8 blocks every iteration"}
+    for depth, temporal in ((2, True), (3, 3)):
+        with Solver(grid, mode="fused", temporal=temporal) as s:
+            s.load(synth_field(grid, seed, 0))
+            s.autotune(reps=3)
+            s.iterate(iters)
+            s.iterate(iters)                 # captures the window's graph
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.iterate(iters)
+            e1.record(s.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            t2 = s.temporal_info()
+        cells = float(grid[0]) * grid[1] * grid[2]
+        launch_ms = depth * ms / iters
+        out["%s_sweeps" % ("two" if depth == 2 else "three")] = {
+            "kernel": "k_sweep%d" % depth, "temporal_tile": [t2["rows"], t2["z_chunk"]],
+            "glups": round(cells * iters / (ms * 1e-3) / 1e9, 1), "ms_per_launch": round(launch_ms, 5),
             "roofline_frac": round(16 * cells / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "note": "two sweeps per launch on one block (no inter-block exchange): bitwise the same iterate; "
-                    "not the headline, which exchanges halos between 8 blocks every iteration"}
+            "bytes_per_unit": "16 B per cell per launch (%.2f B per update)" % (16.0 / depth)}
+    return out
 
 
 def cpu_baseline(grid, seed, seconds):
@@ -606,14 +620,14 @@ def bench_batch(args):
     t0 = time.perf_counter()
     seq_iters = []
     for r in reqs:
-        with Solver((n, n, n), mode="fused", with_source=True, temporal=bool(args.temporal)) as s:
+        with Solver((n, n, n), mode="fused", with_source=True, temporal=tmode(args)) as s:
             s.load(synth_field((n, n, n), r.seed, 0), synth_field((n, n, n), r.seed, 1))
             info = s.solve(rtol=rtol, max_iter=cap, check_every=window)
             seq_iters.append(info["iters"])
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t0
     print("[bench] one after another: %.3f s" % seq_s, file=sys.stderr, flush=True)
-    srv = Server(budget_bytes=1 << 40, window=window, rtol=rtol, max_iter=cap, lanes=(), temporal=bool(args.temporal))
+    srv = Server(budget_bytes=1 << 40, window=window, rtol=rtol, max_iter=cap, lanes=(), temporal=tmode(args))
     t0 = time.perf_counter()
     res = srv.run(reqs, realtime=False)
     bat_s = time.perf_counter() - t0
@@ -622,7 +636,7 @@ def bench_batch(args):
            "value": round(seq_s / bat_s, 3), "unit": "x (speedup of batching)", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "dtype": "f64",
            "config": {"workload": "batch", "grids": count, "grid": [n, n, n], "rtol": rtol, "check_every": window,
-                      "temporal": bool(args.temporal),
+                      "temporal": bool(args.temporal), "sweeps_per_launch": args.sweeps_per_launch if args.temporal else 1,
                       "source": "U[-1,1) SplitMix64", "boundary": "U[0,1) SplitMix64"},
            "one_after_another_s": round(seq_s, 3), "batched_s": round(bat_s, 3),
            "sweeps_per_solve": [min(seq_iters), max(seq_iters)], "same_stop_as_alone": all(same),
@@ -651,12 +665,12 @@ def bench_grids(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "768_grids", "grids": count, "grid": [n, n, n], "tile": list(tile),
                       "mode": "group of independent single-block solves",
-                      "temporal": bool(args.temporal),
+                      "temporal": bool(args.temporal), "sweeps_per_launch": args.sweeps_per_launch if args.temporal else 1,
                       "launch": "hipGraph replay of the timed window"}}
     if args.temporal and args.steps % 2:
         print("bench.py: --temporal needs an even --steps", file=sys.stderr)
         sys.exit(2)
-    with Group(solvers, use_graphs=True, tile=tile, temporal=bool(args.temporal)) as grp:
+    with Group(solvers, use_graphs=True, tile=tile, temporal=tmode(args)) as grp:
         grp.iterate(args.warmup)
         # capture the timed window's graph outside the timed region (both
         # start parities when the window is odd)
@@ -712,7 +726,7 @@ def bench_serve(args):
 
     def server():
         return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter,
-                      progress_every=15.0, lanes=lanes, temporal=bool(args.temporal),
+                      progress_every=15.0, lanes=lanes, temporal=tmode(args),
                       tile=[int(v) for v in args.serve_tile.split(",")] if args.serve_tile else None)
 
     cap = None
@@ -786,8 +800,10 @@ def main():
         kw["cuts"] = [synth.uneven_cuts(grid[a], 32, 160, seed=uneven_seed, axis=a) for a in range(3)]
     graphs = args.graphs == "on" or (args.graphs == "auto" and mode == "fused")
     temporal = bool(args.temporal)
-    if temporal and (bd is not None or uneven_seed is not None or args.steps % 2):
-        print("bench.py: --temporal needs a one-block workload and an even --steps", file=sys.stderr)
+    depth = (3 if args.sweeps_per_launch == 3 else 2) if temporal else 1
+    if temporal and (bd is not None or uneven_seed is not None or args.steps % depth):
+        print("bench.py: --temporal needs a one-block workload and --steps a multiple of the sweeps per launch",
+              file=sys.stderr)
         sys.exit(2)
     if graphs and mode != "fused":
         print("bench.py: --graphs needs the fused mode (one launch per iteration)", file=sys.stderr)
@@ -795,7 +811,7 @@ def main():
     print("[bench] workload %s mode %s: building inputs" % (args.workload, mode), file=sys.stderr, flush=True)
     u0 = synth.boundary_field(grid, seed=args.seed)
     s = Solver(grid, mode=mode, use_graphs=graphs, tile_x=args.tile_x, tile_y=args.tile_y, z_chunk=args.z_chunk,
-               temporal=temporal, **kw)
+               temporal=tmode(args), **kw)
     s.load(u0)
     del u0
     nb = s.num_blocks
@@ -806,7 +822,7 @@ def main():
         if args.temporal_tile:
             s.set_temporal_tiles(*[int(v) for v in args.temporal_tile.split(",")])
             tile_source = "given"
-        elif args.workload in TUNED_TEMPORAL and not args.autotune:
+        elif args.workload in TUNED_TEMPORAL and depth == 2 and not args.autotune:
             s.set_temporal_tiles(*TUNED_TEMPORAL[args.workload])
             tile_source = "tuned (jc_autotune on MI355X)"
         else:
@@ -860,10 +876,10 @@ def main():
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     kinds = {"sweep": L.JC_K_SWEEP, "pack": L.JC_K_PACK, "exchange": L.JC_K_EXCHANGE,
-             "unpack": L.JC_K_UNPACK, "fused": L.JC_K_FUSED, "sweep2": L.JC_K_SWEEP2}
+             "unpack": L.JC_K_UNPACK, "fused": L.JC_K_FUSED, "sweep2": L.JC_K_SWEEP2, "sweep3": L.JC_K_SWEEP3}
     if graphs and temporal:
-        # one two-sweep launch per two iterations
-        ktime = {"sweep2": (gpu_ms, args.steps // 2)}
+        # one multi-sweep launch per `depth` iterations
+        ktime = {"sweep%d" % depth: (gpu_ms, args.steps // depth)}
     elif graphs:
         # one fused launch per iteration: the stream time per iteration bounds
         # the sweep's launch time from above
@@ -880,12 +896,12 @@ def main():
     lups = float(nx) * ny * nz
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     glups = lups * args.steps / (ms_per_step * args.steps * 1e-3) / 1e9
-    dom = "sweep2" if temporal else "fused" if mode == "fused" else "sweep"
+    dom = ("sweep%d" % depth) if temporal else "fused" if mode == "fused" else "sweep"
     dom_ms, dom_n = ktime[dom]
     avg_ms = dom_ms / max(dom_n, 1)
     # read u, write u' per cell update; the two-sweep launch reads iterate k
     # and writes iterate k + 2 once per cell (8 B per update)
-    sweep_bytes = (8.0 if temporal else 16.0) * lups
+    sweep_bytes = 16.0 / depth * lups
     launch_bytes = 16.0 * lups
     halo_values = sum(s.pair_info(q)["count"] for q in range(s.num_pairs))
     # the fused sweep also moves the halo: each exchanged face value is
@@ -910,6 +926,7 @@ def main():
         "config": {"workload": args.workload, "grid": list(grid), "blocks": nb, "mode": mode,
                    "iterations": args.steps, "tile": [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
                    "temporal": temporal,
+                   "sweeps_per_launch": depth,
                    "temporal_tile": t2_shape,
                    "pace": pace,
                    "tile_source": tile_source,
@@ -918,14 +935,16 @@ def main():
         "hbm_gbs_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "pct_hbm_peak_step": round(100 * step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm",
-                     "kernel": "k_sweep2" if temporal else "k_sweep" if mode == "staged" else "k_sweep(fused)",
+                     "kernel": ("k_sweep%d" % depth) if temporal else "k_sweep" if mode == "staged" else "k_sweep(fused)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic_temporal(args.workload, t2_shape) if temporal else recorded_traffic(
+                     "traffic": (recorded_traffic_temporal(args.workload, t2_shape) if depth == 2 else None)
+                     if temporal else recorded_traffic(
                          args.workload, mode, [tiles["tile_x"], tiles["tile_y"], tiles["z_chunk"]],
                          pace["ticks"] if pace else 0),
                      "bytes_per_launch": kernel_bytes, "avg_launch_ms": round(avg_ms, 5),
-                     "bytes_per_unit": ("16 B per cell per two-sweep launch (8 B per update)" if temporal else
+                     "bytes_per_unit": (("16 B per cell per %d-sweep launch (%.2f B per update)" % (depth, 16.0 / depth))
+                                        if temporal else
                                         "16 B per update" + (" + 16 B per exchanged face value (%d values)"
                                                              % halo_values if mode == "fused" else ""))},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in ktime.items() if v[1]},

@@ -75,10 +75,11 @@ enum {
  * Messaging API's receiver needs a host message before it can post its
  * receive.  HOST and METADATA disable graph capture. */
 enum { JC_EXCHANGE_DEVICE = 0, JC_EXCHANGE_HOST = 1, JC_EXCHANGE_METADATA = 2 };
-/* kinds for jc_kernel_time (JC_K_SWEEP2: the two-sweep launches of temporal blocking) */
+/* kinds for jc_kernel_time (JC_K_SWEEP2 / JC_K_SWEEP3: the two- and
+ * three-sweep launches of temporal blocking) */
 enum { JC_K_SWEEP = 0, JC_K_PACK = 1, JC_K_EXCHANGE = 2, JC_K_UNPACK = 3,
        JC_K_RESIDUAL = 4, JC_K_FUSED = 5, JC_K_IR_INNER = 6, JC_K_IR_OUTER = 7,
-       JC_K_SWEEP2 = 8, JC_K_COUNT = 9 };
+       JC_K_SWEEP2 = 8, JC_K_SWEEP3 = 9, JC_K_COUNT = 10 };
 
 typedef struct jc_ctx jc_ctx;
 typedef struct jc_group jc_group;
@@ -115,6 +116,11 @@ typedef struct jc_options {
                             overdecomposition allows, sections 2.3 and 6).  Results are
                             bitwise the same as without.  0: pack, exchange, unpack,
                             then the whole sweep. */
+    int sweeps_per_launch; /* with temporal = 1: 2 (also 0) or 3.  Three: iterates k + 1
+                            and k + 2 stay on chip, so each cell is read and written once
+                            per three sweeps (tiles of 8 or 16 rows); a count that is
+                            not a multiple of three ends with a two-sweep launch or a
+                            single sweep.  Results bitwise the same. */
 } jc_options;
 
 /* Result of a solve. */
@@ -261,7 +267,10 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * (temporal blocking; every member one block, else JC_ERR_INVALID; tiles
  * of 64 cells x 16 rows x max(planes, 32); the first inner sweep of a
  * refinement step and the last of an odd count are single-sweep launches;
- * results bitwise the same as one sweep per launch).  tile: {cells per row 16|32|64,
+ * results bitwise the same as one sweep per launch); bit 2 = three sweeps
+ * per launch (the same conditions and tiles; a count that is not a
+ * multiple of three ends with a two-sweep launch or a single sweep).
+ * tile: {cells per row 16|32|64,
  * rows 4|8|16|32 (at least 8 for 16-cell rows), planes >= 1} for every
  * launch of the group, or NULL for {64, 8, 32}; members' results do not
  * depend on it, their residual norms do in the last bits, so compare
@@ -351,13 +360,14 @@ int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed
  * when bound). */
 int jc_set_tiles(jc_ctx* ctx, int tile_x, int tile_y, int z_chunk);
 
-/* Shape of the two-sweep launch of temporal blocking: rows of its tile
- * (8, 16 or 24; the tile is 64 cells wide) and planes per work-group (>= 1).
+/* Shape of the multi-sweep launch of temporal blocking: rows of its tile
+ * (8, 16 or 24 for two sweeps per launch, 8 or 16 for three; the tile is 64
+ * cells wide) and planes per work-group (>= 1).
  * Results are bitwise independent of it.  JC_ERR_STATE unless the context
  * was created with temporal = 1. */
 int jc_set_temporal_tiles(jc_ctx* ctx, int rows, int z_chunk);
-/* out = {temporal (0 or 1), rows, planes per work-group} of the two-sweep
- * launch.  Until set (jc_set_temporal_tiles or jc_autotune), the planes
+/* out = {sweeps per launch (2 or 3; 0 without temporal blocking), rows,
+ * planes per work-group} of the multi-sweep launch.  Until set (jc_set_temporal_tiles or jc_autotune), the planes
  * follow the one-sweep z_chunk, at least 32, halved (down to 8) while a
  * launch would have fewer than 1024 work-groups. */
 int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);

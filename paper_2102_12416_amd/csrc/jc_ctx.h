@@ -96,6 +96,7 @@ constexpr int kTwoStepMinZ = 32;
 constexpr int kTwoStepFloorZ = 8;
 constexpr int64_t kTwoStepMinGroups = 1024;
 constexpr int kTwoStepRowCandidates[] = {8, 16, 24};
+constexpr int kThreeStepRowCandidates[] = {8, 16};
 inline bool two_step_rows_ok(int rows)
 {
     bool ok = false;
@@ -103,6 +104,7 @@ inline bool two_step_rows_ok(int rows)
         ok = ok || r == rows;
     return ok;
 }
+inline bool three_step_rows_ok(int rows) { return rows == 8 || rows == 16; }
 
 }  // namespace jc_rt
 
@@ -130,6 +132,8 @@ struct jc_ctx {
     // pace of the one-sweep launches of the solve loop (jc_set_pace): ticks
     // of the 100 MHz constant clock per plane step; 0 = none
     uint32_t pace = 0;
+    // sweeps per launch of the solve loop: 1, or 2 / 3 with temporal blocking
+    int depth() const { return !opt.temporal ? 1 : opt.sweeps_per_launch == 3 ? 3 : 2; }
     // boundary-first iterations (options.overlap): the work list holds the
     // n_bnd tiles with a paired face plane first; the halo of the new
     // iterate moves on `side` between ev_fork and ev_join

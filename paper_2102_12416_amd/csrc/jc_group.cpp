@@ -57,7 +57,8 @@ struct jc_group {
     std::vector<BlockDesc> desc;        // joint block table, class-major
     std::vector<Item> items;            // joint work list, class-major
     std::vector<Item> items2;           // joint two-sweep work list, class-major
-    bool two_step = false;              // every launch sweeps every member twice
+    bool two_step = false;              // every launch sweeps every member twice (or three times)
+    bool three_step = false;            // three sweeps of every member per launch
     std::vector<int32_t> lohi;          // per member: joint item range
     std::vector<int> member_bstart;     // per member: first joint block
     size_t off_desc = 0, off_items = 0, off_items2 = 0, off_partials = 0, off_lohi = 0, off_out = 0, footprint = 0;
@@ -171,16 +172,34 @@ int group_sweep2(jc_group* g)
     return JC_OK;
 }
 
-// Bookkeeping after one two-sweep launch: every member advanced two
-// sweeps and its iterate (a refining member: its correction) moved to the
-// other copy once, as the launch parity did.
-void advance2(jc_group* g)
+// Three sweeps of every member in one launch per class (the two-sweep
+// tiles serve the three-sweep kernel too: 64 cells by 16 rows).
+int group_sweep3(jc_group* g)
+{
+    for (const Class& k : g->classes) {
+        hipError_t e;
+        if (!k.ir)
+            e = jc::launch_sweep3(g->d_desc(), g->d_items2() + k.item2_0, (int)k.items2.size(), 0, 0, 0, g->parity,
+                                  kGroupTwoStepRows, 0, k.src, g->stream);
+        else
+            e = jc::launch_ir_inner3(g->d_desc(), g->d_items2() + k.item2_0, (int)k.items2.size(), 0, 0, 0,
+                                     g->members[k.members[0]]->ir_q, kGroupTwoStepRows, 0, k.lo, g->stream);
+        if (e != hipSuccess)
+            return ghip(e, "group three-sweep launch");
+    }
+    return JC_OK;
+}
+
+// Bookkeeping after one multi-sweep launch of `sweeps` sweeps: every
+// member advanced that many sweeps and its iterate (a refining member: its
+// correction) moved to the other copy once, as the launch parity did.
+void advance2(jc_group* g, int sweeps = 2)
 {
     g->parity ^= 1;
     for (const Class& k : g->classes)
         for (int m : k.members) {
             jc_ctx* c = g->members[m];
-            c->iters += 2;
+            c->iters += sweeps;
             if (!k.ir) {
                 c->parity ^= 1;
                 c->ghost = GHOST_CURRENT;
@@ -223,6 +242,11 @@ int group_run(jc_group* g, int64_t n)
 {
     int64_t i = 0;
     int st = JC_OK;
+    if (g->three_step)
+        for (; i + 3 <= n && st == JC_OK; i += 3) {
+            st = group_sweep3(g);
+            advance2(g, 3);
+        }
     if (g->two_step)
         for (; i + 2 <= n && st == JC_OK; i += 2) {
             st = group_sweep2(g);
@@ -246,7 +270,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     *out = nullptr;
     if (!ctxs || n < 1)
         return fail(JC_ERR_INVALID, "a group needs at least one context");
-    if (flags & ~3)
+    if (flags & ~7)
         return fail(JC_ERR_INVALID, "unknown group flags");
     std::set<const jc_ctx*> seen;
     for (int i = 0; i < n; ++i) {
@@ -258,8 +282,8 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             return fail(JC_ERR_INVALID, "a context appears twice in the group");
         if (c->opt.ir_enable && c->parity != 0)
             return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
-        if ((flags & 2) && c->nb() != 1)
-            return fail(JC_ERR_INVALID, "two sweeps per launch (flag 2) needs members of one block");
+        if ((flags & 6) && c->nb() != 1)
+            return fail(JC_ERR_INVALID, "two or three sweeps per launch (flag 2 or 4) needs members of one block");
     }
     if (tile) {
         const bool ok = jc_rt::tile_shape_ok(tile[0], tile[1]) && tile[2] >= 1;
@@ -275,7 +299,8 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     g->members.assign(ctxs, ctxs + n);
     g->stream = static_cast<hipStream_t>(hip_stream);
     g->use_graphs = (flags & 1) && g->stream != nullptr;
-    g->two_step = (flags & 2) != 0;
+    g->two_step = (flags & 6) != 0;
+    g->three_step = (flags & 4) != 0;
     // classes, in a fixed order
     std::map<std::tuple<int, int, int>, int> cls;
     for (int i = 0; i < n; ++i) {
@@ -573,13 +598,14 @@ int jc_group_iterate(jc_group* g, int64_t n)
     if (st != JC_OK)
         return st;
     // the state after the replay, as the eager launches would leave it
-    if (g->two_step) {
-        for (int64_t i = 0; i + 2 <= rest; i += 2)
+    int64_t i = 0;
+    if (g->three_step)
+        for (; i + 3 <= rest; i += 3)
+            advance2(g, 3);
+    if (g->two_step)
+        for (; i + 2 <= rest; i += 2)
             advance2(g);
-        advance(g, rest & 1);
-    } else {
-        advance(g, rest);
-    }
+    advance(g, rest - i);
     return JC_OK;
 }
 

@@ -155,6 +155,10 @@ int validate_options(const jc_options* opt)
         return fail(JC_ERR_INVALID, "options.temporal must be 0 or 1");
     if (opt->overlap != 0 && opt->overlap != 1)
         return fail(JC_ERR_INVALID, "options.overlap must be 0 or 1");
+    if (opt->sweeps_per_launch != 0 && opt->sweeps_per_launch != 2 && opt->sweeps_per_launch != 3)
+        return fail(JC_ERR_INVALID, "options.sweeps_per_launch must be 0, 2 or 3");
+    if (opt->sweeps_per_launch == 3 && !opt->temporal)
+        return fail(JC_ERR_INVALID, "options.sweeps_per_launch = 3 needs options.temporal = 1");
     if (opt->overlap && (opt->mode != JC_MODE_STAGED || opt->exchange != JC_EXCHANGE_DEVICE))
         return fail(JC_ERR_INVALID, "options.overlap needs the staged mode with the device exchange");
     if (opt->ir_enable && opt->ir_dtype != JC_F64 && opt->ir_dtype != JC_F32 && opt->ir_dtype != JC_BF16)
@@ -550,14 +554,48 @@ hipError_t launch_ir_two_step(jc_ctx* c, int qparity, int rows, int zc)
                                 c->opt.ir_dtype, c->stream);
 }
 
+// Three sweeps in one launch (temporal blocking, three per launch).
+hipError_t launch_three_step(jc_ctx* c, int rows, int zc)
+{
+    const HostBlock& b = c->blocks[0];
+    return jc::launch_sweep3(c->d_blocks(), nullptr, 0, (int)b.n[0], (int)b.n[1], (int)b.n[2], c->parity, rows, zc,
+                             c->opt.with_source != 0, c->stream);
+}
+
+hipError_t launch_ir_three_step(jc_ctx* c, int qparity, int rows, int zc)
+{
+    const HostBlock& b = c->blocks[0];
+    return jc::launch_ir_inner3(c->d_blocks(), nullptr, 0, (int)b.n[0], (int)b.n[1], (int)b.n[2], qparity, rows, zc,
+                                c->opt.ir_dtype, c->stream);
+}
+
+// Launches that run n sweeps at depth d (sweeps per launch): n / d full
+// launches, then one launch for a remainder (a two-sweep launch for 2, a
+// single sweep for 1).
+int64_t launches_for(int64_t n, int d)
+{
+    return d <= 1 ? n : n / d + (n % d != 0);
+}
+
 // Copy of d that holds the correction after m inner sweeps: the first
-// sweep writes copy 1 and every later launch flips it (a two-sweep
+// sweep writes copy 1 and every later launch flips it (a multi-sweep
 // launch once).
 int ir_final_copy(const jc_ctx* c, int64_t m)
 {
-    const int64_t pairs = c->opt.temporal ? (m - 1) / 2 : 0;
-    const int64_t launches = pairs + (m - 1 - 2 * pairs);
-    return (int)((1 + launches) & 1);
+    return (int)((1 + launches_for(m - 1, c->depth())) & 1);
+}
+
+// Three sweeps in one launch (temporal blocking; one block, no pairs).
+int do_sweep3(jc_ctx* c)
+{
+    int st = timed(c, JC_K_SWEEP3, [&] { return launch_three_step(c, c->t2_rows, two_step_chunk(c)); });
+    if (st != JC_OK)
+        return st;
+    c->parity ^= 1;
+    c->iters += 3;
+    c->ghost = GHOST_CURRENT;
+    c->fused_primed = c->opt.mode == JC_MODE_FUSED;
+    return JC_OK;
 }
 
 // Two sweeps in one launch (temporal blocking; one block, no pairs).
@@ -717,6 +755,13 @@ int residual_now(jc_ctx* c, double* l2)
 int iterate_eager(jc_ctx* c, int64_t n)
 {
     int64_t i = 0;
+    if (c->depth() == 3) {
+        for (; i + 3 <= n; i += 3) {
+            int st = do_sweep3(c);
+            if (st != JC_OK)
+                return st;
+        }
+    }
     if (c->opt.temporal) {
         for (; i + 2 <= n; i += 2) {
             int st = do_sweep2(c);
@@ -780,7 +825,7 @@ int iterate_window(jc_ctx* c, int64_t n)
     JC_HIP(hipGraphLaunch(found->second, c->stream));
     // the state after n iterations, as the eager path would leave it
     // (a two-sweep launch flips the copy once)
-    const int64_t launches = c->opt.temporal ? n / 2 + (n & 1) : n;
+    const int64_t launches = launches_for(n, c->depth());
     c->parity ^= (int)(launches & 1);
     c->iters += n;
     if (c->np()) {
@@ -813,7 +858,13 @@ int tune_two_step(jc_ctx* c, int reps)
         double ms;
     };
     std::vector<Cand> cand;
-    for (int rows : jc_rt::kTwoStepRowCandidates)
+    const bool three = c->depth() == 3;
+    std::vector<int> row_cands;
+    if (three)
+        row_cands.assign(std::begin(jc_rt::kThreeStepRowCandidates), std::end(jc_rt::kThreeStepRowCandidates));
+    else
+        row_cands.assign(std::begin(jc_rt::kTwoStepRowCandidates), std::end(jc_rt::kTwoStepRowCandidates));
+    for (int rows : row_cands)
         for (int nch : {1, 2, 3, 4, 6, 8, 12, 16}) {
             const int zc = (int)((nz + nch - 1) / nch);
             bool dup = false;
@@ -832,6 +883,8 @@ int tune_two_step(jc_ctx* c, int reps)
     // correction arrays, as the one-sweep search left them)
     const bool ir = c->opt.ir_enable != 0;
     auto launch = [&](const Cand& k) {
+        if (three)
+            return ir ? launch_ir_three_step(c, 1, k.rows, k.zc) : launch_three_step(c, k.rows, k.zc);
         return ir ? launch_ir_two_step(c, 1, k.rows, k.zc) : launch_two_step(c, k.rows, k.zc);
     };
     // milliseconds of n launches after one untimed launch
@@ -1390,6 +1443,13 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
             });
             int qq = 1;
             int64_t j = 1;
+            if (c->depth() == 3) {
+                for (; j + 3 <= m && s2 == JC_OK; j += 3) {
+                    s2 = timed(c, JC_K_IR_INNER,
+                               [&] { return launch_ir_three_step(c, qq, c->t2_rows, two_step_chunk(c)); });
+                    qq ^= 1;
+                }
+            }
             if (c->opt.temporal) {
                 for (; j + 2 <= m && s2 == JC_OK; j += 2) {
                     s2 = timed(c, JC_K_IR_INNER,
@@ -1484,8 +1544,11 @@ int jc_set_temporal_tiles(jc_ctx* c, int rows, int z_chunk)
         return fail(JC_ERR_INVALID, "NULL context");
     if (!c->opt.temporal)
         return fail(JC_ERR_STATE, "the context was created without temporal blocking");
-    if (!jc_rt::two_step_rows_ok(rows) || z_chunk < 1)
-        return fail(JC_ERR_INVALID, "rows must be 8, 16 or 24 and z_chunk >= 1");
+    if (c->depth() == 3 ? !jc_rt::three_step_rows_ok(rows) : !jc_rt::two_step_rows_ok(rows))
+        return fail(JC_ERR_INVALID, c->depth() == 3 ? "rows must be 8 or 16 (three sweeps per launch)"
+                                                    : "rows must be 8, 16 or 24");
+    if (z_chunk < 1)
+        return fail(JC_ERR_INVALID, "z_chunk must be >= 1");
     c->t2_rows = rows;
     c->t2_zc = z_chunk;
     free_graphs(c);                        // graphs hold the old launch shapes
@@ -1496,7 +1559,7 @@ int jc_temporal_info(const jc_ctx* c, int64_t out[3])
 {
     if (!c || !out)
         return fail(JC_ERR_INVALID, "NULL argument");
-    out[0] = c->opt.temporal;
+    out[0] = c->opt.temporal ? c->depth() : 0;
     out[1] = c->t2_rows;
     out[2] = two_step_chunk(c);
     return JC_OK;

@@ -40,6 +40,16 @@ hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int
 hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
                                   int lo_dtype, hipStream_t s);
 
+// Three sweeps in one launch (k_sweep3), tiles of 64 cells by tile_y (8 or
+// 16) rows.  items null: the single block of blocks[0] (nx, ny, nz) in z
+// chunks of z_chunk planes; otherwise the work list items[0 .. nitems) of
+// such tiles (groups), each with its block and flip.
+hipError_t launch_sweep3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz, int parity,
+                         int tile_y, int z_chunk, bool src, hipStream_t s);
+// The same for the refinement correction (copy qparity -> qparity ^ 1).
+hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz,
+                            int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s);
+
 // Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
 // of d and r_lo).  Residual: r of u[parity] with fused ghosts (face
 // buffers of slot parity), partial sums of r^2, r rounded into r_lo.

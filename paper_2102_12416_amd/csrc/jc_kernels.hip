@@ -847,6 +847,264 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
 }
 // ---- two-step sweep: end ----
 
+// ---- three-step sweep (temporal blocking): begin ----
+// Three Jacobi sweeps per launch: iterate k from copy p, iterate k + 3 to
+// copy p ^ 1; iterates k + 1 and k + 2 live only in LDS and registers.
+// The construction of k_sweep2 one level deeper.  Iterate k is loaded on
+// a three-cell ring around the tile: TXP + 4 pairs (cells x0 - 3 ..
+// x0 + 2 TXP + 4) by TY + 6 rows, one aligned pair per thread.  At plane
+// step s every thread writes iterate k of its pair at plane s into LDS,
+// the work-group synchronises once, and then
+//  - every thread computes iterate k + 1 of its pair at plane s (valid on
+//    the tile and a two-cell ring; the outermost values, which would need
+//    cells further out, are never read) into LDS plane B;
+//  - the threads of the tile and of its one-pair / one-row ring ("mid"
+//    threads) compute iterate k + 2 at plane s - 1 from B of the previous
+//    step into LDS plane C;
+//  - the tile threads compute iterate k + 3 at plane s - 2 from C of the
+//    previous step and store it.
+// A ghost cell keeps its value at every level (the context has no face
+// pairs: every ghost is a fixed boundary value), and iterates k + 1 and
+// k + 2 are rounded to the storage format as stored sweeps would leave
+// them, so each cell takes the same sums in the same order as in three
+// one-step sweeps: the result is bitwise the same.  The three LDS planes
+// are double-buffered by step parity, so one barrier per step suffices.
+// Thread order: tile threads (whole waves), then the mid ring (rows y0 and
+// y0 + TY + 1 over pairs 1 .. TXP + 2, then pairs 1 and TXP + 2 of the tile
+// rows), then the outer ring (two rows above and below, then pairs 0 and
+// TXP + 3 of the middle rows).  Work as for k_sweep2 (items null: the
+// tiles of blocks[0]; else a work list of 2 TXP x TY tiles).
+template <typename T, int FIELD, int TXP, int TY, bool SRC>
+__global__ void __launch_bounds__(((TXP + 4) * (TY + 6) + 63) / 64 * 64)
+k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int tiles_x,
+         int tiles_y, int nch, int ntiles)
+{
+    using C = typename Tr<T>::C;
+    using F = Fld<T, FIELD>;
+    constexpr int EP = TXP + 4;                   // pairs of an extended row
+    constexpr int ER = TY + 6;                    // extended rows
+    constexpr int NTILE = TXP * TY;               // tile threads
+    constexpr int NMID = NTILE + 2 * (TXP + 2) + 2 * TY;
+    static_assert(NTILE % 64 == 0, "tile threads are whole waves");
+    constexpr int LW = 2 * EP + 2;                // LDS row: pad, 2 EP cells, pad
+    constexpr int LN = (ER + 2) * LW;             // LDS plane: pad row, ER rows, pad row
+    __shared__ C A[2][LN + 1];                    // iterate k; element LN: sink of idle lanes
+    __shared__ C Bn[2][LN + 1];                   // iterate k + 1
+    __shared__ C Cn[2][LN + 1];                   // iterate k + 2
+
+    const int id = logical_block(blockIdx.x, gridDim.x);
+    if (id >= ntiles)
+        return;                                   // uniform over the work-group
+    const BlockDesc* B = blocks;
+    int p = parity, x0, y0, zf, zl;
+    if (items) {
+        const Item it = items[id];
+        B = blocks + it.block;
+        p = parity ^ it.flip;
+        x0 = it.x0;
+        y0 = it.y0;
+        zf = it.z0 + 1;
+        zl = it.z0 + it.zlen;
+    } else {
+        const int per = tiles_x * tiles_y;
+        const int chunk = id / per;
+        const int nzb = B->n[2];
+        x0 = (id % tiles_x) * (2 * TXP);
+        y0 = ((id % per) / tiles_x) * TY;
+        zf = (int)((int64_t)chunk * nzb / nch) + 1;
+        zl = (int)((int64_t)(chunk + 1) * nzb / nch);
+    }
+    const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+
+    // this thread's pair (j, r) of the extended region
+    const int t = threadIdx.x;
+    int j = 0, r = 0;
+    bool live = true;
+    if (t < NTILE) {
+        j = 2 + t % TXP;
+        r = 3 + t / TXP;
+    } else {
+        int q = t - NTILE;
+        if (q < 2 * (TXP + 2)) {                  // mid rows
+            j = 1 + q % (TXP + 2);
+            r = q < TXP + 2 ? 2 : TY + 3;
+        } else if ((q -= 2 * (TXP + 2)) < 2 * TY) {   // mid pairs of the tile rows
+            j = (q & 1) ? TXP + 2 : 1;
+            r = 3 + (q >> 1);
+        } else if ((q -= 2 * TY) < 4 * EP) {      // outer rows
+            j = q % EP;
+            const int k = q / EP;
+            r = k < 2 ? k : TY + 2 + k;
+        } else if ((q -= 4 * EP) < 2 * (TY + 2)) {    // outer pairs of the middle rows
+            j = (q & 1) ? EP - 1 : 0;
+            r = 2 + (q >> 1);
+        } else {
+            live = false;
+        }
+    }
+    const bool tile = t < NTILE;                  // uniform over each wave
+    const bool mid = t < NMID;
+    const int xs = x0 - 3 + 2 * j;                // cells xs, xs + 1 (xs odd, >= -3)
+    const int ye = y0 - 2 + r;
+    const int xs_c = min(xs, nx | 1);             // last pair holding a cell <= nx + 1
+    const int ye_c = min(max(ye, 0), ny + 1);
+    const bool y_in = ye >= 1 && ye <= ny;
+    const bool in_a = live && y_in && xs >= 1 && xs <= nx;
+    const bool in_b = live && y_in && xs + 1 >= 1 && xs + 1 <= nx;
+    const bool a_ok = tile && ye <= ny && xs <= nx;   // tile cells in the block: stored
+    const bool b_ok = tile && ye <= ny && xs + 1 <= nx;
+    const int64_t pitch = F::pitch(B);
+    const int64_t plane = F::plane(B);
+    const int64_t rowoff = (int64_t)ye_c * pitch + xs_c;
+    const T* __restrict__ col = F::src(B, p) + rowoff;
+    const T* __restrict__ scol = SRC ? F::source(B) + rowoff : nullptr;
+    T* __restrict__ dst = F::dst(B, p) + rowoff;
+
+    const int base = (r + 1) * LW + 2 * j + 1;    // LDS slot of cell xs
+    const int wa = live ? base : LN;
+    const int wb = live ? base + 1 : LN;
+
+    // register rings: iterate k and the source of plane s in slot
+    // (s - zf + 2) mod RS, loads issued PD planes ahead; iterates k + 1 of
+    // plane s and k + 2 of plane s - 1 in slot (s - zf + 2) mod 3
+    constexpr int PD = 3;
+    constexpr int RS = 6;
+    const int zlo = max(zf - 3, 0);               // first plane read
+    const int zhi = min(zl + 3, nz + 1);          // last plane read
+    C ua[RS], ub[RS], ba[RS], bb[RS], va[3], vb[3], wa3[3], wb3[3];
+#pragma unroll
+    for (int k = 0; k < RS; ++k)
+        ba[k] = bb[k] = C(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        va[k] = vb[k] = wa3[k] = wb3[k] = C(0);
+    Tr<T>::ld(col + (int64_t)zlo * plane, ua[RS - 1], ub[RS - 1]);
+    if (SRC)
+        Tr<T>::ld(scol + (int64_t)zlo * plane, ba[RS - 1], bb[RS - 1]);
+#pragma unroll
+    for (int k = 0; k < PD; ++k) {
+        const int64_t zk = (int64_t)min(max(zf - 2 + k, 0), zhi) * plane;
+        Tr<T>::ld(col + zk, ua[k], ub[k]);
+        if (SRC)
+            Tr<T>::ld(scol + zk, ba[k], bb[k]);
+    }
+
+    // STAGES: 1 = iterate k + 1 only, 2 = also k + 2, 3 = also k + 3
+    auto step = [&](int s, auto kc, auto stages) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int ST = decltype(stages)::value;
+        constexpr int SM = (K + RS - 1) % RS, SC = K, SP = (K + 1) % RS, SQ = (K + PD) % RS;
+        constexpr int S2 = (K + RS - 2) % RS;     // plane s - 2
+        constexpr int VC = K % 3, VM = (K + 2) % 3, VMM = (K + 1) % 3;
+        constexpr int HC = K & 1;
+        const int64_t zq = (int64_t)min(s + PD, zhi) * plane;
+        Tr<T>::ld(col + zq, ua[SQ], ub[SQ]);
+        if (SRC)
+            Tr<T>::ld(scol + zq, ba[SQ], bb[SQ]);
+        C* const Ak = A[HC];
+        Ak[wa] = ua[SC];
+        Ak[wb] = ub[SC];
+        __syncthreads();
+        // iterate k + 1 at plane s
+        {
+            C sa = Ak[base - 1] + ub[SC];
+            sa = sa + Ak[base - LW];
+            sa = sa + Ak[base + LW];
+            sa = sa + ua[SM];
+            sa = sa + ua[SP];
+            C sb = ua[SC] + Ak[base + 2];
+            sb = sb + Ak[base + 1 - LW];
+            sb = sb + Ak[base + 1 + LW];
+            sb = sb + ub[SM];
+            sb = sb + ub[SP];
+            C na, nb;
+            if (SRC)
+                div6_pair(sa + ba[SC], sb + bb[SC], na, nb);
+            else
+                div6_pair(sa, sb, na, nb);
+            const bool z_in = s >= 1 && s <= nz;
+            va[VC] = (in_a && z_in) ? storage_round<T>(na) : ua[SC];
+            vb[VC] = (in_b && z_in) ? storage_round<T>(nb) : ub[SC];
+            Bn[HC][wa] = va[VC];
+            Bn[HC][wb] = vb[VC];
+        }
+        // iterate k + 2 at plane s - 1
+        if (ST >= 2 && mid) {
+            const C* const Bk = Bn[HC ^ 1];
+            C qa = Bk[base - 1] + vb[VM];
+            qa = qa + Bk[base - LW];
+            qa = qa + Bk[base + LW];
+            qa = qa + va[VMM];
+            qa = qa + va[VC];
+            C qb = va[VM] + Bk[base + 2];
+            qb = qb + Bk[base + 1 - LW];
+            qb = qb + Bk[base + 1 + LW];
+            qb = qb + vb[VMM];
+            qb = qb + vb[VC];
+            C na, nb;
+            if (SRC)
+                div6_pair(qa + ba[SM], qb + bb[SM], na, nb);
+            else
+                div6_pair(qa, qb, na, nb);
+            const bool z_in = s - 1 >= 1 && s - 1 <= nz;
+            wa3[VC] = (in_a && z_in) ? storage_round<T>(na) : va[VM];
+            wb3[VC] = (in_b && z_in) ? storage_round<T>(nb) : vb[VM];
+            Cn[HC][wa] = wa3[VC];
+            Cn[HC][wb] = wb3[VC];
+        }
+        // iterate k + 3 at plane s - 2
+        if (ST >= 3 && tile) {
+            const C* const Ck = Cn[HC ^ 1];
+            C qa = Ck[base - 1] + wb3[VM];
+            qa = qa + Ck[base - LW];
+            qa = qa + Ck[base + LW];
+            qa = qa + wa3[VMM];
+            qa = qa + wa3[VC];
+            C qb = wa3[VM] + Ck[base + 2];
+            qb = qb + Ck[base + 1 - LW];
+            qb = qb + Ck[base + 1 + LW];
+            qb = qb + wb3[VMM];
+            qb = qb + wb3[VC];
+            C oa, ob;
+            if (SRC)
+                div6_pair(qa + ba[S2], qb + bb[S2], oa, ob);
+            else
+                div6_pair(qa, qb, oa, ob);
+            // past the last cell of a row the pair's second slot is the
+            // x = nx + 1 ghost: write back the value it holds
+            ob = b_ok ? ob : ub[S2];
+            if (a_ok)
+                Tr<T>::stn(dst + (int64_t)(s - 2) * plane, oa, ob);
+        }
+    };
+    using One = std::integral_constant<int, 1>;
+    using Two = std::integral_constant<int, 2>;
+    using Three = std::integral_constant<int, 3>;
+    int s = zf - 2;
+    step(s, std::integral_constant<int, 0>{}, One{});
+    step(s + 1, std::integral_constant<int, 1>{}, One{});
+    step(s + 2, std::integral_constant<int, 2>{}, Two{});
+    step(s + 3, std::integral_constant<int, 3>{}, Two{});
+    s += 4;
+#define JC_STEP3(k) step(s + (k), std::integral_constant<int, ((k) + 4) % RS>{}, Three{})
+    const int s_end = zl + 2;
+    for (; s + 5 <= s_end; s += 6) {
+        JC_STEP3(0);
+        JC_STEP3(1);
+        JC_STEP3(2);
+        JC_STEP3(3);
+        JC_STEP3(4);
+        JC_STEP3(5);
+    }
+    if (s <= s_end) JC_STEP3(0);
+    if (s + 1 <= s_end) JC_STEP3(1);
+    if (s + 2 <= s_end) JC_STEP3(2);
+    if (s + 3 <= s_end) JC_STEP3(3);
+    if (s + 4 <= s_end) JC_STEP3(4);
+#undef JC_STEP3
+}
+// ---- three-step sweep: end ----
+
 // First inner sweep of a refinement step: d_1 = lo((0 + r_lo) / 6)
 // (d_0 = 0, so no neighbour is read); writes copy 1 of d and its faces.
 template <typename T>
@@ -1160,6 +1418,75 @@ hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int n
     JC_SWEEP2_ITEMS_CASE(24, true)
 #undef JC_SWEEP2_ITEMS_CASE
     return hipErrorInvalidValue;
+}
+
+// Three sweeps per launch (k_sweep3): the binary64 iterate, or the
+// refinement correction (lo_dtype 0/1/2); tiles of 64 cells by tile_y (8 or
+// 16) rows; items null: the tiles of blocks[0] in z chunks of z_chunk planes.
+template <typename T, int FIELD, int TY, bool SRC>
+hipError_t sweep3_launch(const BlockDesc* blocks, const Item* items, int parity, int tx, int ty, int nch, int n,
+                         hipStream_t s)
+{
+    const int grid = ((n + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_sweep3<T, FIELD, 32, TY, SRC>), dim3(grid), dim3((36 * (TY + 6) + 63) / 64 * 64), 0, s,
+                       blocks, items, parity, tx, ty, nch, n);
+    return hipGetLastError();
+}
+
+template <typename T, int FIELD, bool SRC>
+hipError_t sweep3_rows(const BlockDesc* blocks, const Item* items, int parity, int tile_y, int tx, int ty, int nch,
+                       int n, hipStream_t s)
+{
+    if (tile_y == 8)
+        return sweep3_launch<T, FIELD, 8, SRC>(blocks, items, parity, tx, ty, nch, n, s);
+    if (tile_y == 16)
+        return sweep3_launch<T, FIELD, 16, SRC>(blocks, items, parity, tx, ty, nch, n, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz, int parity,
+                         int tile_y, int z_chunk, bool src, hipStream_t s)
+{
+    int64_t tx = 0, ty = 0, nch = 0, n = nitems;
+    if (!items) {
+        if (nx < 1 || ny < 1 || nz < 1 || z_chunk < 1 || tile_y < 1)
+            return hipErrorInvalidValue;
+        tx = (nx + 63) / 64;
+        ty = (ny + tile_y - 1) / tile_y;
+        nch = (nz + z_chunk - 1) / z_chunk;
+        n = tx * ty * nch;
+    }
+    if (n <= 0)
+        return hipSuccess;
+    if (n > ((int64_t)1 << 30))
+        return hipErrorInvalidValue;
+    return src ? sweep3_rows<double, FIELD_U, true>(blocks, items, parity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s)
+               : sweep3_rows<double, FIELD_U, false>(blocks, items, parity, tile_y, (int)tx, (int)ty, (int)nch, (int)n,
+                                                     s);
+}
+
+hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz,
+                            int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s)
+{
+    int64_t tx = 0, ty = 0, nch = 0, n = nitems;
+    if (!items) {
+        if (nx < 1 || ny < 1 || nz < 1 || z_chunk < 1 || tile_y < 1)
+            return hipErrorInvalidValue;
+        tx = (nx + 63) / 64;
+        ty = (ny + tile_y - 1) / tile_y;
+        nch = (nz + z_chunk - 1) / z_chunk;
+        n = tx * ty * nch;
+    }
+    if (n <= 0)
+        return hipSuccess;
+    if (n > ((int64_t)1 << 30))
+        return hipErrorInvalidValue;
+    switch (lo_dtype) {
+    case 0: return sweep3_rows<double, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s);
+    case 1: return sweep3_rows<float, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s);
+    case 2: return sweep3_rows<bf16, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,

@@ -123,8 +123,8 @@ class Server:
     lanes: ascending edge bounds of the size classes; a request of edge n
     joins the first lane with n <= bound, else the last (unbounded) lane.
     An empty tuple serves everything in one group.  temporal: every size
-    class gets a lane per precision, and every lane sweeps twice per launch
-    (results bitwise the same)."""
+    class gets a lane per precision, and every lane sweeps twice (True) or
+    three times (3) per launch (results bitwise the same)."""
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
@@ -147,10 +147,11 @@ class Server:
         # residual norms, and so its stopping check, then do not depend on
         # who else is in the group
         self.tile = None if tile is None else tuple(int(v) for v in tile)
-        # temporal: every lane's group sweeps twice per launch (bitwise the
-        # same results), and the size lanes are kept per precision
-        self.temporal = bool(temporal)
-        if self.temporal and self.window % 2:
+        # temporal: every lane's group sweeps twice (True) or three times (3)
+        # per launch (bitwise the same results), and the size lanes are kept
+        # per precision
+        self.temporal = 3 if temporal == 3 else bool(temporal)
+        if self.temporal is True and self.window % 2:
             raise ValueError("two sweeps per launch need an even window")
         self.max_members = 4096
         self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0, lane_windows=[])

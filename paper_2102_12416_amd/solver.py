@@ -34,6 +34,7 @@ class Solver:
     def __init__(self, grid, block_dims=None, cuts=None, mode="staged", with_source=False,
                  tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None,
                  tile_x=0, exchange="device", temporal=False, overlap=False):
+        # temporal: False, True (two sweeps per launch), or 2 / 3 sweeps per launch
         self.grid = tuple(int(v) for v in grid)
         self.device = torch.device(device)
         self.opt = L.Options()
@@ -50,6 +51,7 @@ class Solver:
         self.opt.z_chunk = int(z_chunk)
         self.opt.use_graphs = int(bool(use_graphs))
         self.opt.temporal = int(bool(temporal))
+        self.opt.sweeps_per_launch = 3 if temporal == 3 else 0
         self.opt.overlap = int(bool(overlap))
         self.with_source = bool(with_source)
         self._ctx = ctypes.c_void_p()
@@ -231,7 +233,7 @@ class Solver:
     def temporal_info(self):
         out = (ctypes.c_int64 * 3)()
         check(L.lib.jc_temporal_info(self._ctx, out))
-        return dict(temporal=bool(out[0]), rows=out[1], z_chunk=out[2])
+        return dict(temporal=bool(out[0]), sweeps=int(out[0]), rows=out[1], z_chunk=out[2])
 
     def arena_view(self, byte_off, count, dtype=torch.float64):
         """A tensor view of `count` elements of the arena at `byte_off` (tests)."""
@@ -313,6 +315,7 @@ class Group:
     time) instead of a torch-allocated buffer."""
 
     def __init__(self, solvers, use_graphs=True, stream=None, tile=None, temporal=False, static_scratch=False):
+        # temporal: False, True (two sweeps of every member per launch) or 3
         self.solvers = list(solvers)
         dev = self.solvers[0].device
         self.device = dev
@@ -320,7 +323,7 @@ class Group:
         arr = (ctypes.c_void_p * len(self.solvers))(*[s._ctx.value for s in self.solvers])
         self._g = ctypes.c_void_p()
         tl = None if tile is None else (ctypes.c_int * 3)(*[int(v) for v in tile])
-        flags = (1 if use_graphs else 0) | (2 if temporal else 0)
+        flags = (1 if use_graphs else 0) | (4 if temporal == 3 else 2 if temporal else 0)
         check(L.lib.jc_group_create(arr, len(self.solvers), ctypes.c_void_p(_stream_handle(self.stream)),
                                     flags, tl, ctypes.byref(self._g)))
         fp = ctypes.c_size_t()

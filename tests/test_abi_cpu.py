@@ -325,6 +325,35 @@ def test_overlap_option_validation():
     L.lib.jc_destroy(ctx)
 
 
+def test_three_sweeps_per_launch_options():
+    opt = L.Options()
+    opt.ir_dtype = L.JC_NONE
+    ctx = ctypes.c_void_p()
+    opt.sweeps_per_launch = 3
+    assert L.lib.jc_create(L.i64((40, 30, 20)), L.i64((40, 30, 20)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID                       # needs temporal
+    opt.temporal = 1
+    opt.sweeps_per_launch = 4
+    assert L.lib.jc_create(L.i64((40, 30, 20)), L.i64((40, 30, 20)), ctypes.byref(opt), ctypes.byref(ctx)) == \
+        L.JC_ERR_INVALID
+    opt.sweeps_per_launch = 3
+    check(L.lib.jc_create(L.i64((40, 30, 20)), L.i64((40, 30, 20)), ctypes.byref(opt), ctypes.byref(ctx)))
+    out = (ctypes.c_int64 * 3)()
+    check(L.lib.jc_temporal_info(ctx, out))
+    assert out[0] == 3 and out[1] == 16
+    assert L.lib.jc_set_temporal_tiles(ctx, 24, 8) == L.JC_ERR_INVALID   # 8 or 16 rows for three
+    check(L.lib.jc_set_temporal_tiles(ctx, 8, 5))
+    check(L.lib.jc_temporal_info(ctx, out))
+    assert tuple(out) == (3, 8, 5)
+    L.lib.jc_destroy(ctx)
+    opt.sweeps_per_launch = 0
+    check(L.lib.jc_create(L.i64((40, 30, 20)), L.i64((40, 30, 20)), ctypes.byref(opt), ctypes.byref(ctx)))
+    check(L.lib.jc_temporal_info(ctx, out))
+    assert out[0] == 2
+    check(L.lib.jc_set_temporal_tiles(ctx, 24, 8))
+    L.lib.jc_destroy(ctx)
+
+
 def test_sixteen_cell_tile_options():
     st, ctx = create((40, 24, 24), (40, 24, 24), tile_x=16, tile_y=4)
     assert st == L.JC_ERR_INVALID
@@ -351,15 +380,15 @@ def test_temporal_tile_shape():
     st, ctx = create((40, 24, 100), (40, 24, 100), temporal=1, z_chunk=16)
     assert st == 0
     check(L.lib.jc_temporal_info(ctx, out))
-    assert tuple(out) == (1, 16, 8)               # 2 tiles per plane: chunks halved to 8 planes
+    assert tuple(out) == (2, 16, 8)               # 2 tiles per plane: chunks halved to 8 planes
     st2, big = create((1024, 1024, 1024), (1024, 1024, 1024), temporal=1, z_chunk=512)
     assert st2 == 0
     check(L.lib.jc_temporal_info(big, out))
-    assert tuple(out) == (1, 16, 512)             # 1024 tiles per plane x 2 chunks: kept
+    assert tuple(out) == (2, 16, 512)             # 1024 tiles per plane x 2 chunks: kept
     L.lib.jc_destroy(big)
     check(L.lib.jc_set_temporal_tiles(ctx, 24, 7))
     check(L.lib.jc_temporal_info(ctx, out))
-    assert tuple(out) == (1, 24, 7)
+    assert tuple(out) == (2, 24, 7)
     assert L.lib.jc_set_temporal_tiles(ctx, 12, 7) == L.JC_ERR_INVALID
     check(L.lib.jc_set_temporal_tiles(ctx, 8, 7))
     assert L.lib.jc_set_temporal_tiles(ctx, 16, 0) == L.JC_ERR_INVALID
