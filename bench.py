@@ -838,9 +838,10 @@ def main():
             print("[bench] autotuned tile_x=%d tile_y=%d z_chunk=%d (%.1f us per sweep)" % tuned, file=sys.stderr,
                   flush=True)
     pace = None
-    if not temporal:
-        # the pace of the one-sweep launch, for the shape just set: tuned at
-        # start-up (it depends on the device as much as on the shape)
+    if True:
+        # the pace of the timed launch (the one-sweep launch, or the multi-
+        # sweep launch of a temporal context), for the shape just set: tuned
+        # at start-up (it depends on the device as much as on the shape)
         if args.pace >= 0:
             s.set_pace(args.pace)
             pace = {"ticks": s.pace, "source": "given"}

@@ -393,20 +393,21 @@ int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
  * context. */
 int jc_autotune(jc_ctx* ctx, int reps, int64_t out[4]);
 
-/* Pace of the context's one-sweep launches (the sweep its solve loop runs:
- * the plain sweep, or the inner sweep on a context with refinement
- * buffers).  The work-groups of a launch advance at different rates and
+/* Pace of the launch the context's solve loop runs: the one-sweep launch
+ * (the plain sweep, or the inner sweep on a context with refinement
+ * buffers), or on a temporal context its two- or three-sweep launch (whose
+ * other launches then run unpaced).  The work-groups of a launch advance at different rates and
  * the launch lasts as long as the slowest, so the compute units of the
  * fast ones idle at its end.  With a pace of p ticks of the GPU's constant
  * 100 MHz clock, a work-group that reaches plane step k of its tile before
  * k * p ticks have passed since it started waits (a bounded sleep) until
  * then: the fast work-groups are held to a common rate and all finish
  * together.  Results are bitwise independent of the pace; 0 = none
- * (default).  0 <= ticks <= 10000, else JC_ERR_INVALID.  jc_set_tiles
- * resets the pace to 0 (a pace belongs to a tile shape). */
+ * (default).  0 <= ticks <= 10000, else JC_ERR_INVALID.  jc_set_tiles and
+ * jc_set_temporal_tiles reset the pace to 0 (a pace belongs to a shape). */
 int jc_set_pace(jc_ctx* ctx, int64_t ticks);
 int64_t jc_get_pace(const jc_ctx* ctx);
-/* Time the context's solve-loop sweep, in its current tile shape, with no
+/* Time the context's solve-loop launch, in its current shape, with no
  * pace and with paces of 90, 91, .. 98 % of its measured time per plane step
  * (only where the launch runs its work-groups in one or two rounds on the
  * device's compute units; otherwise the pace stays 0), `reps` sweeps each

@@ -506,7 +506,7 @@ int do_sweep(jc_ctx* c, bool fused, bool resid)
     int st = timed(c, fused ? JC_K_FUSED : JC_K_SWEEP, [&] {
         return jc::launch_sweep(c->d_blocks(), c->d_items(), (int)c->items.size(), c->parity, c->tile_x, c->tile_y,
                                 fused, resid, true, c->opt.with_source != 0, c->d_partials(), c->stream,
-                                c->opt.ir_enable ? 0u : c->pace);
+                                c->opt.ir_enable || c->opt.temporal ? 0u : c->pace);
     });
     if (st != JC_OK)
         return st;
@@ -538,35 +538,49 @@ int two_step_chunk(const jc_ctx* c)
     return (int)zc;
 }
 
-hipError_t launch_two_step(jc_ctx* c, int rows, int zc)
+// The pace of a temporal context belongs to its deepest launch (the one its
+// solve loop runs); the other launches run unpaced.
+uint32_t multi_pace(const jc_ctx* c, int depth) { return c->depth() == depth ? c->pace : 0u; }
+
+hipError_t launch_two_step(jc_ctx* c, int rows, int zc, uint32_t pace)
 {
     const HostBlock& b = c->blocks[0];
     return jc::launch_sweep2(c->d_blocks(), (int)b.n[0], (int)b.n[1], (int)b.n[2], c->parity, rows, zc,
-                             c->opt.with_source != 0, c->stream);
+                             c->opt.with_source != 0, c->stream, pace);
 }
+hipError_t launch_two_step(jc_ctx* c, int rows, int zc) { return launch_two_step(c, rows, zc, multi_pace(c, 2)); }
 
 // Two inner sweeps of the refinement correction in one launch (copy
 // qparity -> qparity ^ 1).
-hipError_t launch_ir_two_step(jc_ctx* c, int qparity, int rows, int zc)
+hipError_t launch_ir_two_step(jc_ctx* c, int qparity, int rows, int zc, uint32_t pace)
 {
     const HostBlock& b = c->blocks[0];
     return jc::launch_ir_inner2(c->d_blocks(), (int)b.n[0], (int)b.n[1], (int)b.n[2], qparity, rows, zc,
-                                c->opt.ir_dtype, c->stream);
+                                c->opt.ir_dtype, c->stream, pace);
+}
+hipError_t launch_ir_two_step(jc_ctx* c, int qparity, int rows, int zc)
+{
+    return launch_ir_two_step(c, qparity, rows, zc, multi_pace(c, 2));
 }
 
 // Three sweeps in one launch (temporal blocking, three per launch).
-hipError_t launch_three_step(jc_ctx* c, int rows, int zc)
+hipError_t launch_three_step(jc_ctx* c, int rows, int zc, uint32_t pace)
 {
     const HostBlock& b = c->blocks[0];
     return jc::launch_sweep3(c->d_blocks(), nullptr, 0, (int)b.n[0], (int)b.n[1], (int)b.n[2], c->parity, rows, zc,
-                             c->opt.with_source != 0, c->stream);
+                             c->opt.with_source != 0, c->stream, pace);
 }
+hipError_t launch_three_step(jc_ctx* c, int rows, int zc) { return launch_three_step(c, rows, zc, multi_pace(c, 3)); }
 
-hipError_t launch_ir_three_step(jc_ctx* c, int qparity, int rows, int zc)
+hipError_t launch_ir_three_step(jc_ctx* c, int qparity, int rows, int zc, uint32_t pace)
 {
     const HostBlock& b = c->blocks[0];
     return jc::launch_ir_inner3(c->d_blocks(), nullptr, 0, (int)b.n[0], (int)b.n[1], (int)b.n[2], qparity, rows, zc,
-                                c->opt.ir_dtype, c->stream);
+                                c->opt.ir_dtype, c->stream, pace);
+}
+hipError_t launch_ir_three_step(jc_ctx* c, int qparity, int rows, int zc)
+{
+    return launch_ir_three_step(c, qparity, rows, zc, multi_pace(c, 3));
 }
 
 // Launches that run n sweeps at depth d (sweeps per launch): n / d full
@@ -884,8 +898,8 @@ int tune_two_step(jc_ctx* c, int reps)
     const bool ir = c->opt.ir_enable != 0;
     auto launch = [&](const Cand& k) {
         if (three)
-            return ir ? launch_ir_three_step(c, 1, k.rows, k.zc) : launch_three_step(c, k.rows, k.zc);
-        return ir ? launch_ir_two_step(c, 1, k.rows, k.zc) : launch_two_step(c, k.rows, k.zc);
+            return ir ? launch_ir_three_step(c, 1, k.rows, k.zc, 0) : launch_three_step(c, k.rows, k.zc, 0);
+        return ir ? launch_ir_two_step(c, 1, k.rows, k.zc, 0) : launch_two_step(c, k.rows, k.zc, 0);
     };
     // milliseconds of n launches after one untimed launch
     auto time_one = [&](const Cand& k, int n, double& ms) -> int {
@@ -927,6 +941,7 @@ int tune_two_step(jc_ctx* c, int reps)
     const Cand best = *std::min_element(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
     c->t2_rows = best.rows;
     c->t2_zc = best.zc;
+    c->pace = 0;
     free_graphs(c);
     return JC_OK;
 }
@@ -1460,7 +1475,7 @@ int jc_solve_ir(jc_ctx* c, int inner_sweeps, double rtol, int64_t max_inner, jc_
             for (; j < m && s2 == JC_OK; ++j) {
                 s2 = timed(c, JC_K_IR_INNER, [&] {
                     return jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)c->items.size(), qq, c->tile_x,
-                                               c->tile_y, lo, c->stream, c->pace);
+                                               c->tile_y, lo, c->stream, c->opt.temporal ? 0u : c->pace);
                 });
                 qq ^= 1;
             }
@@ -1551,6 +1566,7 @@ int jc_set_temporal_tiles(jc_ctx* c, int rows, int z_chunk)
         return fail(JC_ERR_INVALID, "z_chunk must be >= 1");
     c->t2_rows = rows;
     c->t2_zc = z_chunk;
+    c->pace = 0;                           // a pace belongs to a shape
     free_graphs(c);                        // graphs hold the old launch shapes
     return JC_OK;
 }
@@ -1601,7 +1617,15 @@ int tune_pace(jc_ctx* c, int reps, double warm_ms, int64_t out[3])
     int64_t zmax = 0;
     for (const Item& it : c->items)
         zmax = std::max<int64_t>(zmax, it.zlen);
-    const int64_t nit = (int64_t)c->items.size();
+    int64_t nit = (int64_t)c->items.size();
+    const int depth = c->depth();
+    if (depth > 1) {
+        // the multi-sweep launch of a one-block temporal context
+        const HostBlock& b = c->blocks[0];
+        const int zc = two_step_chunk(c);
+        zmax = zc;
+        nit = ((b.n[0] + 63) / 64) * ((b.n[1] + c->t2_rows - 1) / c->t2_rows) * ((b.n[2] + zc - 1) / zc);
+    }
     const int64_t rounds = ncu > 0 ? (nit + ncu - 1) / ncu : 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     JC_HIP(hipEventCreate(&e0));
@@ -1615,6 +1639,11 @@ int tune_pace(jc_ctx* c, int reps, double warm_ms, int64_t out[3])
     // and write the other copy and face slot: the iterate is unchanged
     auto time_at = [&](uint32_t pace, int n, double& ms) -> int {
         auto one = [&]() -> hipError_t {
+            const int zc = two_step_chunk(c);
+            if (depth == 3)
+                return ir ? launch_ir_three_step(c, 1, c->t2_rows, zc, pace) : launch_three_step(c, c->t2_rows, zc, pace);
+            if (depth == 2)
+                return ir ? launch_ir_two_step(c, 1, c->t2_rows, zc, pace) : launch_two_step(c, c->t2_rows, zc, pace);
             return ir ? jc::launch_ir_inner(c->d_blocks(), c->d_items(), (int)nit, 1, c->tile_x, c->tile_y,
                                             c->opt.ir_dtype, c->stream, pace)
                       : jc::launch_sweep(c->d_blocks(), c->d_items(), (int)nit, c->parity, c->tile_x, c->tile_y,
@@ -1839,12 +1868,16 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
                                          [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
     st = jc_set_tiles(c, best.x, best.y, best.z);
     int64_t pace_out[3] = {0, 0, 0};
-    if (st == JC_OK)
+    if (st == JC_OK && !c->opt.temporal)
         st = tune_pace(c, reps, 0.0, pace_out);
     if (st == JC_OK && c->opt.temporal) {
         c->timing = false;
         st = tune_two_step(c, std::max(reps, 2));
         c->timing = was_timing;
+        // then the pace of the multi-sweep launch, for the shape just kept
+        if (st == JC_OK)
+            st = tune_pace(c, std::max(reps, 2), 0.0, pace_out);
+        pace_out[0] = 0;                   // out[3] reports the one-sweep launch
     }
     if (st != JC_OK)
         return st;

@@ -25,7 +25,7 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 // launch (binary64): iterate k from copy parity, iterate k + 2 into copy
 // parity ^ 1.  Tiles of 64 cells by tile_y (8, 16 or 24) rows by z_chunk planes.
 hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
-                         bool src, hipStream_t s);
+                         bool src, hipStream_t s, uint32_t pace = 0);
 // The same over a work list of 64-cell by tile_y-row tiles of several
 // one-block contexts (groups): each item's block, its copy parity ^ flip.
 hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
@@ -34,7 +34,7 @@ hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int n
 // qparity -> qparity ^ 1, source r_lo; tile_y 8, 16 or 24): iterate k + 1 is
 // rounded to the storage format between the two sweeps.
 hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int qparity, int tile_y, int z_chunk,
-                            int lo_dtype, hipStream_t s);
+                            int lo_dtype, hipStream_t s, uint32_t pace = 0);
 // The same over a work list of 64-cell by 16-row tiles (groups; each
 // item's flip must be 0: a refining member holds its iterate in copy 0).
 hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,
@@ -45,10 +45,10 @@ hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, in
 // chunks of z_chunk planes; otherwise the work list items[0 .. nitems) of
 // such tiles (groups), each with its block and flip.
 hipError_t launch_sweep3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz, int parity,
-                         int tile_y, int z_chunk, bool src, hipStream_t s);
+                         int tile_y, int z_chunk, bool src, hipStream_t s, uint32_t pace = 0);
 // The same for the refinement correction (copy qparity -> qparity ^ 1).
 hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz,
-                            int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s);
+                            int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s, uint32_t pace = 0);
 
 // Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
 // of d and r_lo).  Residual: r of u[parity] with fused ghosts (face

@@ -662,7 +662,7 @@ template <> __device__ __forceinline__ float storage_round<bf16>(float v) { retu
 template <typename T, int FIELD, int TXP, int TY, bool SRC>
 __global__ void __launch_bounds__(((TXP + 2) * (TY + 4) + 63) / 64 * 64)
 k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int tiles_x,
-         int tiles_y, int nch, int ntiles)
+         int tiles_y, int nch, int ntiles, uint32_t pace)
 {
     using C = typename Tr<T>::C;
     using F = Fld<T, FIELD>;
@@ -678,6 +678,7 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= ntiles)
         return;                                   // uniform over the work-group
+    const uint64_t pace_t0 = pace ? __builtin_amdgcn_s_memrealtime() : 0;
     const BlockDesc* B = blocks;
     int p = parity, x0, y0, zf, zl;
     if (items) {
@@ -762,12 +763,15 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
             Tr<T>::ld(scol + zk, ba[k], bb[k]);
     }
 
+    const int s_first = zf - 1;
     auto step = [&](int s, auto kc, auto two) {
         constexpr int K = decltype(kc)::value;
         constexpr bool TWO = decltype(two)::value;
         constexpr int SM = (K + RS - 1) % RS, SC = K, SP = (K + 1) % RS, SQ = (K + PD) % RS;
         constexpr int VC = K % 3, VM = (K + 2) % 3, VMM = (K + 1) % 3;
         constexpr int HC = K & 1;
+        if (pace)
+            pace_wait(pace_t0 + (uint64_t)(s - s_first) * pace);
         const int64_t zq = (int64_t)min(s + PD, zhi) * plane;
         Tr<T>::ld(col + zq, ua[SQ], ub[SQ]);
         if (SRC)
@@ -877,7 +881,7 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
 template <typename T, int FIELD, int TXP, int TY, bool SRC>
 __global__ void __launch_bounds__(((TXP + 4) * (TY + 6) + 63) / 64 * 64)
 k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int tiles_x,
-         int tiles_y, int nch, int ntiles)
+         int tiles_y, int nch, int ntiles, uint32_t pace)
 {
     using C = typename Tr<T>::C;
     using F = Fld<T, FIELD>;
@@ -895,6 +899,7 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= ntiles)
         return;                                   // uniform over the work-group
+    const uint64_t pace_t0 = pace ? __builtin_amdgcn_s_memrealtime() : 0;
     const BlockDesc* B = blocks;
     int p = parity, x0, y0, zf, zl;
     if (items) {
@@ -990,6 +995,7 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     }
 
     // STAGES: 1 = iterate k + 1 only, 2 = also k + 2, 3 = also k + 3
+    const int s_first = zf - 2;
     auto step = [&](int s, auto kc, auto stages) {
         constexpr int K = decltype(kc)::value;
         constexpr int ST = decltype(stages)::value;
@@ -997,6 +1003,8 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
         constexpr int S2 = (K + RS - 2) % RS;     // plane s - 2
         constexpr int VC = K % 3, VM = (K + 2) % 3, VMM = (K + 1) % 3;
         constexpr int HC = K & 1;
+        if (pace)
+            pace_wait(pace_t0 + (uint64_t)(s - s_first) * pace);
         const int64_t zq = (int64_t)min(s + PD, zhi) * plane;
         Tr<T>::ld(col + zq, ua[SQ], ub[SQ]);
         if (SRC)
@@ -1373,7 +1381,7 @@ hipError_t launch_sweep(const BlockDesc* blocks, const Item* items, int nitems, 
 }
 
 hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int parity, int tile_y, int z_chunk,
-                         bool src, hipStream_t s)
+                         bool src, hipStream_t s, uint32_t pace)
 {
     if (nx < 1 || ny < 1 || nz < 1 || z_chunk < 1)
         return hipErrorInvalidValue;
@@ -1385,7 +1393,7 @@ hipError_t launch_sweep2(const BlockDesc* blocks, int nx, int ny, int nz, int pa
 #define JC_SWEEP2_CASE(TY, SRC)                                                                               \
     if (tile_y == TY && src == SRC) {                                                                        \
         hipLaunchKernelGGL((k_sweep2<double, FIELD_U, 32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), \
-                           0, s, blocks, nullptr, parity, (int)tx, (int)ty, (int)nch, (int)n);               \
+                           0, s, blocks, nullptr, parity, (int)tx, (int)ty, (int)nch, (int)n, pace);         \
         return hipGetLastError();                                                                            \
     }
     JC_SWEEP2_CASE(8, false)
@@ -1407,7 +1415,7 @@ hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int n
 #define JC_SWEEP2_ITEMS_CASE(TY, SRC)                                                                          \
     if (tile_y == TY && src == SRC) {                                                                         \
         hipLaunchKernelGGL((k_sweep2<double, FIELD_U, 32, TY, SRC>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), \
-                           0, s, blocks, items, parity, 0, 0, 0, nitems);                                     \
+                           0, s, blocks, items, parity, 0, 0, 0, nitems, 0u);                                 \
         return hipGetLastError();                                                                             \
     }
     JC_SWEEP2_ITEMS_CASE(8, false)
@@ -1425,27 +1433,27 @@ hipError_t launch_sweep2_items(const BlockDesc* blocks, const Item* items, int n
 // 16) rows; items null: the tiles of blocks[0] in z chunks of z_chunk planes.
 template <typename T, int FIELD, int TY, bool SRC>
 hipError_t sweep3_launch(const BlockDesc* blocks, const Item* items, int parity, int tx, int ty, int nch, int n,
-                         hipStream_t s)
+                         hipStream_t s, uint32_t pace)
 {
     const int grid = ((n + 7) / 8) * 8;
     hipLaunchKernelGGL((k_sweep3<T, FIELD, 32, TY, SRC>), dim3(grid), dim3((36 * (TY + 6) + 63) / 64 * 64), 0, s,
-                       blocks, items, parity, tx, ty, nch, n);
+                       blocks, items, parity, tx, ty, nch, n, pace);
     return hipGetLastError();
 }
 
 template <typename T, int FIELD, bool SRC>
 hipError_t sweep3_rows(const BlockDesc* blocks, const Item* items, int parity, int tile_y, int tx, int ty, int nch,
-                       int n, hipStream_t s)
+                       int n, hipStream_t s, uint32_t pace)
 {
     if (tile_y == 8)
-        return sweep3_launch<T, FIELD, 8, SRC>(blocks, items, parity, tx, ty, nch, n, s);
+        return sweep3_launch<T, FIELD, 8, SRC>(blocks, items, parity, tx, ty, nch, n, s, pace);
     if (tile_y == 16)
-        return sweep3_launch<T, FIELD, 16, SRC>(blocks, items, parity, tx, ty, nch, n, s);
+        return sweep3_launch<T, FIELD, 16, SRC>(blocks, items, parity, tx, ty, nch, n, s, pace);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz, int parity,
-                         int tile_y, int z_chunk, bool src, hipStream_t s)
+                         int tile_y, int z_chunk, bool src, hipStream_t s, uint32_t pace)
 {
     int64_t tx = 0, ty = 0, nch = 0, n = nitems;
     if (!items) {
@@ -1460,13 +1468,14 @@ hipError_t launch_sweep3(const BlockDesc* blocks, const Item* items, int nitems,
         return hipSuccess;
     if (n > ((int64_t)1 << 30))
         return hipErrorInvalidValue;
-    return src ? sweep3_rows<double, FIELD_U, true>(blocks, items, parity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s)
+    return src ? sweep3_rows<double, FIELD_U, true>(blocks, items, parity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s,
+                                                    pace)
                : sweep3_rows<double, FIELD_U, false>(blocks, items, parity, tile_y, (int)tx, (int)ty, (int)nch, (int)n,
-                                                     s);
+                                                     s, pace);
 }
 
 hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz,
-                            int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s)
+                            int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s, uint32_t pace)
 {
     int64_t tx = 0, ty = 0, nch = 0, n = nitems;
     if (!items) {
@@ -1482,9 +1491,9 @@ hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nite
     if (n > ((int64_t)1 << 30))
         return hipErrorInvalidValue;
     switch (lo_dtype) {
-    case 0: return sweep3_rows<double, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s);
-    case 1: return sweep3_rows<float, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s);
-    case 2: return sweep3_rows<bf16, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s);
+    case 0: return sweep3_rows<double, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s, pace);
+    case 1: return sweep3_rows<float, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s, pace);
+    case 2: return sweep3_rows<bf16, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s, pace);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1498,7 +1507,7 @@ hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, in
 #define JC_IR2_ITEMS_CASE(TY, DT, T)                                                                            \
     if (tile_y == TY && lo_dtype == DT) {                                                                      \
         hipLaunchKernelGGL((k_sweep2<T, FIELD_D, 32, TY, true>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, \
-                           s, blocks, items, qparity, 0, 0, 0, nitems);                                        \
+                           s, blocks, items, qparity, 0, 0, 0, nitems, 0u);                                    \
         return hipGetLastError();                                                                              \
     }
     JC_IR2_ITEMS_CASE(16, 0, double)
@@ -1509,7 +1518,7 @@ hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, in
 }
 
 hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int qparity, int tile_y, int z_chunk,
-                            int lo_dtype, hipStream_t s)
+                            int lo_dtype, hipStream_t s, uint32_t pace)
 {
     if (nx < 1 || ny < 1 || nz < 1 || z_chunk < 1)
         return hipErrorInvalidValue;
@@ -1521,7 +1530,7 @@ hipError_t launch_ir_inner2(const BlockDesc* blocks, int nx, int ny, int nz, int
 #define JC_IR2_CASE(TY, DT, T)                                                                                  \
     if (tile_y == TY && lo_dtype == DT) {                                                                      \
         hipLaunchKernelGGL((k_sweep2<T, FIELD_D, 32, TY, true>), dim3(grid), dim3((34 * (TY + 4) + 63) / 64 * 64), 0, \
-                           s, blocks, nullptr, qparity, (int)tx, (int)ty, (int)nch, (int)n);                   \
+                           s, blocks, nullptr, qparity, (int)tx, (int)ty, (int)nch, (int)n, pace);             \
         return hipGetLastError();                                                                              \
     }
     JC_IR2_CASE(8, 0, double)

@@ -217,3 +217,31 @@ def test_three_sweep_server_same_results():
         assert (a.id, a.iters, a.converged) == (b.id, b.iters, b.converged)
         assert a.rel_resid == b.rel_resid
         assert np.array_equal(a.field, b.field)
+
+
+@pytest.mark.parametrize("temporal", [True, 3])
+def test_paced_multi_sweep_launches_bitwise(temporal):
+    """A pace on the two- or three-sweep launch of a temporal context (set,
+    then tuned) only delays work-groups: iterates and refinement results
+    stay bitwise the oracle's."""
+    n = (130, 50, 97)
+    say("paced multi-sweep", temporal)
+    u0 = synth.boundary_field(n, seed=17)
+    b = synth.source_field(n, seed=17)
+    ref, _ = oracle.c_jacobi(u0, 14, b)
+    with Solver(n, with_source=True, temporal=temporal, use_graphs=False) as s:
+        s.load(u0, b)
+        s.set_pace(60)
+        assert s.pace == 60
+        s.iterate(7)
+        p, us_paced, us_free = s.autotune_pace(reps=3)
+        assert s.pace == p and us_paced > 0 and us_free > 0
+        s.iterate(7)
+        assert np.array_equal(s.store().cpu().numpy(), ref)
+    ref_ir, _, done, _ = oracle.c_ir_solve(u0, b, storage="bf16", inner=20, rtol=0.0, max_inner=47)
+    with Solver(n, with_source=True, ir_dtype="bf16", temporal=temporal) as s:
+        s.load(u0, b)
+        s.set_pace(80)
+        info = s.solve_ir(inner=20, rtol=0.0, max_inner=47)
+        assert info["iters"] == done
+        assert np.array_equal(s.store().cpu().numpy(), ref_ir)
