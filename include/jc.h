@@ -311,6 +311,16 @@ int jc_group_iterate(jc_group* g, int64_t n);
  * outer step of refining members; waits for the stream.  JC_ERR_NONFINITE
  * if any norm is NaN/Inf (all norms are still written). */
 int jc_group_residuals(jc_group* g, double* host_l2);
+/* The stopping rule of independent solves in a group (serving): the
+ * residual norms of jc_group_residuals, then for every member
+ * host_rel[m] = |r| / |r_0| with |r_0| the norm this call saw first for the
+ * member's current solve (kept in the context across groups; reset by
+ * jc_load_field(U); 0 when |r_0| = 0), and host_done[m] = 1 when
+ * host_rel[m] <= rtol or the member has run max_iter sweeps (iterations
+ * since its load), else 0.  A member whose norm is NaN or infinite is not
+ * done by the test and makes the call return JC_ERR_NONFINITE (all outputs
+ * still written).  Waits for the stream. */
+int jc_group_check(jc_group* g, double rtol, int64_t max_iter, double* host_rel, int* host_done);
 /* Frees the group's host data, graphs and events (waits for its stream).
  * NULL-safe.  The scratch stays the caller's. */
 void jc_group_destroy(jc_group* g);

@@ -87,6 +87,8 @@ SIGNATURES = {
     "jc_group_footprint": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_size_t)]),
     "jc_group_bind": (ctypes.c_int, [VP, VP, ctypes.c_size_t]),
     "jc_group_bind_static": (ctypes.c_int, [VP]),
+    "jc_group_check": (ctypes.c_int, [VP, ctypes.c_double, I64, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int)]),
     "jc_set_pace": (ctypes.c_int, [CTX, I64]),
     "jc_get_pace": (I64, [CTX]),
     "jc_autotune_pace": (ctypes.c_int, [CTX, ctypes.c_int, I64P]),

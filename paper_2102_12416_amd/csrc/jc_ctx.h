@@ -132,6 +132,9 @@ struct jc_ctx {
     // pace of the one-sweep launches of the solve loop (jc_set_pace): ticks
     // of the 100 MHz constant clock per plane step; 0 = none
     uint32_t pace = 0;
+    // |r_0| of the current solve as first seen by jc_group_check (-1: none
+    // yet); reset by jc_load_field(U)
+    double check_r0 = -1.0;
     // sweeps per launch of the solve loop: 1, or 2 / 3 with temporal blocking
     int depth() const { return !opt.temporal ? 1 : opt.sweeps_per_launch == 3 ? 3 : 2; }
     // boundary-first iterations (options.overlap): the work list holds the

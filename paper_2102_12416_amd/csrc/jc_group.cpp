@@ -672,6 +672,27 @@ int jc_group_residuals(jc_group* g, double* host_l2)
     return JC_OK;
 }
 
+int jc_group_check(jc_group* g, double rtol, int64_t max_iter, double* host_rel, int* host_done)
+{
+    if (!g || !host_rel || !host_done)
+        return fail(JC_ERR_INVALID, "bad group or output");
+    if (!std::isfinite(rtol) || max_iter < 0)
+        return fail(JC_ERR_INVALID, "rtol must be finite and max_iter >= 0");
+    const int nm = (int)g->members.size();
+    std::vector<double> l2(nm, 0.0);
+    const int st = jc_group_residuals(g, l2.data());
+    if (st != JC_OK && st != JC_ERR_NONFINITE)
+        return st;
+    for (int m = 0; m < nm; ++m) {
+        jc_ctx* c = g->members[m];
+        if (c->check_r0 < 0)
+            c->check_r0 = l2[m];
+        host_rel[m] = c->check_r0 > 0 ? l2[m] / c->check_r0 : 0.0;
+        host_done[m] = (host_rel[m] <= rtol || c->iters >= max_iter) ? 1 : 0;
+    }
+    return st;
+}
+
 void jc_group_destroy(jc_group* g)
 {
     if (!g)

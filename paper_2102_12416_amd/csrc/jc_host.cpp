@@ -1199,6 +1199,7 @@ int jc_load_field(jc_ctx* c, int which, const void* src)
                               which, c->stream));
     if (which == JC_FIELD_U) {
         c->loaded_u = true;
+        c->check_r0 = -1.0;
         c->parity = 0;
         c->iters = 0;
         c->ghost = GHOST_CURRENT;     // the scatter filled every ghost with iterate 0

@@ -91,7 +91,6 @@ class _Live:
     solver: Solver
     res: Result
     bytes: int
-    r0: float = -1.0
 
 
 class _Lane:
@@ -205,15 +204,13 @@ class Server:
             lane.pending = []
         if lane.group is None or lane.key != tuple(l.req.id for l in lane.active):
             self._regroup(lane)
-        norms = lane.group.residuals()
+        # the stopping rule runs in the library: |r| / |r_0| <= rtol or the cap
+        checks = lane.group.check(self.rtol, self.max_iter)
         now = clock()
         freed = 0
         keep = []
-        for live, r in zip(lane.active, norms):
-            if live.r0 < 0:
-                live.r0 = r
-            rel = r / live.r0 if live.r0 > 0 else 0.0
-            if rel <= self.rtol or live.solver.iterations >= self.max_iter:
+        for live, (rel, stop) in zip(lane.active, checks):
+            if stop:
                 self._retire(live, now, rel)
                 freed += live.bytes
                 done.append(live.res)

@@ -351,6 +351,14 @@ class Group:
         check(L.lib.jc_group_residuals(self._g, out))
         return list(out)
 
+    def check(self, rtol, max_iter):
+        """The stopping rule of every member (jc_group_check): a list of
+        (relative residual, done) pairs."""
+        rel = (ctypes.c_double * len(self.solvers))()
+        done = (ctypes.c_int * len(self.solvers))()
+        check(L.lib.jc_group_check(self._g, float(rtol), int(max_iter), rel, done))
+        return [(rel[i], bool(done[i])) for i in range(len(self.solvers))]
+
     def close(self):
         if self._g:
             L.lib.jc_group_destroy(self._g)

@@ -130,3 +130,38 @@ def test_requests_joining_mid_solve_same_as_alone(how):
             ref, _, done, st = oracle.c_ir_solve(u0, b, storage="f32", inner=50, rtol=1e-10, max_inner=max_iter)
             assert done == m.iters and (st == 0) == m.converged, r.id
         assert np.array_equal(m.field, ref), r.id
+
+
+def test_group_check_is_the_stopping_rule():
+    """jc_group_check: relative residual against the first norm it saw for
+    the member's current solve (kept across groups, reset by a load), and
+    the stop flag for the tolerance or the sweep cap."""
+    from paper_2102_12416_amd import Group, Solver
+    say("group check")
+    specs = [(20, "f64"), (16, "f32"), (24, "f64")]
+    solvers = []
+    for i, (n, p) in enumerate(specs):
+        s = Solver((n, n, n), mode="fused", with_source=True, ir_dtype="f32" if p == "f32" else None)
+        s.load(synth.boundary_field((n, n, n), seed=80 + i), synth.source_field((n, n, n), seed=80 + i))
+        solvers.append(s)
+    with Group(solvers) as g:
+        first = g.check(1e-10, 10 ** 6)
+        assert all(rel == 1.0 and not done for rel, done in first)
+        g.iterate(50)
+        chk = g.check(1e-10, 10 ** 6)
+        assert all(0.0 < rel < 1.0 and not done for rel, done in chk)
+        # a tolerance above the relative residual stops; the cap stops
+        assert all(done for _, done in g.check(2.0, 10 ** 6))
+        assert all(done for _, done in g.check(1e-300, 50))
+    # r0 is kept across groups: a new group sees the same relative residual
+    with Group(solvers[:2]) as g2:
+        again = g2.check(1e-10, 10 ** 6)
+        for (r1, _), (r2, _) in zip(chk[:2], again):
+            assert r1 == r2
+    # a load starts a new solve: its first check is 1 again
+    n0 = specs[0][0]
+    solvers[0].load(synth.boundary_field((n0,) * 3, seed=80), synth.source_field((n0,) * 3, seed=80))
+    with Group(solvers[:2]) as g3:
+        assert g3.check(1e-10, 10 ** 6)[0] == (1.0, False)
+    for s in solvers:
+        s.close()
