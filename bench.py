@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--settle-ms", type=float, default=250.0,
+                    help="sustained sweeps (in ms of wall time) after set-up and before the warm-up steps: the device "
+                         "runs launches slower for tens of ms after tuning and graph capture left it idle")
     ap.add_argument("--workload", default="512_2x2x2",
                     choices=sorted(WORKLOADS) + ["refine", "serve", "768_grids", "batch"])
     ap.add_argument("--batch-grids", type=int, default=64, help="batch: independent grids solved to 1e-10")
@@ -854,13 +857,23 @@ def main():
         print("[bench] pace %s" % pace, file=sys.stderr, flush=True)
     tiles = s.tile_info()
     if graphs:
-        # capture the timed window's graph outside the timed region (both
-        # start parities when the window is odd)
+        # capture the timed window's and the warm-up's graphs outside the
+        # timed region (both start parities when a window is odd)
+        for n in (args.steps, args.warmup):
+            if n > 0:
+                s.iterate(n)
+                if n % 2:
+                    s.iterate(n)
+    # set-up (tuning, capture) leaves the device idle or lightly loaded, and
+    # the next launches then run slower until it has swept for tens of ms (the
+    # first 20-iteration window after 5 warm-up steps measured 2 % slow): the
+    # settle phase sweeps for a fixed wall time, then the warm-up steps run
+    # last, right before the timed window
+    settle_iters, t_settle = 0, time.perf_counter()
+    while args.settle_ms > 0 and (time.perf_counter() - t_settle) * 1e3 < args.settle_ms:
         s.iterate(args.steps)
-        if args.steps % 2:
-            s.iterate(args.steps)
-    # the warm-up steps run last, right before the timed window: an idle
-    # device slows the next launches (a 20 ms gap measured 6 % slower)
+        settle_iters += args.steps
+        s.synchronize()
     s.iterate(args.warmup)
     s.synchronize()
 
@@ -930,6 +943,8 @@ def main():
                    "sweeps_per_launch": depth,
                    "temporal_tile": t2_shape,
                    "pace": pace,
+                   "settle": {"iterations": settle_iters, "ms": args.settle_ms,
+                              "note": "untimed sweeps after set-up, before the warm-up steps"},
                    "tile_source": tile_source,
                    "launch": "hipGraph replay of the timed window" if graphs else "eager, HIP events per launch",
                    "boundary": "U[0,1) SplitMix64 seed %d, interior 0, no source" % args.seed},
