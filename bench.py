@@ -54,9 +54,9 @@ PAPER_COMM_SPEEDUPS = {
 }
 
 TUNED_TILES = {
-    ("512_2x2x2", "fused"): (64, 32, 256),
-    ("512_2x2x2", "staged"): (64, 32, 64),
-    ("768_8x8x8", "fused"): (32, 32, 16),
+    ("512_2x2x2", "fused"): (256, 8, 256),
+    ("512_2x2x2", "staged"): (256, 8, 128),
+    ("768_8x8x8", "fused"): (96, 16, 16),
     ("768_uneven", "fused"): (32, 16, 16),
 }
 

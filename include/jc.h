@@ -95,8 +95,11 @@ typedef struct jc_options {
     int z_chunk;         /* planes per tile; 0 = auto */
     int use_graphs;      /* 1: capture jc_iterate windows as HIP graphs */
     int debug_epochs;    /* reserved, must be 0 */
-    int tile_x;          /* cells per tile row: 16, 32 or 64 (16 needs tile_y >= 8 or
-                            auto); 0 = auto (64, or 32 where it idles fewer lanes) */
+    int tile_x;          /* cells per tile row: 16, 32, 64, or 96, 128, 256 (binary64
+                            storage only: not with an ir_dtype of JC_F32 / JC_BF16);
+                            tile_x / 2 x tile_y is 64 to 1024 threads (16 needs
+                            tile_y >= 8, 256 tile_y <= 8 or auto); 0 = auto (64, or
+                            32 where it idles fewer lanes) */
     int exchange;        /* JC_EXCHANGE_DEVICE (default), _HOST or _METADATA */
     int temporal;        /* 1: temporal blocking -- jc_iterate, the windows of jc_solve
                             and the inner sweeps of jc_solve_ir advance two sweeps per
@@ -270,8 +273,8 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * results bitwise the same as one sweep per launch); bit 2 = three sweeps
  * per launch (the same conditions and tiles; a count that is not a
  * multiple of three ends with a two-sweep launch or a single sweep).
- * tile: {cells per row 16|32|64,
- * rows 4|8|16|32 (at least 8 for 16-cell rows), planes >= 1} for every
+ * tile: {cells per row 16|32|64 (or 96|128|256 when no member refines in
+ * binary32 or bfloat16), rows 4|8|16|32 (64 to 1024 threads), planes >= 1} for every
  * launch of the group, or NULL for {64, 8, 32}; members' results do not
  * depend on it, their residual norms do in the last bits, so compare
  * mixes within one tile shape.  Host only until jc_group_bind. */
@@ -361,9 +364,12 @@ int jc_synth_field(void* dev_global_padded, const int64_t grid[3], uint64_t seed
 
 /* ---- tile shape ------------------------------------------------------ */
 
-/* Set the sweep's tile shape: tile_x cells per row (16, 32 or 64), tile_y
- * rows (4, 8, 16 or 32; at least 8 with 16-cell rows, so that a work-group
- * is whole 64-lane waves) and z_chunk planes per work item (>= 1, within
+/* Set the sweep's tile shape: tile_x cells per row (16, 32 or 64; or 96,
+ * 128 or 256 -- a whole block row -- where the swept storage is binary64,
+ * i.e. not on a context refining in binary32 or bfloat16), tile_y rows (4,
+ * 8, 16 or 32), with tile_x / 2 x tile_y between 64 and 1024 threads, so
+ * that a work-group is whole 64-lane waves (16-cell rows need 8 rows or
+ * more, 256-cell rows 8 or fewer), and z_chunk planes per work item (>= 1, within
  * the work-list region sized at creation: >= 16 always fits).  Results
  * are bitwise independent of the shape; residual norms change in the last
  * bits (reduction order).  Uploads the new work list (waits for the stream
@@ -383,7 +389,9 @@ int jc_set_temporal_tiles(jc_ctx* ctx, int rows, int z_chunk);
 int jc_temporal_info(const jc_ctx* ctx, int64_t out[3]);
 
 /* Time `reps` sweeps of every valid candidate shape (tile_x in {64, 32,
- * 16} x tile_y in {4, 8, 16, 32} x z_chunk in {16, 32, 64, ..., depth}) on
+ * 16}, and 96, 128 or 256 where the storage is binary64 and they leave at
+ * most 1/8 of the lanes idle, x tile_y in {4, 8, 16, 32} x z_chunk in {16,
+ * 32, 64, ..., depth}) on
  * the bound stream after at least 150 ms of warm-up sweeps, time the four
  * fastest again in turn over three rounds and keep the fastest of those;
  * out = {tile_x, tile_y, z_chunk, microseconds per sweep}.  The sweep timed

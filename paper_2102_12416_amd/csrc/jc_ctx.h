@@ -70,19 +70,24 @@ inline void z_chunk_range(int64_t nz, int64_t zc, int64_t k, int64_t* z0, int64_
 // Bytes of one element of the refinement storage format.
 inline size_t lo_size(int dtype) { return dtype == JC_F64 ? 8 : dtype == JC_F32 ? 4 : 2; }
 
-constexpr int kTileXCandidates[] = {64, 32, 16};
+constexpr int kTileXCandidates[] = {64, 32, 16, 96, 128, 256};
 constexpr int kTileYCandidates[] = {4, 8, 16, 32};
+constexpr int kNarrowTileMax = 64;
 
-// A tile is 16, 32 or 64 cells wide (two per thread) and 4..32 rows; a
-// work-group is whole 64-lane waves, so a 16-cell tile needs 8 rows.
-inline bool tile_shape_ok(int tile_x, int tile_y)
+// A tile is 16, 32, 64, 96, 128 or 256 cells wide (two per thread) and
+// 4..32 rows; a work-group is whole 64-lane waves and at most 1024 threads
+// (a 16-cell tile needs 8 rows, a 256-cell tile at most 8).  Tiles wider
+// than 64 cells sweep binary64 storage only: `narrow` is set when the
+// swept storage is binary32 or bfloat16 (the refinement's correction).
+inline bool tile_shape_ok(int tile_x, int tile_y, bool narrow = false)
 {
     bool ok_x = false, ok_y = false;
     for (int x : kTileXCandidates)
         ok_x = ok_x || x == tile_x;
     for (int y : kTileYCandidates)
         ok_y = ok_y || y == tile_y;
-    return ok_x && ok_y && (tile_x / 2) * tile_y >= 64;
+    const int threads = (tile_x / 2) * tile_y;
+    return ok_x && ok_y && threads >= 64 && threads <= 1024 && (!narrow || tile_x <= kNarrowTileMax);
 }
 constexpr int kMinZChunk = 16;
 // largest pace (ticks of the 100 MHz clock per plane step): each wait of a
@@ -207,6 +212,10 @@ struct jc_ctx {
 
 
 namespace jc_rt {
+
+// The context sweeps binary32 or bfloat16 storage (the refinement's
+// correction): its tiles are at most 64 cells wide.
+inline bool narrow_storage(const jc_ctx* c) { return c->opt.ir_enable && c->opt.ir_dtype != JC_F64; }
 
 hipEvent_t take_event(jc_ctx* c);
 int drain_timing(jc_ctx* c);

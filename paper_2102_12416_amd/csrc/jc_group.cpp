@@ -286,9 +286,13 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             return fail(JC_ERR_INVALID, "two or three sweeps per launch (flag 2 or 4) needs members of one block");
     }
     if (tile) {
-        const bool ok = jc_rt::tile_shape_ok(tile[0], tile[1]) && tile[2] >= 1;
+        bool narrow = false;
+        for (int i = 0; i < n; ++i)
+            narrow = narrow || jc_rt::narrow_storage(ctxs[i]);
+        const bool ok = jc_rt::tile_shape_ok(tile[0], tile[1], narrow) && tile[2] >= 1;
         if (!ok)
-            return fail(JC_ERR_INVALID, "group tile must be {16|32|64, 4|8|16|32 (>= 8 for 16), >= 1}");
+            return fail(JC_ERR_INVALID, "group tile must be {16|32|64|96|128|256 (above 64 only without binary32 "
+                                        "or bfloat16 members), 4|8|16|32, >= 1} with 64 to 1024 threads");
     }
     jc_group* g = new (std::nothrow) jc_group();
     if (!g)

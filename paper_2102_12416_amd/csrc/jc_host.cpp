@@ -138,17 +138,15 @@ int validate_options(const jc_options* opt)
         return fail(JC_ERR_INVALID, "host-staged or metadata exchange needs the staged mode");
     if (opt->debug_epochs != 0)
         return fail(JC_ERR_INVALID, "options.debug_epochs is reserved and must be 0");
-    if (opt->tile_x != 0 && opt->tile_x != 16 && opt->tile_x != 32 && opt->tile_x != 64)
-        return fail(JC_ERR_INVALID, "options.tile_x must be 0, 16, 32 or 64");
-    if (opt->tile_x == 16 && opt->tile_y == 4)
-        return fail(JC_ERR_INVALID, "a 16-cell tile needs options.tile_y of 8, 16 or 32 (whole waves)");
-    if (opt->tile_y != 0) {
-        bool ok = false;
-        for (int t : kTileYCandidates)
-            ok = ok || t == opt->tile_y;
-        if (!ok)
-            return fail(JC_ERR_INVALID, "options.tile_y must be 0, 4, 8, 16 or 32");
-    }
+    if (opt->tile_x != 0 && !tile_shape_ok(opt->tile_x, 8))
+        return fail(JC_ERR_INVALID, "options.tile_x must be 0, 16, 32, 64, 96, 128 or 256");
+    if (opt->tile_y != 0 && !tile_shape_ok(64, opt->tile_y))
+        return fail(JC_ERR_INVALID, "options.tile_y must be 0, 4, 8, 16 or 32");
+    if (opt->tile_x != 0 && opt->tile_y != 0 && !tile_shape_ok(opt->tile_x, opt->tile_y))
+        return fail(JC_ERR_INVALID, "options.tile_x / 2 x options.tile_y must be 64 to 1024 threads (a 16-cell "
+                                    "tile needs 8 rows or more, a 256-cell tile 8 or fewer)");
+    if (opt->tile_x > kNarrowTileMax && opt->ir_enable && opt->ir_dtype != JC_F64)
+        return fail(JC_ERR_INVALID, "tiles wider than 64 cells need binary64 storage (options.ir_dtype JC_F64)");
     if (opt->z_chunk < 0)
         return fail(JC_ERR_INVALID, "options.z_chunk must be >= 0");
     if (opt->temporal != 0 && opt->temporal != 1)
@@ -1533,9 +1531,10 @@ int jc_set_tiles(jc_ctx* c, int tile_x, int tile_y, int z_chunk)
 {
     if (!c)
         return fail(JC_ERR_INVALID, "NULL context");
-    if (!tile_shape_ok(tile_x, tile_y) || z_chunk < 1)
-        return fail(JC_ERR_INVALID, "tile_x must be 16, 32 or 64, tile_y 4, 8, 16 or 32 (at least 8 for "
-                                    "tile_x 16) and z_chunk >= 1");
+    if (!tile_shape_ok(tile_x, tile_y, narrow_storage(c)) || z_chunk < 1)
+        return fail(JC_ERR_INVALID, "tile_x must be 16, 32, 64, 96, 128 or 256 (above 64 for binary64 storage "
+                                    "only), tile_y 4, 8, 16 or 32, tile_x / 2 x tile_y 64 to 1024 threads, and "
+                                    "z_chunk >= 1");
     if (items_for(c, tile_x, tile_y, z_chunk) > c->max_items)
         return fail(JC_ERR_INVALID, "z_chunk too small for the work-list region");
     c->tile_x = tile_x;
@@ -1789,11 +1788,19 @@ int jc_autotune(jc_ctx* c, int reps, int64_t out[4])
         double ms;
     };
     std::vector<Shape> cand;
-    for (int xw : kTileXCandidates)
+    int64_t cells = 0;
+    for (const HostBlock& b : c->blocks)
+        cells += b.n[0] * b.n[1] * b.n[2];
+    for (int xw : kTileXCandidates) {
+        // a tile wider than 64 cells is a candidate where it leaves at most
+        // 1/8 of its lanes idle (rows that fill it)
+        if (xw > kNarrowTileMax && idle_cells(c, xw) * 8 > cells)
+            continue;
         for (int t : kTileYCandidates)
             for (int z : zcs)
-                if (tile_shape_ok(xw, t) && items_for(c, xw, t, z) <= c->max_items)
+                if (tile_shape_ok(xw, t, narrow_storage(c)) && items_for(c, xw, t, z) <= c->max_items)
                     cand.push_back({xw, t, z, 0.0});
+    }
     if (cand.empty())
         return fail(JC_ERR_INVALID, "no tile shape fits the work-list region");
 

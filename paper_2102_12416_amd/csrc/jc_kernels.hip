@@ -234,8 +234,8 @@ __device__ __forceinline__ void pace_wait(uint64_t due)
 // registers would cost a resident work-group.
 template <typename T> constexpr int prefetch_planes() { return sizeof(T) == 8 ? 3 : 2; }
 
-// One work-group sweeps a tile of 2 TXP x cells (64, 32 or 16) by TY rows of
-// one block, marching along z.  Each thread owns two adjacent x cells of one row
+// One work-group sweeps a tile of 2 TXP x cells (16, 32 or 64; or 96, 128 or
+// 256 for binary64 storage) by TY rows of one block, marching along z.  Each thread owns two adjacent x cells of one row
 // (one aligned-pair load per plane: cell x = 1 of every row starts a
 // 128-byte line).  Per plane the work-group writes the plane -- its cells
 // plus a one-cell halo ring -- into an LDS tile, synchronises once (the
@@ -593,6 +593,7 @@ template <typename T, int FIELD, int TXP, bool SRC, typename R>
 hipError_t sweep_rows(const BlockDesc* blocks, const Item* items, int nitems, int parity, int tile_y,
                       bool fused, bool resid, bool store, double* partials, hipStream_t s, uint32_t pace)
 {
+    // at most 1024 threads per work-group
     switch (tile_y) {
     case 4:
         // a 16-cell tile needs 8 rows for whole waves
@@ -600,9 +601,21 @@ hipError_t sweep_rows(const BlockDesc* blocks, const Item* items, int nitems, in
             return sweep_flags<T, FIELD, TXP, 4, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
         else
             return hipErrorInvalidValue;
-    case 8: return sweep_flags<T, FIELD, TXP, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
-    case 16: return sweep_flags<T, FIELD, TXP, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
-    case 32: return sweep_flags<T, FIELD, TXP, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
+    case 8:
+        if constexpr (TXP * 8 <= 1024)
+            return sweep_flags<T, FIELD, TXP, 8, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
+        else
+            return hipErrorInvalidValue;
+    case 16:
+        if constexpr (TXP * 16 <= 1024)
+            return sweep_flags<T, FIELD, TXP, 16, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
+        else
+            return hipErrorInvalidValue;
+    case 32:
+        if constexpr (TXP * 32 <= 1024)
+            return sweep_flags<T, FIELD, TXP, 32, SRC, R>(blocks, items, nitems, parity, fused, resid, store, partials, s, pace);
+        else
+            return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -615,8 +628,20 @@ hipError_t sweep_tiles(const BlockDesc* blocks, const Item* items, int nitems, i
     case 16: return sweep_rows<T, FIELD, 8, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
     case 32: return sweep_rows<T, FIELD, 16, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
     case 64: return sweep_rows<T, FIELD, 32, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
-    default: return hipErrorInvalidValue;
+    default: break;
     }
+    // Tiles as wide as a whole block row of 96, 128 or 256 cells (binary64
+    // storage): the x halo is then the block's ghost column, never a
+    // neighbour tile's lines.
+    if constexpr (sizeof(T) == 8) {
+        switch (tile_x) {
+        case 96: return sweep_rows<T, FIELD, 48, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
+        case 128: return sweep_rows<T, FIELD, 64, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
+        case 256: return sweep_rows<T, FIELD, 128, SRC, R>(blocks, items, nitems, parity, tile_y, fused, resid, store, partials, s, pace);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---- sweep kernel: end ----

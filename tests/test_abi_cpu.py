@@ -36,7 +36,8 @@ def create(grid, bd, **kw):
     opt = L.Options()
     opt.mode = kw.get("mode", 0)
     opt.with_source = kw.get("with_source", 0)
-    opt.ir_dtype = L.JC_NONE
+    opt.ir_dtype = kw.get("ir_dtype", L.JC_NONE)
+    opt.ir_enable = kw.get("ir_enable", 0)
     opt.tile_y = kw.get("tile_y", 0)
     opt.z_chunk = kw.get("z_chunk", 0)
     opt.tile_x = kw.get("tile_x", 0)
@@ -283,6 +284,50 @@ def test_set_tiles_validation_and_items():
     check(L.lib.jc_tile_info(ctx, out))
     # the finest shapes the tuner may pick fit the work-list region
     assert tuple(out) == (16, 8, 16, 2 * 7 * 13 * 6)
+    L.lib.jc_destroy(ctx)
+
+
+def test_wide_tile_shapes():
+    # 96-, 128- and 256-cell rows: at most 1024 threads per work-group
+    st, ctx = create((200, 100, 96), (100, 100, 96))
+    assert st == 0
+    out = (ctypes.c_int64 * 4)()
+    check(L.lib.jc_set_tiles(ctx, 96, 16, 48))
+    check(L.lib.jc_tile_info(ctx, out))
+    # 2 blocks x ceil(100/96) x ceil(100/16) x ceil(96/48): a 4-cell tail tile per row
+    assert tuple(out) == (96, 16, 48, 2 * 2 * 7 * 2)
+    check(L.lib.jc_set_tiles(ctx, 256, 8, 96))
+    check(L.lib.jc_tile_info(ctx, out))
+    assert tuple(out) == (256, 8, 96, 2 * 1 * 13 * 1)
+    check(L.lib.jc_set_tiles(ctx, 128, 16, 32))
+    check(L.lib.jc_set_tiles(ctx, 256, 4, 32))
+    for shape in ((256, 16, 32), (96, 32, 16), (128, 32, 16), (192, 8, 16), (48, 8, 16)):
+        assert L.lib.jc_set_tiles(ctx, *shape) == L.JC_ERR_INVALID, shape
+    L.lib.jc_destroy(ctx)
+    # as options: the pair is checked when both are given
+    st, ctx = create((64, 64, 64), (64, 64, 64), tile_x=256, tile_y=16)
+    assert st == L.JC_ERR_INVALID and "1024" in L.last_error()
+    for tx in (96, 128, 256):
+        st, ctx = create((64, 64, 64), (64, 64, 64), tile_x=tx)
+        assert st == 0, tx
+        check(L.lib.jc_tile_info(ctx, out))
+        assert out[0] == tx and (tx // 2) * out[1] <= 1024
+        L.lib.jc_destroy(ctx)
+
+
+def test_wide_tiles_need_binary64_storage():
+    # the refinement's binary32 / bfloat16 correction is swept in tiles of at most 64 cells
+    for dt in (L.JC_F32, L.JC_BF16):
+        st, _ = create((64, 64, 64), (64, 64, 64), tile_x=96, ir_enable=1, ir_dtype=dt)
+        assert st == L.JC_ERR_INVALID and "binary64" in L.last_error()
+        st, ctx = create((64, 64, 64), (64, 64, 64), ir_enable=1, ir_dtype=dt)
+        assert st == 0
+        assert L.lib.jc_set_tiles(ctx, 128, 8, 32) == L.JC_ERR_INVALID
+        check(L.lib.jc_set_tiles(ctx, 64, 8, 32))
+        L.lib.jc_destroy(ctx)
+    st, ctx = create((64, 64, 64), (64, 64, 64), tile_x=128, ir_enable=1, ir_dtype=L.JC_F64)
+    assert st == 0
+    check(L.lib.jc_set_tiles(ctx, 256, 8, 32))
     L.lib.jc_destroy(ctx)
 
 
