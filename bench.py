@@ -411,14 +411,15 @@ def forms(args):
                                          "step of 50 inner sweeps (binary64 residual, update and norm included)",
                                   per_sweep=rates)
     print("[bench] forms: refinement per sweep %s" % json.dumps(rates), file=sys.stderr, flush=True)
-    # ---- time to 1e-10 at 128^3: binary64 vs the refined forms (two sweeps per launch)
+    # ---- time to 1e-10 at 128^3: binary64 vs the refined forms (two and three sweeps per launch)
     m = 128
     gm = (m, m, m)
     gg = synth_field(gm, args.seed, 0)
     bb = synth_field(gm, args.seed, 1)
     row = {}
     for tag, ir, temporal in (("f64", None, False), ("f64_temporal", None, True), ("f32_refined_temporal", "f32", True),
-                              ("bf16_refined_temporal", "bf16", True)):
+                              ("bf16_refined_temporal", "bf16", True), ("f64_three_sweeps", None, 3),
+                              ("f32_refined_three_sweeps", "f32", 3), ("bf16_refined_three_sweeps", "bf16", 3)):
         with Solver(gm, with_source=True, ir_dtype=ir, temporal=temporal) as s:
             s.load(gg, bb)
             s.autotune(reps=2)
@@ -430,7 +431,8 @@ def forms(args):
             u = s.store()
             if tag == "f64":
                 u64, scale = u, float(u.abs().max())
-            row[tag] = dict(seconds=round(sec, 3), sweeps=info["iters"], rel_resid=info["rel_resid"],
+            row[tag] = dict(seconds=round(sec, 3), sweeps_per_launch=3 if temporal == 3 else 2 if temporal else 1,
+                            sweeps=info["iters"], rel_resid=info["rel_resid"],
                             converged=info["converged"],
                             max_rel_err_vs_f64=float((u - u64).abs().max()) / scale)
     for tag in row:
@@ -448,7 +450,7 @@ def forms(args):
 
     def server(keep):
         return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter, lanes=(64, 160),
-                      temporal=True, keep_fields=keep)
+                      temporal=3, keep_fields=keep)
     t0 = time.perf_counter()
     cap = summarize(server(False).run(reqs(0.0), realtime=False), 1.0)
     cap_s = time.perf_counter() - t0
@@ -474,7 +476,7 @@ def forms(args):
     res["serving"] = dict(
         config=dict(requests=nreq, edges="log-uniform [32, %d]" % hi, precision="Bernoulli(0.5) f64 / f32-refined",
                     rtol=1e-10, max_iter=args.serve_max_iter, window=50, lanes=[64, 160],
-                    two_sweeps_per_launch=True, budget_gb=args.serve_budget_gb,
+                    sweeps_per_launch=3, budget_gb=args.serve_budget_gb,
                     rate_per_s=round(rate, 3), rate_source="0.7 x closed-loop capacity of the same requests"),
         solves_per_s=round(summ["solves_per_s"], 3), p50_s=round(summ["p50_s"], 4), p99_s=round(summ["p99_s"], 4),
         mean_s=round(summ["mean_s"], 4), converged=summ["converged"], capped=summ["capped"],
