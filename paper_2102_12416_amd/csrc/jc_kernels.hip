@@ -684,6 +684,11 @@ template <> __device__ __forceinline__ float storage_round<bf16>(float v) { retu
 // chunk, nch chunks, ntiles in all) numbered from the work-group index;
 // otherwise the work list items[0 .. ntiles), whose tiles must be 2 TXP
 // cells by TY rows, each with its block and ping-pong flip (groups).
+// A pair of arithmetic values as one LDS access (16 bytes in binary64).
+template <typename C> struct Pair2;
+template <> struct Pair2<double> { using V = v2d; };
+template <> struct Pair2<float> { using V = v2f; };
+
 template <typename T, int FIELD, int TXP, int TY, bool SRC>
 __global__ void __launch_bounds__(((TXP + 2) * (TY + 4) + 63) / 64 * 64)
 k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int tiles_x,
@@ -695,10 +700,14 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     constexpr int ER = TY + 4;                    // extended rows
     constexpr int NTILE = TXP * TY;               // tile threads
     static_assert(NTILE % 64 == 0, "tile threads are whole waves");
-    constexpr int LW = 2 * EP + 2;                // LDS row: pad, 2 EP cells, pad
+    using V = typename Pair2<C>::V;
+    // LDS row: two pad cells, 2 EP cells, two pad cells, so that every
+    // thread's pair is one aligned vector: a pair is written with one
+    // access and its neighbours' pairs are read with one access each
+    constexpr int LW = 2 * EP + 4;
     constexpr int LN = (ER + 2) * LW;             // LDS plane: pad row, ER rows, pad row
-    __shared__ C A[2][LN + 1];                    // iterate k; element LN: sink of idle lanes
-    __shared__ C Bn[2][LN + 1];                   // iterate k + 1
+    __shared__ V A[2][LN / 2 + 1];                // iterate k; pair LN / 2: sink of idle lanes
+    __shared__ V Bn[2][LN / 2 + 1];               // iterate k + 1
 
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= ntiles)
@@ -764,9 +773,8 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     const T* __restrict__ scol = SRC ? F::source(B) + rowoff : nullptr;
     T* __restrict__ dst = F::dst(B, p) + rowoff;
 
-    const int base = (r + 1) * LW + 2 * j + 1;    // LDS slot of cell xs
-    const int wa = live ? base : LN;
-    const int wb = live ? base + 1 : LN;
+    const int pn = (r + 1) * (LW / 2) + j + 1;    // LDS pair of cells xs, xs + 1
+    const int pw = live ? pn : LN / 2;            // the pair this thread writes
 
     // register rings: iterate k and the source of plane s in slot
     // (s - zf + 1) mod RS, loads issued PD planes ahead; iterate k + 1 of
@@ -801,19 +809,19 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
         Tr<T>::ld(col + zq, ua[SQ], ub[SQ]);
         if (SRC)
             Tr<T>::ld(scol + zq, ba[SQ], bb[SQ]);
-        C* const Ak = A[HC];
-        Ak[wa] = ua[SC];
-        Ak[wb] = ub[SC];
+        V* const Ak = A[HC];
+        Ak[pw] = V{ua[SC], ub[SC]};
         __syncthreads();
         // iterate k + 1 at plane s
-        C sa = Ak[base - 1] + ub[SC];
-        sa = sa + Ak[base - LW];
-        sa = sa + Ak[base + LW];
+        const V ym = Ak[pn - LW / 2], yp = Ak[pn + LW / 2], xm = Ak[pn - 1], xp = Ak[pn + 1];
+        C sa = xm.y + ub[SC];
+        sa = sa + ym.x;
+        sa = sa + yp.x;
         sa = sa + ua[SM];
         sa = sa + ua[SP];
-        C sb = ua[SC] + Ak[base + 2];
-        sb = sb + Ak[base + 1 - LW];
-        sb = sb + Ak[base + 1 + LW];
+        C sb = ua[SC] + xp.x;
+        sb = sb + ym.y;
+        sb = sb + yp.y;
         sb = sb + ub[SM];
         sb = sb + ub[SP];
         C na, nb;
@@ -824,19 +832,19 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
         const bool z_in = s >= 1 && s <= nz;
         va[VC] = (in_a && z_in) ? storage_round<T>(na) : ua[SC];
         vb[VC] = (in_b && z_in) ? storage_round<T>(nb) : ub[SC];
-        Bn[HC][wa] = va[VC];
-        Bn[HC][wb] = vb[VC];
+        Bn[HC][pw] = V{va[VC], vb[VC]};
         // iterate k + 2 at plane s - 1
         if (TWO && tile) {
-            const C* const Bk = Bn[HC ^ 1];
-            C qa = Bk[base - 1] + vb[VM];
-            qa = qa + Bk[base - LW];
-            qa = qa + Bk[base + LW];
+            const V* const Bk = Bn[HC ^ 1];
+            const V ym2 = Bk[pn - LW / 2], yp2 = Bk[pn + LW / 2], xm2 = Bk[pn - 1], xp2 = Bk[pn + 1];
+            C qa = xm2.y + vb[VM];
+            qa = qa + ym2.x;
+            qa = qa + yp2.x;
             qa = qa + va[VMM];
             qa = qa + va[VC];
-            C qb = va[VM] + Bk[base + 2];
-            qb = qb + Bk[base + 1 - LW];
-            qb = qb + Bk[base + 1 + LW];
+            C qb = va[VM] + xp2.x;
+            qb = qb + ym2.y;
+            qb = qb + yp2.y;
             qb = qb + vb[VMM];
             qb = qb + vb[VC];
             C wa2, wb2;
@@ -915,11 +923,15 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     constexpr int NTILE = TXP * TY;               // tile threads
     constexpr int NMID = NTILE + 2 * (TXP + 2) + 2 * TY;
     static_assert(NTILE % 64 == 0, "tile threads are whole waves");
-    constexpr int LW = 2 * EP + 2;                // LDS row: pad, 2 EP cells, pad
+    using V = typename Pair2<C>::V;
+    // LDS row: two pad cells, 2 EP cells, two pad cells, so that every
+    // thread's pair is one aligned vector: a pair is written with one
+    // access and its neighbours' pairs are read with one access each
+    constexpr int LW = 2 * EP + 4;
     constexpr int LN = (ER + 2) * LW;             // LDS plane: pad row, ER rows, pad row
-    __shared__ C A[2][LN + 1];                    // iterate k; element LN: sink of idle lanes
-    __shared__ C Bn[2][LN + 1];                   // iterate k + 1
-    __shared__ C Cn[2][LN + 1];                   // iterate k + 2
+    __shared__ V A[2][LN / 2 + 1];                // iterate k; pair LN / 2: sink of idle lanes
+    __shared__ V Bn[2][LN / 2 + 1];               // iterate k + 1
+    __shared__ V Cn[2][LN / 2 + 1];               // iterate k + 2
 
     const int id = logical_block(blockIdx.x, gridDim.x);
     if (id >= ntiles)
@@ -990,9 +1002,8 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     const T* __restrict__ scol = SRC ? F::source(B) + rowoff : nullptr;
     T* __restrict__ dst = F::dst(B, p) + rowoff;
 
-    const int base = (r + 1) * LW + 2 * j + 1;    // LDS slot of cell xs
-    const int wa = live ? base : LN;
-    const int wb = live ? base + 1 : LN;
+    const int pn = (r + 1) * (LW / 2) + j + 1;    // LDS pair of cells xs, xs + 1
+    const int pw = live ? pn : LN / 2;            // the pair this thread writes
 
     // register rings: iterate k and the source of plane s in slot
     // (s - zf + 2) mod RS, loads issued PD planes ahead; iterates k + 1 of
@@ -1034,20 +1045,20 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
         Tr<T>::ld(col + zq, ua[SQ], ub[SQ]);
         if (SRC)
             Tr<T>::ld(scol + zq, ba[SQ], bb[SQ]);
-        C* const Ak = A[HC];
-        Ak[wa] = ua[SC];
-        Ak[wb] = ub[SC];
+        V* const Ak = A[HC];
+        Ak[pw] = V{ua[SC], ub[SC]};
         __syncthreads();
         // iterate k + 1 at plane s
         {
-            C sa = Ak[base - 1] + ub[SC];
-            sa = sa + Ak[base - LW];
-            sa = sa + Ak[base + LW];
+            const V ym = Ak[pn - LW / 2], yp = Ak[pn + LW / 2], xm = Ak[pn - 1], xp = Ak[pn + 1];
+            C sa = xm.y + ub[SC];
+            sa = sa + ym.x;
+            sa = sa + yp.x;
             sa = sa + ua[SM];
             sa = sa + ua[SP];
-            C sb = ua[SC] + Ak[base + 2];
-            sb = sb + Ak[base + 1 - LW];
-            sb = sb + Ak[base + 1 + LW];
+            C sb = ua[SC] + xp.x;
+            sb = sb + ym.y;
+            sb = sb + yp.y;
             sb = sb + ub[SM];
             sb = sb + ub[SP];
             C na, nb;
@@ -1058,20 +1069,20 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
             const bool z_in = s >= 1 && s <= nz;
             va[VC] = (in_a && z_in) ? storage_round<T>(na) : ua[SC];
             vb[VC] = (in_b && z_in) ? storage_round<T>(nb) : ub[SC];
-            Bn[HC][wa] = va[VC];
-            Bn[HC][wb] = vb[VC];
+            Bn[HC][pw] = V{va[VC], vb[VC]};
         }
         // iterate k + 2 at plane s - 1
         if (ST >= 2 && mid) {
-            const C* const Bk = Bn[HC ^ 1];
-            C qa = Bk[base - 1] + vb[VM];
-            qa = qa + Bk[base - LW];
-            qa = qa + Bk[base + LW];
+            const V* const Bk = Bn[HC ^ 1];
+            const V ym = Bk[pn - LW / 2], yp = Bk[pn + LW / 2], xm = Bk[pn - 1], xp = Bk[pn + 1];
+            C qa = xm.y + vb[VM];
+            qa = qa + ym.x;
+            qa = qa + yp.x;
             qa = qa + va[VMM];
             qa = qa + va[VC];
-            C qb = va[VM] + Bk[base + 2];
-            qb = qb + Bk[base + 1 - LW];
-            qb = qb + Bk[base + 1 + LW];
+            C qb = va[VM] + xp.x;
+            qb = qb + ym.y;
+            qb = qb + yp.y;
             qb = qb + vb[VMM];
             qb = qb + vb[VC];
             C na, nb;
@@ -1082,20 +1093,20 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
             const bool z_in = s - 1 >= 1 && s - 1 <= nz;
             wa3[VC] = (in_a && z_in) ? storage_round<T>(na) : va[VM];
             wb3[VC] = (in_b && z_in) ? storage_round<T>(nb) : vb[VM];
-            Cn[HC][wa] = wa3[VC];
-            Cn[HC][wb] = wb3[VC];
+            Cn[HC][pw] = V{wa3[VC], wb3[VC]};
         }
         // iterate k + 3 at plane s - 2
         if (ST >= 3 && tile) {
-            const C* const Ck = Cn[HC ^ 1];
-            C qa = Ck[base - 1] + wb3[VM];
-            qa = qa + Ck[base - LW];
-            qa = qa + Ck[base + LW];
+            const V* const Ck = Cn[HC ^ 1];
+            const V ym = Ck[pn - LW / 2], yp = Ck[pn + LW / 2], xm = Ck[pn - 1], xp = Ck[pn + 1];
+            C qa = xm.y + wb3[VM];
+            qa = qa + ym.x;
+            qa = qa + yp.x;
             qa = qa + wa3[VMM];
             qa = qa + wa3[VC];
-            C qb = wa3[VM] + Ck[base + 2];
-            qb = qb + Ck[base + 1 - LW];
-            qb = qb + Ck[base + 1 + LW];
+            C qb = wa3[VM] + xp.x;
+            qb = qb + ym.y;
+            qb = qb + yp.y;
             qb = qb + wb3[VMM];
             qb = qb + wb3[VC];
             C oa, ob;
