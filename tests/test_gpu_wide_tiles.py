@@ -103,3 +103,35 @@ def test_wide_group_tile():
         Group([f32], tile=(96, 8, 16))
     assert e.value.code == L.JC_ERR_INVALID
     f32.close()
+
+
+@pytest.mark.parametrize("variant", ["overlap", "host", "metadata", "paced_fused", "paced_staged"])
+def test_wide_tiles_other_paths(variant):
+    """Wide tiles on the other iteration paths: boundary-first overlapped
+    staged iterations (boundary tiles found with the wide tile width), host-
+    staged and metadata exchanges, and paced launches (a pace that binds,
+    then the tuned one): bitwise the oracle's."""
+    n, bd = (200, 70, 66), (100, 35, 66)
+    say("wide tile", variant)
+    u0 = synth.boundary_field(n, seed=34)
+    b = synth.source_field(n, seed=34)
+    ref9, _ = oracle.c_jacobi(u0, 9, b)
+    ref18, _ = oracle.c_jacobi(u0, 18, b)
+    kw = dict(block_dims=bd, with_source=True, tile_x=128, tile_y=8, z_chunk=16)
+    if variant == "overlap":
+        kw.update(mode="staged", overlap=True)
+    elif variant in ("host", "metadata"):
+        kw.update(mode="staged", exchange=variant, use_graphs=False, tile_x=96)
+    else:
+        kw.update(mode=variant.split("_")[1])
+    with Solver(n, **kw) as s:
+        s.load(u0, b)
+        if variant.startswith("paced"):
+            s.set_pace(40)
+        s.iterate(9)
+        assert np.array_equal(s.store().cpu().numpy(), ref9)
+        if variant.startswith("paced"):
+            s.autotune_pace(reps=3)
+            assert np.array_equal(s.store().cpu().numpy(), ref9)
+        s.iterate(9)
+        assert np.array_equal(s.store().cpu().numpy(), ref18)
