@@ -909,8 +909,10 @@ k_sweep2(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
 // are double-buffered by step parity, so one barrier per step suffices.
 // Thread order: tile threads (whole waves), then the mid ring (rows y0 and
 // y0 + TY + 1 over pairs 1 .. TXP + 2, then pairs 1 and TXP + 2 of the tile
-// rows), then the outer ring (two rows above and below, then pairs 0 and
-// TXP + 3 of the middle rows).  Work as for k_sweep2 (items null: the
+// rows), then the rest of the two-cell ring (rows y0 - 1 and y0 + TY + 2
+// over pairs 1 .. TXP + 2), then the third ring (the outermost rows, then
+// pairs 0 and TXP + 3 of the other rows), whose iterate k + 1 is not
+// needed.  Work as for k_sweep2 (items null: the
 // tiles of blocks[0]; else a work list of 2 TXP x TY tiles).
 template <typename T, int FIELD, int TXP, int TY, bool SRC>
 __global__ void __launch_bounds__(((TXP + 4) * (TY + 6) + 63) / 64 * 64)
@@ -923,6 +925,7 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
     constexpr int ER = TY + 6;                    // extended rows
     constexpr int NTILE = TXP * TY;               // tile threads
     constexpr int NMID = NTILE + 2 * (TXP + 2) + 2 * TY;
+    constexpr int NL1 = NMID + 2 * (TXP + 2);
     static_assert(NTILE % 64 == 0, "tile threads are whole waves");
     using V = typename Pair2<C>::V;
     // LDS row: two pad cells, 2 EP cells, two pad cells, so that every
@@ -974,19 +977,26 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
         } else if ((q -= 2 * (TXP + 2)) < 2 * TY) {   // mid pairs of the tile rows
             j = (q & 1) ? TXP + 2 : 1;
             r = 3 + (q >> 1);
-        } else if ((q -= 2 * TY) < 4 * EP) {      // outer rows
+        } else if ((q -= 2 * TY) < 2 * (TXP + 2)) {   // second ring: rows 1 and ER - 2
+            j = 1 + q % (TXP + 2);
+            r = q < TXP + 2 ? 1 : ER - 2;
+        } else if ((q -= 2 * (TXP + 2)) < 2 * EP) {   // third ring: rows 0 and ER - 1
             j = q % EP;
-            const int k = q / EP;
-            r = k < 2 ? k : TY + 2 + k;
-        } else if ((q -= 4 * EP) < 2 * (TY + 2)) {    // outer pairs of the middle rows
+            r = q < EP ? 0 : ER - 1;
+        } else if ((q -= 2 * EP) < 2 * (ER - 2)) {    // third ring: pairs 0 and EP - 1
             j = (q & 1) ? EP - 1 : 0;
-            r = 2 + (q >> 1);
+            r = 1 + (q >> 1);
         } else {
             live = false;
         }
     }
     const bool tile = t < NTILE;                  // uniform over each wave
     const bool mid = t < NMID;
+    // Iterate k + 1 is needed on the tile and its two-cell ring only (the
+    // first NL1 threads); the third ring's threads come last and only load
+    // iterate k, so the waves holding none of the first NL1 threads skip the
+    // first stage (a wave-uniform branch)
+    const bool l1 = (t & ~63) < NL1;
     const int xs = x0 - 3 + 2 * j;                // cells xs, xs + 1 (xs odd, >= -3)
     const int ye = y0 - 2 + r;
     const int xs_c = min(xs, nx | 1);             // last pair holding a cell <= nx + 1
@@ -1050,7 +1060,7 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
         Ak[pw] = V{ua[SC], ub[SC]};
         __syncthreads();
         // iterate k + 1 at plane s
-        {
+        if (l1) {
             const V ym = Ak[pn - LW / 2], yp = Ak[pn + LW / 2], xm = Ak[pn - 1], xp = Ak[pn + 1];
             C sa = xm.y + ub[SC];
             sa = sa + ym.x;
