@@ -968,6 +968,9 @@ def main():
                                         "16 B per update" + (" + 16 B per exchanged face value (%d values)"
                                                              % halo_values if mode == "fused" else ""))},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in ktime.items() if v[1]},
+        "device": {"name": torch.cuda.get_device_name(0),
+                   "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", ""),
+                   "compute_units": torch.cuda.get_device_properties(0).multi_processor_count},
     }
     tr = out["roofline"]["traffic"]
     # counter-measured DRAM bytes (recorded for this kernel source) over the live launch time
