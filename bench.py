@@ -76,9 +76,13 @@ def parse():
                     help="sustained sweeps (in ms of wall time) after set-up and before the warm-up steps: the device "
                          "runs launches slower for tens of ms after tuning and graph capture left it idle")
     ap.add_argument("--workload", default="512_2x2x2",
-                    choices=sorted(WORKLOADS) + ["refine", "serve", "768_grids", "batch"])
+                    choices=sorted(WORKLOADS) + ["refine", "serve", "768_grids", "batch", "small"])
     ap.add_argument("--batch-grids", type=int, default=64, help="batch: independent grids solved to 1e-10")
     ap.add_argument("--batch-edge", type=int, default=64, help="batch: cubic edge of each grid")
+    ap.add_argument("--small-edges", type=int, nargs="*", default=[32, 24, 16],
+                    help="small: cubic edges solved to 1e-10 with each launch form")
+    ap.add_argument("--small-group-sizes", type=int, nargs="*", default=[256, 1024],
+                    help="small: group sizes of 32^3 members swept together")
     ap.add_argument("--ir-edge", type=int, default=1024, help="refine: grid edge of the per-sweep rates")
     ap.add_argument("--ir-sweeps", type=int, default=100, help="refine: sweeps timed per precision")
     ap.add_argument("--ir-tile", default="", help="refine: tile_x,tile_y,z_chunk of the refinement solvers "
@@ -649,6 +653,101 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_small(args):
+    """Small grids (binary64, with source) solved to 1e-10 with each launch
+    form: one, two and three sweeps per launch (graph-captured windows,
+    shapes tuned by jc_autotune), and resident sweeps (one launch per
+    window, the grid on chip).  Per form: time per sweep over a long
+    window (HIP events on the context's stream) and wall time to 1e-10
+    with a residual check every 50 sweeps; every form's final iterate is
+    compared with the one-sweep form's."""
+    import torch
+
+    from paper_2102_12416_amd import Solver, _lib as L, synth_field
+    forms_ = (("one_sweep", dict()), ("two_sweeps", dict(temporal=True)), ("three_sweeps", dict(temporal=3)),
+              ("resident", dict(resident=True)))
+    rows = {}
+    for m in args.small_edges:
+        gm = (m, m, m)
+        g = synth_field(gm, args.seed, 0)
+        b = synth_field(gm, args.seed, 1)
+        row, ref = {}, None
+        for tag, kw in forms_:
+            with Solver(gm, mode="fused", with_source=True, **kw) as s:
+                s.load(g, b)
+                if not kw.get("resident"):
+                    s.autotune(reps=2)
+                window = 3000
+                s.iterate(window)                 # warm-up (and graph capture)
+                s.stream.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s.stream)
+                s.iterate(window)
+                e1.record(s.stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / window
+                s.load(g, b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = s.solve(rtol=1e-10, max_iter=2000000, check_every=50)
+                sec = time.perf_counter() - t0
+                u = s.store()
+                if ref is None:
+                    ref = u
+                row[tag] = dict(us_per_sweep=round(ms * 1e3, 3), glups=round(m ** 3 / (ms * 1e-3) / 1e9, 3),
+                                seconds_to_1e10=round(sec, 4), sweeps=info["iters"], converged=info["converged"],
+                                bitwise_equal_one_sweep=bool(torch.equal(u, ref)))
+        rows[str(m)] = row
+        print("[bench] small %d^3: %s" % (m, json.dumps(row)), file=sys.stderr, flush=True)
+    # many small solves at once: a group of 32^3 members, each form's
+    # launches shared by all members (one work-group per member when resident)
+    from paper_2102_12416_amd import Group
+    m = 32
+    gm = (m, m, m)
+    batch = {}
+    for count in args.small_group_sizes:
+        stream = torch.cuda.Stream()
+        solvers = [Solver(gm, mode="fused", with_source=True, use_graphs=False, stream=stream)
+                   .load(synth_field(gm, args.seed + i, 0), synth_field(gm, args.seed + i, 1)) for i in range(count)]
+        row, ref = {}, None
+        for tag, kw in (("one_sweep", dict()), ("three_sweeps", dict(temporal=3)), ("resident", dict(resident=True))):
+            for i, s in enumerate(solvers):
+                s.load(synth_field(gm, args.seed + i, 0), synth_field(gm, args.seed + i, 1))
+            window = 300
+            with Group(solvers, use_graphs=True, stream=stream, **kw) as grp:
+                grp.iterate(window)               # warm-up and graph capture
+                grp.stream.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(grp.stream)
+                grp.iterate(window)
+                e1.record(grp.stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / window
+            u = solvers[count // 2].store()
+            if ref is None:
+                ref = u
+            row[tag] = dict(us_per_sweep=round(ms * 1e3, 2), glups=round(count * m ** 3 / (ms * 1e-3) / 1e9, 2),
+                            bitwise_equal_one_sweep=bool(torch.equal(u, ref)))
+        for s in solvers:
+            s.close()
+        del solvers
+        torch.cuda.empty_cache()
+        batch[str(count)] = row
+        print("[bench] small group of %d x 32^3: %s" % (count, json.dumps(row)), file=sys.stderr, flush=True)
+    first = rows[str(args.small_edges[0])]
+    best_other = min(first[t]["seconds_to_1e10"] for t in ("one_sweep", "two_sweeps", "three_sweeps"))
+    out = {"metric": "time to 1e-10 relative residual for a small grid: resident sweeps vs launches per sweep",
+           "value": round(best_other / first["resident"]["seconds_to_1e10"], 3),
+           "unit": "x (speedup of resident sweeps over the fastest launch form, first edge)", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "small", "edges": list(args.small_edges), "rtol": 1e-10, "check_every": 50,
+                      "mode": "fused, one block", "source": "U[-1,1) SplitMix64", "boundary": "U[0,1) SplitMix64"},
+           "forms": rows, "groups_of_32_cubed": batch}
+    print(json.dumps(out), flush=True)
+
+
 def bench_grids(args):
     """Many independent grids in one launch per iteration: 512 grids of
     96^3 (the 768^3 volume as separate solves, seeds seed + i), swept by a
@@ -790,6 +889,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "small":
+        bench_small(args)
         return
 
     import numpy as np

@@ -76,10 +76,11 @@ enum {
  * receive.  HOST and METADATA disable graph capture. */
 enum { JC_EXCHANGE_DEVICE = 0, JC_EXCHANGE_HOST = 1, JC_EXCHANGE_METADATA = 2 };
 /* kinds for jc_kernel_time (JC_K_SWEEP2 / JC_K_SWEEP3: the two- and
- * three-sweep launches of temporal blocking) */
+ * three-sweep launches of temporal blocking; JC_K_RESIDENT: the many-sweep
+ * launches of a resident context) */
 enum { JC_K_SWEEP = 0, JC_K_PACK = 1, JC_K_EXCHANGE = 2, JC_K_UNPACK = 3,
        JC_K_RESIDUAL = 4, JC_K_FUSED = 5, JC_K_IR_INNER = 6, JC_K_IR_OUTER = 7,
-       JC_K_SWEEP2 = 8, JC_K_SWEEP3 = 9, JC_K_COUNT = 10 };
+       JC_K_SWEEP2 = 8, JC_K_SWEEP3 = 9, JC_K_RESIDENT = 10, JC_K_COUNT = 11 };
 
 typedef struct jc_ctx jc_ctx;
 typedef struct jc_group jc_group;
@@ -124,6 +125,17 @@ typedef struct jc_options {
                             per three sweeps (tiles of 8 or 16 rows); a count that is
                             not a multiple of three ends with a two-sweep launch or a
                             single sweep.  Results bitwise the same. */
+    int resident;        /* 1: on-chip sweeps for a small grid -- jc_iterate and the windows
+                            of jc_solve run as one launch each, whatever their length: one
+                            work-group holds the block on chip (its iterate in registers, a
+                            plane and the ghost rings in LDS) and sweeps it that many times,
+                            so a solve costs one launch per residual check.  Needs a context
+                            of one block of at most 32 planes with (nx + 1) / 2 * ny <= 512
+                            (for instance 32^3, 64 x 16 x 32) whose LDS need fits 64 KiB, no
+                            refinement, temporal = 0 and overlap = 0; else JC_ERR_INVALID at
+                            creation.  Results bitwise equal to one-sweep launches.  After a
+                            window only the copy holding the iterate is defined (the other
+                            copy holds an older iterate).  0: off. */
 } jc_options;
 
 /* Result of a solve. */
@@ -272,7 +284,13 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * refinement step and the last of an odd count are single-sweep launches;
  * results bitwise the same as one sweep per launch); bit 2 = three sweeps
  * per launch (the same conditions and tiles; a count that is not a
- * multiple of three ends with a two-sweep launch or a single sweep).
+ * multiple of three ends with a two-sweep launch or a single sweep);
+ * bit 3 = resident sweeps: every jc_group_iterate window is one launch per
+ * class (two when members' plane counts differ in parity) with one
+ * work-group per member, which keeps its member's block on chip for the
+ * whole window (members as for options.resident: one block of at most 32
+ * planes, (nx + 1) / 2 * ny <= 512, LDS need within 64 KiB, no refinement;
+ * else JC_ERR_INVALID; not with bits 1 and 2; results bitwise the same).
  * tile: {cells per row 16|32|64 (or 96|128|256 when no member refines in
  * binary32 or bfloat16), rows 4|8|16|32 (64 to 1024 threads), planes >= 1} for every
  * launch of the group, or NULL for {64, 8, 32}; members' results do not

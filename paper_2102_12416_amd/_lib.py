@@ -27,7 +27,7 @@ JC_FIELD_U, JC_FIELD_B = 0, 1
 JC_MODE_STAGED, JC_MODE_FUSED = 0, 1
 JC_EXCHANGE_DEVICE, JC_EXCHANGE_HOST, JC_EXCHANGE_METADATA = 0, 1, 2
 (JC_K_SWEEP, JC_K_PACK, JC_K_EXCHANGE, JC_K_UNPACK, JC_K_RESIDUAL, JC_K_FUSED,
- JC_K_IR_INNER, JC_K_IR_OUTER, JC_K_SWEEP2, JC_K_SWEEP3) = range(10)
+ JC_K_IR_INNER, JC_K_IR_OUTER, JC_K_SWEEP2, JC_K_SWEEP3, JC_K_RESIDENT) = range(11)
 
 _NAMES = {JC_ERR_INVALID: "JC_ERR_INVALID", JC_ERR_NOMEM: "JC_ERR_NOMEM",
           JC_ERR_DEVICE: "JC_ERR_DEVICE", JC_ERR_STATE: "JC_ERR_STATE",
@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("ir_enable", ctypes.c_int), ("tile_y", ctypes.c_int), ("z_chunk", ctypes.c_int),
                 ("use_graphs", ctypes.c_int), ("debug_epochs", ctypes.c_int), ("tile_x", ctypes.c_int),
                 ("exchange", ctypes.c_int), ("temporal", ctypes.c_int), ("overlap", ctypes.c_int),
-                ("sweeps_per_launch", ctypes.c_int)]
+                ("sweeps_per_launch", ctypes.c_int), ("resident", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -40,6 +40,12 @@ struct Class {
     size_t item2_0 = 0;              // first joint two-sweep item
     std::vector<Item> items2;        // two-sweep tiles (groups that sweep twice per launch)
     std::vector<int> members;
+    // resident sweeps: one item per member, split by the parity of its
+    // plane count (the kernel's step schedule depends on it)
+    std::vector<Item> itemsr[2];
+    size_t itemr0[2] = {0, 0};       // first joint resident item of each split
+    int max_pairs[2] = {1, 1}, max_nz[2] = {1, 1};
+    int64_t lds[2] = {0, 0};
 };
 
 // Two-sweep tiles of a group: 64 cells by kGroupTwoStepRows rows, and at
@@ -59,9 +65,12 @@ struct jc_group {
     std::vector<Item> items2;           // joint two-sweep work list, class-major
     bool two_step = false;              // every launch sweeps every member twice (or three times)
     bool three_step = false;            // three sweeps of every member per launch
+    bool resident = false;              // every window one launch, one work-group per member
+    std::vector<Item> itemsr;           // joint resident items, class-major
     std::vector<int32_t> lohi;          // per member: joint item range
     std::vector<int> member_bstart;     // per member: first joint block
-    size_t off_desc = 0, off_items = 0, off_items2 = 0, off_partials = 0, off_lohi = 0, off_out = 0, footprint = 0;
+    size_t off_desc = 0, off_items = 0, off_items2 = 0, off_itemsr = 0, off_partials = 0, off_lohi = 0, off_out = 0,
+           footprint = 0;
     char* scratch = nullptr;
     bool bound = false;
     double* h_out = nullptr;            // pinned, one per member (or h_out_plain)
@@ -74,6 +83,7 @@ struct jc_group {
     BlockDesc* d_desc() const { return reinterpret_cast<BlockDesc*>(scratch + off_desc); }
     Item* d_items() const { return reinterpret_cast<Item*>(scratch + off_items); }
     Item* d_items2() const { return reinterpret_cast<Item*>(scratch + off_items2); }
+    Item* d_itemsr() const { return reinterpret_cast<Item*>(scratch + off_itemsr); }
     double* d_partials() const { return reinterpret_cast<double*>(scratch + off_partials); }
     int32_t* d_lohi() const { return reinterpret_cast<int32_t*>(scratch + off_lohi); }
     double* d_out() const { return reinterpret_cast<double*>(scratch + off_out); }
@@ -190,6 +200,23 @@ int group_sweep3(jc_group* g)
     return JC_OK;
 }
 
+// n sweeps of every member in one launch per class and plane-count parity
+// (resident groups).
+int group_resident(jc_group* g, int64_t n)
+{
+    for (const Class& k : g->classes)
+        for (int q = 0; q < 2; ++q) {
+            if (k.itemsr[q].empty())
+                continue;
+            const hipError_t e = jc::launch_resident(g->d_desc(), g->d_itemsr() + k.itemr0[q], (int)k.itemsr[q].size(),
+                                                     k.max_pairs[q], k.max_nz[q], (size_t)k.lds[q], q, g->parity,
+                                                     (int)n, k.src, g->stream);
+            if (e != hipSuccess)
+                return ghip(e, "group resident launch");
+        }
+    return JC_OK;
+}
+
 // Bookkeeping after one multi-sweep launch of `sweeps` sweeps: every
 // member advanced that many sweeps and its iterate (a refining member: its
 // correction) moved to the other copy once, as the launch parity did.
@@ -242,6 +269,16 @@ int group_run(jc_group* g, int64_t n)
 {
     int64_t i = 0;
     int st = JC_OK;
+    if (g->resident) {
+        for (; i < n && st == JC_OK;) {
+            const int64_t m = std::min<int64_t>(n - i, (int64_t)1 << 30);
+            st = group_resident(g, m);
+            if (st == JC_OK)
+                advance(g, m);
+            i += m;
+        }
+        return st;
+    }
     if (g->three_step)
         for (; i + 3 <= n && st == JC_OK; i += 3) {
             st = group_sweep3(g);
@@ -270,8 +307,10 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     *out = nullptr;
     if (!ctxs || n < 1)
         return fail(JC_ERR_INVALID, "a group needs at least one context");
-    if (flags & ~7)
+    if (flags & ~15)
         return fail(JC_ERR_INVALID, "unknown group flags");
+    if ((flags & 8) && (flags & 6))
+        return fail(JC_ERR_INVALID, "resident sweeps (flag 8) exclude flags 2 and 4");
     std::set<const jc_ctx*> seen;
     for (int i = 0; i < n; ++i) {
         jc_ctx* c = ctxs[i];
@@ -284,6 +323,11 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             return fail(JC_ERR_STATE, "a refining member must hold its iterate in copy 0");
         if ((flags & 6) && c->nb() != 1)
             return fail(JC_ERR_INVALID, "two or three sweeps per launch (flag 2 or 4) needs members of one block");
+        if ((flags & 8) && (c->opt.ir_enable || c->nb() != 1 ||
+                            !jc::resident_fits(c->blocks[0].n[0], c->blocks[0].n[1], c->blocks[0].n[2])))
+            return fail(JC_ERR_INVALID, "resident sweeps (flag 8) need members of one block of at most 32 planes "
+                                        "with (nx + 1) / 2 * ny <= 512 and an LDS need within 64 KiB, without "
+                                        "refinement");
     }
     if (tile) {
         bool narrow = false;
@@ -305,6 +349,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     g->use_graphs = (flags & 1) && g->stream != nullptr;
     g->two_step = (flags & 6) != 0;
     g->three_step = (flags & 4) != 0;
+    g->resident = (flags & 8) != 0;
     // classes, in a fixed order
     std::map<std::tuple<int, int, int>, int> cls;
     for (int i = 0; i < n; ++i) {
@@ -339,6 +384,19 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
                 const int t2[3] = {64, kGroupTwoStepRows, std::max(g->tile[2], jc_rt::kTwoStepMinZ)};
                 member_items(c, t2, (int)g->desc.size(), m, k.items2);
             }
+            if (g->resident) {
+                const int64_t* bn = c->blocks[0].n;
+                const int q = (int)(bn[2] & 1);
+                Item it{};
+                it.block = (int32_t)g->desc.size();
+                it.zlen = (int32_t)bn[2];
+                it.flip = c->parity;
+                it.owner = m;
+                k.itemsr[q].push_back(it);
+                k.max_pairs[q] = std::max<int>(k.max_pairs[q], (int)((bn[0] + 1) / 2 * bn[1]));
+                k.max_nz[q] = std::max<int>(k.max_nz[q], (int)bn[2]);
+                k.lds[q] = std::max(k.lds[q], jc::resident_lds_bytes(bn[0], bn[1], bn[2]));
+            }
             g->desc.insert(g->desc.end(), c->hdesc.begin(), c->hdesc.end());
             g->items.insert(g->items.end(), k.items.begin() + first, k.items.end());
             g->lohi[2 * m] = (int32_t)i0;
@@ -347,6 +405,10 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
         k.bend = (int)g->desc.size();
         k.item2_0 = g->items2.size();
         g->items2.insert(g->items2.end(), k.items2.begin(), k.items2.end());
+        for (int q = 0; q < 2; ++q) {
+            k.itemr0[q] = g->itemsr.size();
+            g->itemsr.insert(g->itemsr.end(), k.itemsr[q].begin(), k.itemsr[q].end());
+        }
     }
     if (g->desc.size() > 65535 || g->items.size() > ((size_t)1 << 30) || g->items2.size() > ((size_t)1 << 30)) {
         delete g;
@@ -356,6 +418,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
     g->off_desc = off; off = align_up(off + sizeof(BlockDesc) * g->desc.size(), kAlign);
     g->off_items = off; off = align_up(off + sizeof(Item) * g->items.size(), kAlign);
     g->off_items2 = off; off = align_up(off + sizeof(Item) * std::max<size_t>(1, g->items2.size()), kAlign);
+    g->off_itemsr = off; off = align_up(off + sizeof(Item) * std::max<size_t>(1, g->itemsr.size()), kAlign);
     g->off_partials = off; off = align_up(off + sizeof(double) * g->items.size(), kAlign);
     g->off_lohi = off; off = align_up(off + sizeof(int32_t) * g->lohi.size(), kAlign);
     g->off_out = off; off = align_up(off + sizeof(double) * n, kAlign);
@@ -419,6 +482,9 @@ int bind_common(jc_group* g, char* scratch, bool plain)
     if (st == JC_OK && !g->items2.empty())
         st = ghip(hipMemcpyAsync(g->d_items2(), g->items2.data(), sizeof(Item) * g->items2.size(),
                                  hipMemcpyHostToDevice, g->stream), "upload two-sweep items");
+    if (st == JC_OK && !g->itemsr.empty())
+        st = ghip(hipMemcpyAsync(g->d_itemsr(), g->itemsr.data(), sizeof(Item) * g->itemsr.size(),
+                                 hipMemcpyHostToDevice, g->stream), "upload resident items");
     if (st == JC_OK)
         st = ghip(hipMemcpyAsync(g->d_lohi(), g->lohi.data(), sizeof(int32_t) * g->lohi.size(),
                                  hipMemcpyHostToDevice, g->stream), "upload ranges");

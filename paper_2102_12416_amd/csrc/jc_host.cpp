@@ -161,6 +161,10 @@ int validate_options(const jc_options* opt)
         return fail(JC_ERR_INVALID, "options.overlap needs the staged mode with the device exchange");
     if (opt->ir_enable && opt->ir_dtype != JC_F64 && opt->ir_dtype != JC_F32 && opt->ir_dtype != JC_BF16)
         return fail(JC_ERR_INVALID, "options.ir_dtype must be JC_F64, JC_F32 or JC_BF16 when ir_enable is set");
+    if (opt->resident != 0 && opt->resident != 1)
+        return fail(JC_ERR_INVALID, "options.resident must be 0 or 1");
+    if (opt->resident && (opt->ir_enable || opt->temporal || opt->overlap))
+        return fail(JC_ERR_INVALID, "options.resident excludes refinement, temporal blocking and overlap");
     return JC_OK;
 }
 
@@ -253,6 +257,9 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         return fail(JC_ERR_INVALID, "too many blocks for one launch");
     if (c->opt.temporal && c->nb() != 1)
         return fail(JC_ERR_INVALID, "options.temporal needs a context of one block (no face pairs)");
+    if (c->opt.resident && (c->nb() != 1 || !jc::resident_fits(c->blocks[0].n[0], c->blocks[0].n[1], c->blocks[0].n[2])))
+        return fail(JC_ERR_INVALID, "options.resident needs a context of one block of at most 32 planes with "
+                                    "(nx + 1) / 2 * ny <= 512 and a ghost ring that fits 64 KiB of LDS");
     default_tiles(c, &c->tile_x, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
@@ -623,6 +630,25 @@ int do_sweep2(jc_ctx* c)
     return JC_OK;
 }
 
+// n sweeps in one launch (a resident context: one block that fits on chip).
+int do_resident(jc_ctx* c, int64_t n)
+{
+    const auto& b = c->blocks[0];
+    const int nx = (int)b.n[0], ny = (int)b.n[1], nz = (int)b.n[2];
+    int st = timed(c, JC_K_RESIDENT, [&] {
+        return jc::launch_resident(c->d_blocks(), nullptr, 1, (nx + 1) / 2 * ny, nz,
+                                   (size_t)jc::resident_lds_bytes(nx, ny, nz), nz & 1, c->parity, (int)n,
+                                   c->opt.with_source != 0, c->stream);
+    });
+    if (st != JC_OK)
+        return st;
+    c->parity ^= (int)(n & 1);
+    c->iters += n;
+    c->ghost = GHOST_CURRENT;
+    c->fused_primed = false;
+    return JC_OK;
+}
+
 int do_halo(jc_ctx* c)
 {
     if (c->np() == 0) {
@@ -766,6 +792,17 @@ int residual_now(jc_ctx* c, double* l2)
 // sweeps in one launch each and a last single sweep when n is odd.
 int iterate_eager(jc_ctx* c, int64_t n)
 {
+    if (c->opt.resident) {
+        // one launch per 2^30 sweeps
+        for (int64_t i = 0; i < n;) {
+            const int64_t m = std::min<int64_t>(n - i, (int64_t)1 << 30);
+            int st = do_resident(c, m);
+            if (st != JC_OK)
+                return st;
+            i += m;
+        }
+        return JC_OK;
+    }
     int64_t i = 0;
     if (c->depth() == 3) {
         for (; i + 3 <= n; i += 3) {
@@ -794,8 +831,9 @@ int iterate_window(jc_ctx* c, int64_t n)
 {
     if (n <= 0)
         return JC_OK;
+    // a resident window is one launch already: nothing to capture
     const bool graphs = c->opt.use_graphs && c->stream != nullptr && !c->timing &&
-                        c->opt.exchange == JC_EXCHANGE_DEVICE;
+                        c->opt.exchange == JC_EXCHANGE_DEVICE && !c->opt.resident;
     if (!graphs)
         return iterate_eager(c, n);
     // the priming pack of fused mode stays outside the graph

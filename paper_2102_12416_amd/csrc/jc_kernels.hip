@@ -1160,6 +1160,226 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
 }
 // ---- three-step sweep: end ----
 
+// ---- resident sweeps: many sweeps of a small block in one launch ----
+//
+// The on-chip small-grid solver: one work-group holds a whole block of
+// at most 32 planes and (nx + 1) / 2 * ny <= 512 cell pairs and runs any
+// number of Jacobi sweeps on it without leaving the compute unit, so a
+// small solve costs one launch per window instead of one per sweep (or
+// per two or three), and the block's cells cross HBM once per launch.
+//
+// Each thread owns the z columns of two adjacent x cells of one row, in
+// registers (element z of the column arrays is plane z; 0 the bottom
+// ghost plane; the top ghost plane is kept apart because its index is
+// not a compile-time constant).  A sweep marches up the columns; at plane
+// z every thread writes its pair of iterate-k values into an LDS plane
+// buffer (two buffers, alternating every plane step, so one barrier per
+// step suffices), reads its x and y neighbours from it and forms the
+// update with the same sums in the same order as every other sweep
+// kernel, so results are bitwise those of one-sweep launches.  The
+// update of plane z cannot overwrite plane z of the column yet (plane z +
+// 1 still needs its old value), so it waits one step in a register.
+//
+// The ghost cells around each plane never change: they are copied into
+// LDS once (the x = 0 and x = nx + 1 columns and the y = 0 and y = ny + 1
+// rows of every plane), and a thread on the block's edge reads its
+// neighbour from there instead of from the plane buffer.  The source b is
+// re-read from global memory (L2) every sweep, two plane steps ahead.
+//
+// Steps are unrolled two sweeps at a time so that the plane buffer and
+// the source register slot of every step are compile-time constants
+// (step s of the launch uses buffer s & 1; NZODD is nz & 1).
+
+template <int Z, int N, typename F>
+__device__ __forceinline__ void resident_steps(F& f)
+{
+    if constexpr (Z <= N) {
+        if (f(std::integral_constant<int, Z>{}))
+            resident_steps<Z + 1, N>(f);
+    }
+}
+
+template <int NZM, bool SRC, int NZODD>
+__global__ void __launch_bounds__(512)
+k_resident(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int nsweeps)
+{
+    extern __shared__ v2d lds_pairs[];
+    double* const lds = reinterpret_cast<double*>(lds_pairs);
+    const int blk = items ? items[blockIdx.x].block : 0;
+    const int p0 = parity ^ (items ? items[blockIdx.x].flip : 0);
+    const BlockDesc* B = blocks + blk;
+    const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+    const int ep = (nx + 1) >> 1;             // cell pairs per row
+    const int pw = 2 * ep;                    // LDS row length
+    const int ps = ny * pw;                   // LDS plane length
+    const int64_t pitch = B->pitch, plane = B->plane;
+    const double* __restrict__ u = B->u[p0];
+    double* const P = lds;                    // [2][ny][pw]  plane buffers
+    double* const RXM = P + 2 * ps;           // [nz][ny]     x = 0
+    double* const RXP = RXM + nz * ny;        // [nz][ny]     x = nx + 1
+    double* const RYM = RXP + nz * ny;        // [nz][pw]     y = 0
+    double* const RYP = RYM + nz * pw;        // [nz][pw]     y = ny + 1
+    const int t = threadIdx.x;
+    for (int i = t; i < nz * ny; i += blockDim.x) {
+        const int64_t o = (int64_t)(i / ny + 1) * plane + (int64_t)(i % ny + 1) * pitch;
+        RXM[i] = u[o];
+        RXP[i] = u[o + nx + 1];
+    }
+    for (int i = t; i < nz * pw; i += blockDim.x) {
+        const int64_t o = (int64_t)(i / pw + 1) * plane + (i % pw + 1);
+        RYM[i] = u[o];
+        RYP[i] = u[o + (int64_t)(ny + 1) * pitch];
+    }
+    const bool live = t < ep * ny;
+    const int j = live ? t % ep : 0, y0 = live ? t / ep : 0;
+    const bool b_ok = 2 * j + 2 <= nx;        // else the pair's second cell is the x = nx + 1 ghost
+    const int64_t own = (int64_t)(y0 + 1) * pitch + 2 * j + 1;
+
+    // LDS offsets of the neighbours of plane 1: in the plane buffer (buffer
+    // 0; the second buffer is sb further) or, on the block's edge, in the
+    // ghost ring of plane 1 (plane z is (z - 1) * sx further)
+    const bool xm_ring = j == 0, xp_ring = j == ep - 1, ym_ring = y0 == 0, yp_ring = y0 == ny - 1;
+    const int row = y0 * pw + 2 * j;
+    const int o_xm = xm_ring ? 2 * ps + y0 : row - 1;
+    const int o_xp = xp_ring ? 2 * ps + nz * ny + y0 : row + 2;
+    const int o_ym = ym_ring ? 2 * ps + 2 * nz * ny + 2 * j : row - pw;
+    const int o_yp = yp_ring ? 2 * ps + 2 * nz * ny + nz * pw + 2 * j : row + pw;
+    const int sx_xm = xm_ring ? ny : 0, sb_xm = xm_ring ? 0 : ps;
+    const int sx_xp = xp_ring ? ny : 0, sb_xp = xp_ring ? 0 : ps;
+    const int sx_ym = ym_ring ? pw : 0, sb_ym = ym_ring ? 0 : ps;
+    const int sx_yp = yp_ring ? pw : 0, sb_yp = yp_ring ? 0 : ps;
+    v2d* const w0 = reinterpret_cast<v2d*>(P + row);
+
+    double ca[NZM + 2], cb[NZM + 2];
+    {
+        const v2d g = *(const v2d JC_GLOBAL*)(u + own);
+        ca[0] = g.x;
+        cb[0] = g.y;
+    }
+#pragma unroll
+    for (int z = 1; z <= NZM; ++z) {
+        if (z <= nz) {
+            const v2d v = *(const v2d JC_GLOBAL*)(u + (int64_t)z * plane + own);
+            ca[z] = v.x;
+            cb[z] = v.y;
+        } else {
+            ca[z] = cb[z] = 0.0;
+        }
+    }
+    ca[NZM + 1] = cb[NZM + 1] = 0.0;
+    double ta, tb;                            // the z = nz + 1 ghosts
+    {
+        const v2d g = *(const v2d JC_GLOBAL*)(u + (int64_t)(nz + 1) * plane + own);
+        ta = g.x;
+        tb = g.y;
+    }
+    // source of step s in slot s & 1, loaded two steps ahead
+    const double* const bsrc = SRC ? B->b : nullptr;
+    const int own32 = (int)own;
+    double qa[2] = {0.0, 0.0}, qb[2] = {0.0, 0.0};
+    if (SRC) {
+        const v2d q1 = *(const v2d JC_GLOBAL*)(bsrc + own + plane);
+        qa[1] = q1.x;
+        qb[1] = q1.y;
+        const v2d q2 = *(const v2d JC_GLOBAL*)(bsrc + own + (int64_t)(nz >= 2 ? 2 : 1) * plane);
+        qa[0] = q2.x;
+        qb[0] = q2.y;
+    }
+    __syncthreads();                          // ghost rings written
+
+    double pa = 0.0, pb = 0.0;                // the update of the plane below, not yet stored
+    auto sweep = [&](auto hc) {
+        constexpr int H = decltype(hc)::value;
+        // running neighbour offsets, opaque to the compiler: otherwise it
+        // hoists the address of every plane step out of the sweep loop and
+        // holds them all in registers
+        int r_xm = o_xm, r_xp = o_xp, r_ym = o_ym, r_yp = o_yp, r_src = own32;
+        asm volatile("" : "+v"(r_xm), "+v"(r_xp), "+v"(r_ym), "+v"(r_yp), "+v"(r_src));
+        auto step = [&](auto zc) -> bool {
+            constexpr int Z = decltype(zc)::value;
+            if (Z > nz)
+                return false;
+            constexpr int S = (Z + H * NZODD) & 1;
+            const double a = ca[Z], b = cb[Z];
+            const double zpa = (Z == nz) ? ta : ca[Z + 1];
+            const double zpb = (Z == nz) ? tb : cb[Z + 1];
+            double s_a = 0.0, s_b = 0.0;
+            if (SRC) {
+                s_a = qa[S];
+                s_b = qb[S];
+                int zq = Z + 2;
+                if (zq > nz) zq -= nz;
+                if (zq > nz) zq = 1;
+                const v2d q = *(const v2d JC_GLOBAL*)(bsrc + (int64_t)zq * plane + r_src);
+                qa[S] = q.x;
+                qb[S] = q.y;
+            }
+            if (live) {
+                v2d w;
+                w.x = a;
+                w.y = b;
+                w0[S * (ps / 2)] = w;
+            }
+            __syncthreads();
+            const double xm = lds[r_xm + (S ? sb_xm : 0)];
+            const double xp = lds[r_xp + (S ? sb_xp : 0)];
+            const v2d ym = *reinterpret_cast<const v2d*>(lds + r_ym + (S ? sb_ym : 0));
+            const v2d yp = *reinterpret_cast<const v2d*>(lds + r_yp + (S ? sb_yp : 0));
+            r_xm += sx_xm;
+            r_xp += sx_xp;
+            r_ym += sx_ym;
+            r_yp += sx_yp;
+            double sa = xm + b;
+            sa = sa + ym.x;
+            sa = sa + yp.x;
+            sa = sa + ca[Z - 1];
+            sa = sa + zpa;
+            double sb = a + xp;
+            sb = sb + ym.y;
+            sb = sb + yp.y;
+            sb = sb + cb[Z - 1];
+            sb = sb + zpb;
+            double va, vb;
+            if (SRC)
+                div6_pair(sa + s_a, sb + s_b, va, vb);
+            else
+                div6_pair(sa, sb, va, vb);
+            vb = b_ok ? vb : b;
+            if (Z > 1) {
+                ca[Z - 1] = pa;
+                cb[Z - 1] = pb;
+            }
+            pa = va;
+            pb = vb;
+            if (Z == nz) {
+                ca[Z] = va;
+                cb[Z] = vb;
+            }
+            return true;
+        };
+        resident_steps<1, NZM>(step);
+    };
+    for (int k = 0; k < nsweeps; k += 2) {
+        sweep(std::integral_constant<int, 0>{});
+        if (k + 1 < nsweeps)
+            sweep(std::integral_constant<int, 1>{});
+    }
+
+    double* const dst = B->u[p0 ^ (nsweeps & 1)];
+    if (live) {
+#pragma unroll
+        for (int z = 1; z <= NZM; ++z) {
+            if (z <= nz) {
+                v2d v;
+                v.x = ca[z];
+                v.y = cb[z];
+                *(v2d JC_GLOBAL*)(dst + (int64_t)z * plane + own) = v;
+            }
+        }
+    }
+}
+// ---- resident sweeps: end ----
+
 // First inner sweep of a refinement step: d_1 = lo((0 + r_lo) / 6)
 // (d_0 = 0, so no neighbour is read); writes copy 1 of d and its faces.
 template <typename T>
@@ -1543,6 +1763,34 @@ hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nite
     case 2: return sweep3_rows<bf16, FIELD_D, true>(blocks, items, qparity, tile_y, (int)tx, (int)ty, (int)nch, (int)n, s, pace);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int NZM, bool SRC>
+hipError_t resident_launch(const BlockDesc* blocks, const Item* items, int n, int threads, size_t lds, int nz_odd,
+                           int parity, int nsweeps, hipStream_t s)
+{
+    if (nz_odd)
+        hipLaunchKernelGGL((k_resident<NZM, SRC, 1>), dim3(n), dim3(threads), lds, s, blocks, items, parity, nsweeps);
+    else
+        hipLaunchKernelGGL((k_resident<NZM, SRC, 0>), dim3(n), dim3(threads), lds, s, blocks, items, parity, nsweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(const BlockDesc* blocks, const Item* items, int nitems, int max_pairs, int max_nz,
+                           size_t lds_bytes, int nz_odd, int parity, int nsweeps, bool src, hipStream_t s)
+{
+    const int n = items ? nitems : 1;
+    if (n <= 0 || nsweeps <= 0)
+        return hipSuccess;
+    if (max_pairs < 1 || max_pairs > kResidentMaxPairs || max_nz < 1 || max_nz > kResidentMaxPlanes ||
+        lds_bytes > kResidentMaxLds || n > 65535)
+        return hipErrorInvalidValue;
+    const int threads = (max_pairs + 63) / 64 * 64;
+    if (max_nz <= 16)
+        return src ? resident_launch<16, true>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s)
+                   : resident_launch<16, false>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s);
+    return src ? resident_launch<32, true>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s)
+               : resident_launch<32, false>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s);
 }
 
 hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,

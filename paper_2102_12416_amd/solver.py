@@ -29,11 +29,14 @@ class Solver:
     kernels) or 'fused' (one launch per iteration).  temporal: a one-block
     context advances iterate/solve windows two sweeps per launch.  overlap
     (staged mode): boundary tiles sweep first, then the halo of the new
-    iterate moves on a second stream while the interior tiles sweep."""
+    iterate moves on a second stream while the interior tiles sweep.
+    resident: a small one-block grid (at most 32 planes, (nx + 1) / 2 * ny
+    <= 512) runs each iterate/solve window as one launch that keeps the
+    grid on chip."""
 
     def __init__(self, grid, block_dims=None, cuts=None, mode="staged", with_source=False,
                  tile_y=0, z_chunk=0, use_graphs=True, ir_dtype=None, device="cuda:0", stream=None,
-                 tile_x=0, exchange="device", temporal=False, overlap=False):
+                 tile_x=0, exchange="device", temporal=False, overlap=False, resident=False):
         # temporal: False, True (two sweeps per launch), or 2 / 3 sweeps per launch
         self.grid = tuple(int(v) for v in grid)
         self.device = torch.device(device)
@@ -53,6 +56,7 @@ class Solver:
         self.opt.temporal = int(bool(temporal))
         self.opt.sweeps_per_launch = 3 if temporal == 3 else 0
         self.opt.overlap = int(bool(overlap))
+        self.opt.resident = int(bool(resident))
         self.with_source = bool(with_source)
         self._ctx = ctypes.c_void_p()
         g = L.i64(self.grid)
@@ -314,8 +318,10 @@ class Group:
     (jc_group_bind_static, no allocation; one such group per device at a
     time) instead of a torch-allocated buffer."""
 
-    def __init__(self, solvers, use_graphs=True, stream=None, tile=None, temporal=False, static_scratch=False):
-        # temporal: False, True (two sweeps of every member per launch) or 3
+    def __init__(self, solvers, use_graphs=True, stream=None, tile=None, temporal=False, static_scratch=False,
+                 resident=False):
+        # temporal: False, True (two sweeps of every member per launch) or 3;
+        # resident: every window one launch, one work-group per member
         self.solvers = list(solvers)
         dev = self.solvers[0].device
         self.device = dev
@@ -323,7 +329,7 @@ class Group:
         arr = (ctypes.c_void_p * len(self.solvers))(*[s._ctx.value for s in self.solvers])
         self._g = ctypes.c_void_p()
         tl = None if tile is None else (ctypes.c_int * 3)(*[int(v) for v in tile])
-        flags = (1 if use_graphs else 0) | (4 if temporal == 3 else 2 if temporal else 0)
+        flags = (1 if use_graphs else 0) | (4 if temporal == 3 else 2 if temporal else 0) | (8 if resident else 0)
         check(L.lib.jc_group_create(arr, len(self.solvers), ctypes.c_void_p(_stream_handle(self.stream)),
                                     flags, tl, ctypes.byref(self._g)))
         fp = ctypes.c_size_t()

@@ -42,6 +42,8 @@ def create(grid, bd, **kw):
     opt.z_chunk = kw.get("z_chunk", 0)
     opt.tile_x = kw.get("tile_x", 0)
     opt.temporal = kw.get("temporal", 0)
+    opt.overlap = kw.get("overlap", 0)
+    opt.resident = kw.get("resident", 0)
     ctx = ctypes.c_void_p()
     st = L.lib.jc_create(L.i64(grid), L.i64(bd), ctypes.byref(opt), ctypes.byref(ctx))
     return st, ctx
@@ -328,6 +330,42 @@ def test_wide_tiles_need_binary64_storage():
     st, ctx = create((64, 64, 64), (64, 64, 64), tile_x=128, ir_enable=1, ir_dtype=L.JC_F64)
     assert st == 0
     check(L.lib.jc_set_tiles(ctx, 256, 8, 32))
+    L.lib.jc_destroy(ctx)
+
+
+def resident_lds(nx, ny, nz):
+    # two plane buffers of (nx + 1) // 2 pairs by ny rows, and the x and y ghost rings of every plane
+    pw = 2 * ((nx + 1) // 2)
+    return 8 * (2 * ny * pw + 2 * nz * ny + 2 * nz * pw)
+
+
+@pytest.mark.parametrize("grid,ok", [((32, 32, 32), True), ((31, 32, 32), True), ((1, 1, 1), True),
+                                     ((64, 16, 32), True), ((33, 32, 32), False), ((32, 32, 33), False),
+                                     ((2, 512, 8), False), ((2, 512, 1), True), ((64, 16, 24), True)])
+def test_resident_shape_limits(grid, ok):
+    """One block of at most 32 planes, (nx + 1) / 2 * ny <= 512 cell pairs
+    and an LDS need of at most 64 KiB."""
+    nx, ny, nz = grid
+    assert ok == (nz <= 32 and (nx + 1) // 2 * ny <= 512 and resident_lds(nx, ny, nz) <= 65536)
+    st, ctx = create(grid, grid, resident=1, with_source=1)
+    if ok:
+        assert st == 0, L.last_error()
+        L.lib.jc_destroy(ctx)
+    else:
+        assert st == L.JC_ERR_INVALID and "resident" in L.last_error()
+
+
+def test_resident_option_conflicts():
+    g = (16, 16, 16)
+    st, _ = create(g, (8, 16, 16), resident=1)
+    assert st == L.JC_ERR_INVALID and "one block" in L.last_error()
+    for kw in (dict(ir_enable=1, ir_dtype=L.JC_F64), dict(temporal=1), dict(overlap=1)):
+        st, _ = create(g, g, resident=1, **kw)
+        assert st == L.JC_ERR_INVALID and "resident" in L.last_error()
+    st, _ = create(g, g, resident=2)
+    assert st == L.JC_ERR_INVALID
+    st, ctx = create(g, g, resident=1, mode=L.JC_MODE_FUSED)
+    assert st == 0
     L.lib.jc_destroy(ctx)
 
 
