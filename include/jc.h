@@ -131,9 +131,12 @@ typedef struct jc_options {
                             plane and the ghost rings in LDS) and sweeps it that many times,
                             so a solve costs one launch per residual check.  Needs a context
                             of one block of at most 32 planes with (nx + 1) / 2 * ny <= 512
-                            (for instance 32^3, 64 x 16 x 32) whose LDS need fits 64 KiB, no
-                            refinement, temporal = 0 and overlap = 0; else JC_ERR_INVALID at
-                            creation.  Results bitwise equal to one-sweep launches.  After a
+                            cell pairs (one thread each, rounded up to whole waves of 64),
+                            at most that many threads' worth of ghost ring per plane
+                            (2 nx' + 2 ny, nx' = nx rounded up to even) and an LDS need of
+                            8 (2 (ny + 2)(nx' + 4) + nz (2 nx' + 2 ny)) bytes within 64 KiB
+                            (for instance 32^3, 64 x 16 x 32), no refinement, temporal = 0
+                            and overlap = 0; else JC_ERR_INVALID at creation.  Results bitwise equal to one-sweep launches.  After a
                             window only the copy holding the iterate is defined (the other
                             copy holds an older iterate).  0: off. */
 } jc_options;
@@ -286,11 +289,12 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * per launch (the same conditions and tiles; a count that is not a
  * multiple of three ends with a two-sweep launch or a single sweep);
  * bit 3 = resident sweeps: every jc_group_iterate window is one launch per
- * class (two when members' plane counts differ in parity) with one
+ * class and parity of the members' plane counts with one
  * work-group per member, which keeps its member's block on chip for the
  * whole window (members as for options.resident: one block of at most 32
- * planes, (nx + 1) / 2 * ny <= 512, LDS need within 64 KiB, no refinement;
- * else JC_ERR_INVALID; not with bits 1 and 2; results bitwise the same).
+ * planes, (nx + 1) / 2 * ny <= 512, the ring and LDS limits there, no
+ * refinement; else JC_ERR_INVALID; not with bits 1 and 2; results bitwise
+ * the same).
  * tile: {cells per row 16|32|64 (or 96|128|256 when no member refines in
  * binary32 or bfloat16), rows 4|8|16|32 (64 to 1024 threads), planes >= 1} for every
  * launch of the group, or NULL for {64, 8, 32}; members' results do not

@@ -40,12 +40,12 @@ struct Class {
     size_t item2_0 = 0;              // first joint two-sweep item
     std::vector<Item> items2;        // two-sweep tiles (groups that sweep twice per launch)
     std::vector<int> members;
-    // resident sweeps: one item per member, split by the parity of its
-    // plane count (the kernel's step schedule depends on it)
-    std::vector<Item> itemsr[2];
-    size_t itemr0[2] = {0, 0};       // first joint resident item of each split
-    int max_pairs[2] = {1, 1}, max_nz[2] = {1, 1};
-    int64_t lds[2] = {0, 0};
+    // resident sweeps: one item per member, split by launch variant (the
+    // kernel's step schedule depends on the parity of the plane count)
+    std::vector<Item> itemsr[jc::kResidentVariants];
+    size_t itemr0[jc::kResidentVariants] = {};       // first joint resident item of each split
+    int max_pairs[jc::kResidentVariants] = {}, max_nz[jc::kResidentVariants] = {};
+    int64_t lds[jc::kResidentVariants] = {};
 };
 
 // Two-sweep tiles of a group: 64 cells by kGroupTwoStepRows rows, and at
@@ -200,12 +200,12 @@ int group_sweep3(jc_group* g)
     return JC_OK;
 }
 
-// n sweeps of every member in one launch per class and plane-count parity
+// n sweeps of every member in one launch per class and launch variant
 // (resident groups).
 int group_resident(jc_group* g, int64_t n)
 {
     for (const Class& k : g->classes)
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < jc::kResidentVariants; ++q) {
             if (k.itemsr[q].empty())
                 continue;
             const hipError_t e = jc::launch_resident(g->d_desc(), g->d_itemsr() + k.itemr0[q], (int)k.itemsr[q].size(),
@@ -326,7 +326,8 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
         if ((flags & 8) && (c->opt.ir_enable || c->nb() != 1 ||
                             !jc::resident_fits(c->blocks[0].n[0], c->blocks[0].n[1], c->blocks[0].n[2])))
             return fail(JC_ERR_INVALID, "resident sweeps (flag 8) need members of one block of at most 32 planes "
-                                        "with (nx + 1) / 2 * ny <= 512 and an LDS need within 64 KiB, without "
+                                        "with (nx + 1) / 2 * ny <= 512 cell pairs, a ghost ring per plane no "
+                                        "longer than the work-group and an LDS need within 64 KiB, without "
                                         "refinement");
     }
     if (tile) {
@@ -386,7 +387,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
             }
             if (g->resident) {
                 const int64_t* bn = c->blocks[0].n;
-                const int q = (int)(bn[2] & 1);
+                const int q = jc::resident_variant(bn[2]);
                 Item it{};
                 it.block = (int32_t)g->desc.size();
                 it.zlen = (int32_t)bn[2];
@@ -405,7 +406,7 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
         k.bend = (int)g->desc.size();
         k.item2_0 = g->items2.size();
         g->items2.insert(g->items2.end(), k.items2.begin(), k.items2.end());
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < jc::kResidentVariants; ++q) {
             k.itemr0[q] = g->itemsr.size();
             g->itemsr.insert(g->itemsr.end(), k.itemsr[q].begin(), k.itemsr[q].end());
         }

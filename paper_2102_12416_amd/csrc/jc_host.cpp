@@ -259,7 +259,8 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         return fail(JC_ERR_INVALID, "options.temporal needs a context of one block (no face pairs)");
     if (c->opt.resident && (c->nb() != 1 || !jc::resident_fits(c->blocks[0].n[0], c->blocks[0].n[1], c->blocks[0].n[2])))
         return fail(JC_ERR_INVALID, "options.resident needs a context of one block of at most 32 planes with "
-                                    "(nx + 1) / 2 * ny <= 512 and a ghost ring that fits 64 KiB of LDS");
+                                    "(nx + 1) / 2 * ny <= 512 cell pairs, a ghost ring per plane no longer than "
+                                    "the work-group and an LDS need within 64 KiB");
     default_tiles(c, &c->tile_x, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
@@ -637,7 +638,7 @@ int do_resident(jc_ctx* c, int64_t n)
     const int nx = (int)b.n[0], ny = (int)b.n[1], nz = (int)b.n[2];
     int st = timed(c, JC_K_RESIDENT, [&] {
         return jc::launch_resident(c->d_blocks(), nullptr, 1, (nx + 1) / 2 * ny, nz,
-                                   (size_t)jc::resident_lds_bytes(nx, ny, nz), nz & 1, c->parity, (int)n,
+                                   (size_t)jc::resident_lds_bytes(nx, ny, nz), jc::resident_variant(nz), c->parity, (int)n,
                                    c->opt.with_source != 0, c->stream);
     });
     if (st != JC_OK)

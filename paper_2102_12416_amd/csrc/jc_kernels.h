@@ -50,15 +50,16 @@ hipError_t launch_sweep3(const BlockDesc* blocks, const Item* items, int nitems,
 hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nitems, int nx, int ny, int nz,
                             int qparity, int tile_y, int z_chunk, int lo_dtype, hipStream_t s, uint32_t pace = 0);
 
-// Many sweeps in one launch (k_resident): nsweeps Jacobi sweeps of blocks
-// that fit on chip (resident_fits), one work-group per block, iterate k
-// from copy parity (xor the item's flip), iterate k + nsweeps into copy
-// parity ^ (nsweeps & 1).  items null: blocks[0] alone; otherwise one
-// work-group per item (block and flip; every block's nz & 1 = nz_odd).
-// max_pairs / max_nz / lds_bytes: the largest (nx + 1) / 2 * ny, nz and
-// resident_lds_bytes over the blocks swept.
+// Many sweeps in one launch (k_resident, k_resident_pipe): nsweeps Jacobi
+// sweeps of blocks that fit on chip (resident_fits), one work-group per
+// block, iterate k from copy parity (xor the item's flip), iterate k +
+// nsweeps into copy parity ^ (nsweeps & 1).  items null: blocks[0] alone;
+// otherwise one work-group per item (block and flip; every block's
+// resident_variant(nz) equal to variant).  max_pairs / max_nz /
+// lds_bytes: the largest (nx + 1) / 2 * ny, nz and resident_lds_bytes
+// over the blocks swept.
 hipError_t launch_resident(const BlockDesc* blocks, const Item* items, int nitems, int max_pairs, int max_nz,
-                           size_t lds_bytes, int nz_odd, int parity, int nsweeps, bool src, hipStream_t s);
+                           size_t lds_bytes, int variant, int parity, int nsweeps, bool src, hipStream_t s);
 
 // Refinement passes (lo_dtype: 0 binary64, 1 binary32, 2 bfloat16 storage
 // of d and r_lo).  Residual: r of u[parity] with fused ghosts (face

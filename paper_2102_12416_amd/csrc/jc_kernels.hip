@@ -1171,51 +1171,58 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
 // Each thread owns the z columns of two adjacent x cells of one row, in
 // registers (element z of the column arrays is plane z; 0 the bottom
 // ghost plane; the top ghost plane is kept apart because its index is
-// not a compile-time constant).  A sweep marches up the columns; at plane
-// z every thread writes its pair of iterate-k values into an LDS plane
-// buffer (two buffers, alternating every plane step, so one barrier per
-// step suffices), reads its x and y neighbours from it and forms the
-// update with the same sums in the same order as every other sweep
-// kernel, so results are bitwise those of one-sweep launches.  The
-// update of plane z cannot overwrite plane z of the column yet (plane z +
-// 1 still needs its old value), so it waits one step in a register.
+// not a compile-time constant).  A sweep marches up the columns two
+// planes at a time: every thread writes its iterate-k pairs of planes z
+// and z + 1 into two LDS plane buffers, synchronises once, reads its x
+// and y neighbours in both planes and forms both updates with the same
+// sums in the same order as every other sweep kernel, so results are
+// bitwise those of one-sweep launches.  Within a sweep the planes depend
+// on iterate k only, so the two planes' dependent chains of additions
+// and the division run interleaved; the step is bound by that latency
+// and by the LDS round trip, not by bandwidth.  The buffers come in two
+// sets that alternate every step, so one barrier per step suffices.  The
+// update of plane z + 1 cannot overwrite the column yet (plane z + 2
+// still needs its old value), so it waits one step in a register.
 //
 // The ghost cells around each plane never change: they are copied into
 // LDS once (the x = 0 and x = nx + 1 columns and the y = 0 and y = ny + 1
 // rows of every plane), and a thread on the block's edge reads its
-// neighbour from there instead of from the plane buffer.  The source b is
-// re-read from global memory (L2) every sweep, two plane steps ahead.
+// neighbour from there instead of from a plane buffer.  The source b is
+// re-read from global memory (L2) every sweep, two steps ahead.
 //
-// Steps are unrolled two sweeps at a time so that the plane buffer and
-// the source register slot of every step are compile-time constants
-// (step s of the launch uses buffer s & 1; NZODD is nz & 1).
+// Steps are unrolled two sweeps at a time so that the buffer set and the
+// source register slot of every step are compile-time constants (step s
+// of the launch uses set s & 1; NBODD is the parity of the number of
+// steps per sweep, (nz + 1) / 2).
 
-template <int Z, int N, typename F>
+template <int I, int N, typename F>
 __device__ __forceinline__ void resident_steps(F& f)
 {
-    if constexpr (Z <= N) {
-        if (f(std::integral_constant<int, Z>{}))
-            resident_steps<Z + 1, N>(f);
+    if constexpr (I < N) {
+        if (f(std::integral_constant<int, I>{}))
+            resident_steps<I + 1, N>(f);
     }
 }
 
-template <int NZM, bool SRC, int NZODD>
+template <bool SRC, int NBODD>
 __global__ void __launch_bounds__(512)
 k_resident(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, int parity, int nsweeps)
 {
+    constexpr int NZM = kResidentMaxPlanes;
     extern __shared__ v2d lds_pairs[];
     double* const lds = reinterpret_cast<double*>(lds_pairs);
     const int blk = items ? items[blockIdx.x].block : 0;
     const int p0 = parity ^ (items ? items[blockIdx.x].flip : 0);
     const BlockDesc* B = blocks + blk;
     const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+    const int nb = (nz + 1) >> 1;             // steps per sweep
     const int ep = (nx + 1) >> 1;             // cell pairs per row
     const int pw = 2 * ep;                    // LDS row length
-    const int ps = ny * pw;                   // LDS plane length
+    const int ps = ny * pw;                   // LDS plane buffer length
     const int64_t pitch = B->pitch, plane = B->plane;
     const double* __restrict__ u = B->u[p0];
-    double* const P = lds;                    // [2][ny][pw]  plane buffers
-    double* const RXM = P + 2 * ps;           // [nz][ny]     x = 0
+    double* const P = lds;                    // [2 sets][2 planes][ny][pw]
+    double* const RXM = P + 4 * ps;           // [nz][ny]     x = 0
     double* const RXP = RXM + nz * ny;        // [nz][ny]     x = nx + 1
     double* const RYM = RXP + nz * ny;        // [nz][pw]     y = 0
     double* const RYP = RYM + nz * pw;        // [nz][pw]     y = ny + 1
@@ -1235,15 +1242,16 @@ k_resident(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items,
     const bool b_ok = 2 * j + 2 <= nx;        // else the pair's second cell is the x = nx + 1 ghost
     const int64_t own = (int64_t)(y0 + 1) * pitch + 2 * j + 1;
 
-    // LDS offsets of the neighbours of plane 1: in the plane buffer (buffer
-    // 0; the second buffer is sb further) or, on the block's edge, in the
-    // ghost ring of plane 1 (plane z is (z - 1) * sx further)
+    // LDS offsets of the neighbours in plane 1: in plane buffer 0, or on
+    // the block's edge in the ghost ring of plane 1.  Buffer k is k * sb
+    // further (sb = 0 on a ring), plane z of a ring (z - 1) * sx further
+    // (sx = 0 in the buffers).
     const bool xm_ring = j == 0, xp_ring = j == ep - 1, ym_ring = y0 == 0, yp_ring = y0 == ny - 1;
     const int row = y0 * pw + 2 * j;
-    const int o_xm = xm_ring ? 2 * ps + y0 : row - 1;
-    const int o_xp = xp_ring ? 2 * ps + nz * ny + y0 : row + 2;
-    const int o_ym = ym_ring ? 2 * ps + 2 * nz * ny + 2 * j : row - pw;
-    const int o_yp = yp_ring ? 2 * ps + 2 * nz * ny + nz * pw + 2 * j : row + pw;
+    const int o_xm = xm_ring ? 4 * ps + y0 : row - 1;
+    const int o_xp = xp_ring ? 4 * ps + nz * ny + y0 : row + 2;
+    const int o_ym = ym_ring ? 4 * ps + 2 * nz * ny + 2 * j : row - pw;
+    const int o_yp = yp_ring ? 4 * ps + 2 * nz * ny + nz * pw + 2 * j : row + pw;
     const int sx_xm = xm_ring ? ny : 0, sb_xm = xm_ring ? 0 : ps;
     const int sx_xp = xp_ring ? ny : 0, sb_xp = xp_ring ? 0 : ps;
     const int sx_ym = ym_ring ? pw : 0, sb_ym = ym_ring ? 0 : ps;
@@ -1273,91 +1281,152 @@ k_resident(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items,
         ta = g.x;
         tb = g.y;
     }
-    // source of step s in slot s & 1, loaded two steps ahead
-    const double* const bsrc = SRC ? B->b : nullptr;
+    // source of the two planes of step s in slot s & 1, loaded two steps
+    // ahead (the second plane of a one-plane step repeats the first)
     const int own32 = (int)own;
-    double qa[2] = {0.0, 0.0}, qb[2] = {0.0, 0.0};
+    double qa[2][2] = {}, qb[2][2] = {};
+    auto load_src = [&](int step, double* da, double* db) __attribute__((always_inline)) {
+        while (step >= nb)
+            step -= nb;
+        const int z1 = 2 * step + 1, z2 = z1 + 1 <= nz ? z1 + 1 : z1;
+        const v2d q1 = *(const v2d JC_GLOBAL*)(B->b + (int64_t)z1 * plane + own32);
+        const v2d q2 = *(const v2d JC_GLOBAL*)(B->b + (int64_t)z2 * plane + own32);
+        da[0] = q1.x;
+        db[0] = q1.y;
+        da[1] = q2.x;
+        db[1] = q2.y;
+    };
     if (SRC) {
-        const v2d q1 = *(const v2d JC_GLOBAL*)(bsrc + own + plane);
-        qa[1] = q1.x;
-        qb[1] = q1.y;
-        const v2d q2 = *(const v2d JC_GLOBAL*)(bsrc + own + (int64_t)(nz >= 2 ? 2 : 1) * plane);
-        qa[0] = q2.x;
-        qb[0] = q2.y;
+        load_src(0, qa[0], qb[0]);
+        load_src(1, qa[1], qb[1]);
     }
     __syncthreads();                          // ghost rings written
 
     double pa = 0.0, pb = 0.0;                // the update of the plane below, not yet stored
-    auto sweep = [&](auto hc) {
+    auto sweep = [&](auto hc) __attribute__((always_inline)) {
         constexpr int H = decltype(hc)::value;
-        // running neighbour offsets, opaque to the compiler: otherwise it
-        // hoists the address of every plane step out of the sweep loop and
-        // holds them all in registers
-        int r_xm = o_xm, r_xp = o_xp, r_ym = o_ym, r_yp = o_yp, r_src = own32;
-        asm volatile("" : "+v"(r_xm), "+v"(r_xp), "+v"(r_ym), "+v"(r_yp), "+v"(r_src));
-        auto step = [&](auto zc) -> bool {
-            constexpr int Z = decltype(zc)::value;
+        // running ring offsets of the step's first plane, opaque to the
+        // compiler: otherwise it hoists the address of every step out of
+        // the sweep loop and holds them all in registers
+        int r_xm = o_xm, r_xp = o_xp, r_ym = o_ym, r_yp = o_yp;
+        asm volatile("" : "+v"(r_xm), "+v"(r_xp), "+v"(r_ym), "+v"(r_yp));
+        auto step = [&](auto ic) __attribute__((always_inline)) -> bool {
+            constexpr int I = decltype(ic)::value;
+            constexpr int Z = 2 * I + 1;      // the step's first plane
             if (Z > nz)
                 return false;
-            constexpr int S = (Z + H * NZODD) & 1;
-            const double a = ca[Z], b = cb[Z];
-            const double zpa = (Z == nz) ? ta : ca[Z + 1];
-            const double zpb = (Z == nz) ? tb : cb[Z + 1];
-            double s_a = 0.0, s_b = 0.0;
+            constexpr int SET = (I + H * NBODD) & 1;
+            double s1a = 0.0, s1b = 0.0, s2a = 0.0, s2b = 0.0;
             if (SRC) {
-                s_a = qa[S];
-                s_b = qb[S];
-                int zq = Z + 2;
-                if (zq > nz) zq -= nz;
-                if (zq > nz) zq = 1;
-                const v2d q = *(const v2d JC_GLOBAL*)(bsrc + (int64_t)zq * plane + r_src);
-                qa[S] = q.x;
-                qb[S] = q.y;
+                s1a = qa[SET][0];
+                s1b = qb[SET][0];
+                s2a = qa[SET][1];
+                s2b = qb[SET][1];
+                load_src(I + 2, qa[SET], qb[SET]);
             }
-            if (live) {
-                v2d w;
-                w.x = a;
-                w.y = b;
-                w0[S * (ps / 2)] = w;
+            // TWO: planes Z and Z + 1 (else Z alone, the top plane);
+            // TOP: the step's last plane is the top plane nz
+            auto body = [&](auto twoc, auto topc) __attribute__((always_inline)) {
+                constexpr bool TWO = decltype(twoc)::value, TOP = decltype(topc)::value;
+                if (live) {
+                    v2d w;
+                    w.x = ca[Z];
+                    w.y = cb[Z];
+                    w0[(2 * SET) * (ps / 2)] = w;
+                    if (TWO) {
+                        w.x = ca[Z + 1];
+                        w.y = cb[Z + 1];
+                        w0[(2 * SET + 1) * (ps / 2)] = w;
+                    }
+                }
+                __syncthreads();
+                const double xm1 = lds[r_xm + (2 * SET) * sb_xm];
+                const double xp1 = lds[r_xp + (2 * SET) * sb_xp];
+                const v2d ym1 = *reinterpret_cast<const v2d*>(lds + r_ym + (2 * SET) * sb_ym);
+                const v2d yp1 = *reinterpret_cast<const v2d*>(lds + r_yp + (2 * SET) * sb_yp);
+                double xm2 = 0.0, xp2 = 0.0;
+                v2d ym2 = {0.0, 0.0}, yp2 = {0.0, 0.0};
+                if (TWO) {
+                    xm2 = lds[r_xm + sx_xm + (2 * SET + 1) * sb_xm];
+                    xp2 = lds[r_xp + sx_xp + (2 * SET + 1) * sb_xp];
+                    ym2 = *reinterpret_cast<const v2d*>(lds + r_ym + sx_ym + (2 * SET + 1) * sb_ym);
+                    yp2 = *reinterpret_cast<const v2d*>(lds + r_yp + sx_yp + (2 * SET + 1) * sb_yp);
+                }
+                // plane Z
+                const double a1 = ca[Z], b1 = cb[Z];
+                double sa1 = xm1 + b1;
+                sa1 = sa1 + ym1.x;
+                sa1 = sa1 + yp1.x;
+                sa1 = sa1 + ca[Z - 1];
+                sa1 = sa1 + (TWO ? ca[Z + 1] : ta);
+                double sb1 = a1 + xp1;
+                sb1 = sb1 + ym1.y;
+                sb1 = sb1 + yp1.y;
+                sb1 = sb1 + cb[Z - 1];
+                sb1 = sb1 + (TWO ? cb[Z + 1] : tb);
+                double va1, vb1;
+                if (SRC)
+                    div6_pair(sa1 + s1a, sb1 + s1b, va1, vb1);
+                else
+                    div6_pair(sa1, sb1, va1, vb1);
+                vb1 = b_ok ? vb1 : b1;
+                if (TWO) {
+                    // plane Z + 1
+                    const double a2 = ca[Z + 1], b2 = cb[Z + 1];
+                    double sa2 = xm2 + b2;
+                    sa2 = sa2 + ym2.x;
+                    sa2 = sa2 + yp2.x;
+                    sa2 = sa2 + a1;
+                    sa2 = sa2 + (TOP ? ta : ca[Z + 2]);
+                    double sb2 = a2 + xp2;
+                    sb2 = sb2 + ym2.y;
+                    sb2 = sb2 + yp2.y;
+                    sb2 = sb2 + b1;
+                    sb2 = sb2 + (TOP ? tb : cb[Z + 2]);
+                    double va2, vb2;
+                    if (SRC)
+                        div6_pair(sa2 + s2a, sb2 + s2b, va2, vb2);
+                    else
+                        div6_pair(sa2, sb2, va2, vb2);
+                    vb2 = b_ok ? vb2 : b2;
+                    if (Z > 1) {
+                        ca[Z - 1] = pa;
+                        cb[Z - 1] = pb;
+                    }
+                    ca[Z] = va1;
+                    cb[Z] = vb1;
+                    pa = va2;
+                    pb = vb2;
+                    if (TOP) {
+                        ca[Z + 1] = va2;
+                        cb[Z + 1] = vb2;
+                    }
+                } else {
+                    if (Z > 1) {
+                        ca[Z - 1] = pa;
+                        cb[Z - 1] = pb;
+                    }
+                    ca[Z] = va1;
+                    cb[Z] = vb1;
+                }
+            };
+            if constexpr (Z + 1 <= NZM) {
+                if (Z + 1 < nz)
+                    body(std::true_type{}, std::false_type{});
+                else if (Z + 1 == nz)
+                    body(std::true_type{}, std::true_type{});
+                else
+                    body(std::false_type{}, std::true_type{});
+            } else {
+                body(std::false_type{}, std::true_type{});
             }
-            __syncthreads();
-            const double xm = lds[r_xm + (S ? sb_xm : 0)];
-            const double xp = lds[r_xp + (S ? sb_xp : 0)];
-            const v2d ym = *reinterpret_cast<const v2d*>(lds + r_ym + (S ? sb_ym : 0));
-            const v2d yp = *reinterpret_cast<const v2d*>(lds + r_yp + (S ? sb_yp : 0));
-            r_xm += sx_xm;
-            r_xp += sx_xp;
-            r_ym += sx_ym;
-            r_yp += sx_yp;
-            double sa = xm + b;
-            sa = sa + ym.x;
-            sa = sa + yp.x;
-            sa = sa + ca[Z - 1];
-            sa = sa + zpa;
-            double sb = a + xp;
-            sb = sb + ym.y;
-            sb = sb + yp.y;
-            sb = sb + cb[Z - 1];
-            sb = sb + zpb;
-            double va, vb;
-            if (SRC)
-                div6_pair(sa + s_a, sb + s_b, va, vb);
-            else
-                div6_pair(sa, sb, va, vb);
-            vb = b_ok ? vb : b;
-            if (Z > 1) {
-                ca[Z - 1] = pa;
-                cb[Z - 1] = pb;
-            }
-            pa = va;
-            pb = vb;
-            if (Z == nz) {
-                ca[Z] = va;
-                cb[Z] = vb;
-            }
+            r_xm += 2 * sx_xm;
+            r_xp += 2 * sx_xp;
+            r_ym += 2 * sx_ym;
+            r_yp += 2 * sx_yp;
             return true;
         };
-        resident_steps<1, NZM>(step);
+        resident_steps<0, (NZM + 1) / 2>(step);
     };
     for (int k = 0; k < nsweeps; k += 2) {
         sweep(std::integral_constant<int, 0>{});
@@ -1765,32 +1834,29 @@ hipError_t launch_ir_inner3(const BlockDesc* blocks, const Item* items, int nite
     }
 }
 
-template <int NZM, bool SRC>
-hipError_t resident_launch(const BlockDesc* blocks, const Item* items, int n, int threads, size_t lds, int nz_odd,
-                           int parity, int nsweeps, hipStream_t s)
-{
-    if (nz_odd)
-        hipLaunchKernelGGL((k_resident<NZM, SRC, 1>), dim3(n), dim3(threads), lds, s, blocks, items, parity, nsweeps);
-    else
-        hipLaunchKernelGGL((k_resident<NZM, SRC, 0>), dim3(n), dim3(threads), lds, s, blocks, items, parity, nsweeps);
-    return hipGetLastError();
-}
-
 hipError_t launch_resident(const BlockDesc* blocks, const Item* items, int nitems, int max_pairs, int max_nz,
-                           size_t lds_bytes, int nz_odd, int parity, int nsweeps, bool src, hipStream_t s)
+                           size_t lds_bytes, int variant, int parity, int nsweeps, bool src, hipStream_t s)
 {
     const int n = items ? nitems : 1;
     if (n <= 0 || nsweeps <= 0)
         return hipSuccess;
     if (max_pairs < 1 || max_pairs > kResidentMaxPairs || max_nz < 1 || max_nz > kResidentMaxPlanes ||
-        lds_bytes > kResidentMaxLds || n > 65535)
+        lds_bytes > (size_t)kResidentMaxLds || n > 65535 || variant < 0 || variant >= kResidentVariants)
         return hipErrorInvalidValue;
-    const int threads = (max_pairs + 63) / 64 * 64;
-    if (max_nz <= 16)
-        return src ? resident_launch<16, true>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s)
-                   : resident_launch<16, false>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s);
-    return src ? resident_launch<32, true>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s)
-               : resident_launch<32, false>(blocks, items, n, threads, lds_bytes, nz_odd, parity, nsweeps, s);
+    const dim3 grid(n), block((max_pairs + 63) / 64 * 64);
+    // variants (resident_variant): an even or odd number of steps per sweep
+#define JC_RESIDENT_CASE(V, KT, KF)                                                                            \
+    if (variant == V) {                                                                                        \
+        if (src)                                                                                               \
+            hipLaunchKernelGGL(KT, grid, block, lds_bytes, s, blocks, items, parity, nsweeps);                   \
+        else                                                                                                   \
+            hipLaunchKernelGGL(KF, grid, block, lds_bytes, s, blocks, items, parity, nsweeps);                   \
+        return hipGetLastError();                                                                              \
+    }
+    JC_RESIDENT_CASE(0, (k_resident<true, 0>), (k_resident<false, 0>))
+    JC_RESIDENT_CASE(1, (k_resident<true, 1>), (k_resident<false, 1>))
+#undef JC_RESIDENT_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ir_inner2_items(const BlockDesc* blocks, const Item* items, int nitems, int qparity, int tile_y,

@@ -334,14 +334,15 @@ def test_wide_tiles_need_binary64_storage():
 
 
 def resident_lds(nx, ny, nz):
-    # two plane buffers of (nx + 1) // 2 pairs by ny rows, and the x and y ghost rings of every plane
+    # four plane buffers of (nx + 1) // 2 pairs by ny rows, and the x and y ghost rings of every plane
     pw = 2 * ((nx + 1) // 2)
-    return 8 * (2 * ny * pw + 2 * nz * ny + 2 * nz * pw)
+    return 8 * (4 * ny * pw + 2 * nz * ny + 2 * nz * pw)
 
 
 @pytest.mark.parametrize("grid,ok", [((32, 32, 32), True), ((31, 32, 32), True), ((1, 1, 1), True),
-                                     ((64, 16, 32), True), ((33, 32, 32), False), ((32, 32, 33), False),
-                                     ((2, 512, 8), False), ((2, 512, 1), True), ((64, 16, 24), True)])
+                                     ((64, 8, 32), True), ((64, 16, 32), False), ((64, 16, 24), True),
+                                     ((33, 32, 32), False), ((32, 32, 33), False), ((2, 512, 8), False),
+                                     ((2, 512, 1), True), ((3, 250, 5), True), ((4, 300, 2), False)])
 def test_resident_shape_limits(grid, ok):
     """One block of at most 32 planes, (nx + 1) / 2 * ny <= 512 cell pairs
     and an LDS need of at most 64 KiB."""

@@ -4,11 +4,11 @@ sweeps per launch) against the CPU oracle.
 Each sweep forms every cell's update with the same sums in the same order
 as a one-sweep launch, so the iterate is expected bitwise equal to the
 oracle's after any number of sweeps: even and odd block extents (odd nx:
-the last thread's second column is the x = nx + 1 ghost; odd nz: the
-other of the two unrolled step parities), even and odd sweep counts,
-one- and two-plane blocks (the source prefetch wraps into the next sweep
-at once), the largest blocks the kernel takes, and solves whose windows
-are single launches."""
+the last thread's second column is the x = nx + 1 ghost; odd nz: a sweep
+ends with a one-plane step; nz mod 4: the two step schedules), even and
+odd sweep counts, blocks of one to three planes (the source prefetch
+wraps into the next sweep at once, or twice), the largest blocks the
+kernel takes, and solves whose windows are single launches."""
 import numpy as np
 import pytest
 
@@ -36,8 +36,14 @@ def say(*a):
     ((6, 4, 2), 5, True),          # two planes
     ((1, 1, 1), 4, True),
     ((2, 1, 3), 3, False),
-    ((64, 16, 32), 11, True),      # 512 threads, 64-cell rows
-    ((63, 16, 32), 10, True),
+    ((7, 6, 3), 10, True),
+    ((8, 9, 4), 7, True),
+    ((10, 3, 5), 8, False),
+    ((12, 10, 22), 9, True),       # eleven two-plane steps per sweep
+    ((13, 7, 9), 6, False),        # four two-plane steps and one single
+    ((64, 8, 32), 11, True),       # 64-cell rows
+    ((63, 8, 32), 10, True),
+    ((64, 16, 24), 5, True),       # 512 threads, 64-cell rows, near the LDS limit
     ((3, 250, 5), 6, True),        # two pairs per row, 250 rows
 ])
 @pytest.mark.parametrize("mode", ["staged", "fused"])
@@ -110,7 +116,7 @@ def test_resident_group_vs_oracle(graphs):
     when the group forms: each member's iterate equals the oracle's."""
     from paper_2102_12416_amd import Group
     specs = [((32, 32, 32), True, 0), ((17, 23, 31), True, 3), ((20, 18, 16), False, 1),
-             ((9, 5, 15), False, 0), ((64, 16, 32), True, 2), ((6, 4, 2), True, 5), ((1, 1, 1), True, 1)]
+             ((9, 5, 15), False, 0), ((64, 8, 32), True, 2), ((6, 4, 2), True, 5), ((1, 1, 1), True, 1)]
     say("resident group", "graphs" if graphs else "eager")
     solvers, refs = [], []
     for i, (n, src, pre) in enumerate(specs):
