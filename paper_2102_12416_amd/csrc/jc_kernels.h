@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "jc_types.h"
+#include "jc_resident.h"
 
 namespace jc {
 
