@@ -489,7 +489,48 @@ def forms(args):
                          max_rel_diff_host_vs_gpu_residual=worst,
                          how="numpy binary64 residual of every returned iterate over that of the initial one"))
     print("[bench] forms: serving %s" % json.dumps(res["serving"]), file=sys.stderr, flush=True)
+    res["small_grids"] = small_group_rates(args, 256, 32, forms_=("three_sweeps", "resident"))
+    print("[bench] forms: small grids %s" % json.dumps(res["small_grids"]), file=sys.stderr, flush=True)
     return res
+
+
+def small_group_rates(args, count, m, forms_=("one_sweep", "three_sweeps", "resident"), window=300):
+    """A group of `count` independent m^3 grids (binary64, with a source)
+    swept together in each launch form: time per sweep of all members over
+    a window of shared launches (HIP events, graph replay), aggregate
+    GLUP/s, and whether a member's iterate equals the first form's."""
+    import torch
+
+    from paper_2102_12416_amd import Group, Solver, synth_field
+    gm = (m, m, m)
+    kws = {"one_sweep": dict(), "three_sweeps": dict(temporal=3), "resident": dict(resident=True)}
+    stream = torch.cuda.Stream()
+    solvers = [Solver(gm, mode="fused", with_source=True, use_graphs=False, stream=stream) for _ in range(count)]
+    row, ref = {}, None
+    for tag in forms_:
+        for i, s in enumerate(solvers):
+            s.load(synth_field(gm, args.seed + i, 0), synth_field(gm, args.seed + i, 1))
+        with Group(solvers, use_graphs=True, stream=stream, **kws[tag]) as grp:
+            grp.iterate(window)                   # warm-up and graph capture
+            grp.stream.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(grp.stream)
+            grp.iterate(window)
+            e1.record(grp.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / window
+        u = solvers[count // 2].store()
+        if ref is None:
+            ref = u
+        row[tag] = dict(us_per_sweep=round(ms * 1e3, 2), glups=round(count * m ** 3 / (ms * 1e-3) / 1e9, 2),
+                        bitwise_equal_first_form=bool(torch.equal(u, ref)))
+    for s in solvers:
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+    return dict(config="group of %d independent %d^3 grids, binary64 with a source, fused, %d-sweep windows"
+                       % (count, m, window), forms=row)
 
 
 def bench_refinement(args):
@@ -702,40 +743,11 @@ def bench_small(args):
         print("[bench] small %d^3: %s" % (m, json.dumps(row)), file=sys.stderr, flush=True)
     # many small solves at once: a group of 32^3 members, each form's
     # launches shared by all members (one work-group per member when resident)
-    from paper_2102_12416_amd import Group
-    m = 32
-    gm = (m, m, m)
     batch = {}
     for count in args.small_group_sizes:
-        stream = torch.cuda.Stream()
-        solvers = [Solver(gm, mode="fused", with_source=True, use_graphs=False, stream=stream)
-                   .load(synth_field(gm, args.seed + i, 0), synth_field(gm, args.seed + i, 1)) for i in range(count)]
-        row, ref = {}, None
-        for tag, kw in (("one_sweep", dict()), ("three_sweeps", dict(temporal=3)), ("resident", dict(resident=True))):
-            for i, s in enumerate(solvers):
-                s.load(synth_field(gm, args.seed + i, 0), synth_field(gm, args.seed + i, 1))
-            window = 300
-            with Group(solvers, use_graphs=True, stream=stream, **kw) as grp:
-                grp.iterate(window)               # warm-up and graph capture
-                grp.stream.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(grp.stream)
-                grp.iterate(window)
-                e1.record(grp.stream)
-                e1.synchronize()
-                ms = e0.elapsed_time(e1) / window
-            u = solvers[count // 2].store()
-            if ref is None:
-                ref = u
-            row[tag] = dict(us_per_sweep=round(ms * 1e3, 2), glups=round(count * m ** 3 / (ms * 1e-3) / 1e9, 2),
-                            bitwise_equal_one_sweep=bool(torch.equal(u, ref)))
-        for s in solvers:
-            s.close()
-        del solvers
-        torch.cuda.empty_cache()
-        batch[str(count)] = row
-        print("[bench] small group of %d x 32^3: %s" % (count, json.dumps(row)), file=sys.stderr, flush=True)
+        batch[str(count)] = small_group_rates(args, count, 32)["forms"]
+        print("[bench] small group of %d x 32^3: %s" % (count, json.dumps(batch[str(count)])), file=sys.stderr,
+              flush=True)
     first = rows[str(args.small_edges[0])]
     best_other = min(first[t]["seconds_to_1e10"] for t in ("one_sweep", "two_sweeps", "three_sweeps"))
     out = {"metric": "time to 1e-10 relative residual for a small grid: resident sweeps vs launches per sweep",
