@@ -147,3 +147,28 @@ def test_resident_group_rejects():
         Group([s], resident=True, temporal=True)
     assert e.value.code == L.JC_ERR_INVALID
     s.close()
+
+
+def test_resident_random_shapes():
+    """Seeded random blocks within the kernel's limits, random sweep counts
+    and sources, both modes: bitwise the oracle's."""
+    rng = np.random.default_rng(2102)
+    done = 0
+    while done < 24:
+        n = (int(rng.integers(1, 65)), int(rng.integers(1, 41)), int(rng.integers(1, 33)))
+        pw = 2 * ((n[0] + 1) // 2)
+        if (n[0] + 1) // 2 * n[1] > 512 or 8 * (4 * n[1] * pw + 2 * n[2] * n[1] + 2 * n[2] * pw) > 65536:
+            continue
+        iters = int(rng.integers(1, 12))
+        src = bool(rng.integers(0, 2))
+        mode = ("staged", "fused")[done % 2]
+        say("resident random", n, iters, "source" if src else "", mode)
+        u0 = synth.boundary_field(n, seed=100 + done)
+        b = synth.source_field(n, seed=100 + done) if src else None
+        ref, _ = oracle.c_jacobi(u0, iters, b)
+        with Solver(n, mode=mode, with_source=src, resident=True, use_graphs=False) as s:
+            s.load(u0, b)
+            s.iterate(iters)
+            got = s.store().cpu().numpy()
+        assert np.array_equal(got, ref), (n, iters, src, mode)
+        done += 1
