@@ -757,6 +757,19 @@ def bench_small(args):
            "config": {"workload": "small", "edges": list(args.small_edges), "rtol": 1e-10, "check_every": 50,
                       "mode": "fused, one block", "source": "U[-1,1) SplitMix64", "boundary": "U[0,1) SplitMix64"},
            "forms": rows, "groups_of_32_cubed": batch}
+    if batch:
+        # the resident kernel is neither HBM- nor matrix-bound: price its
+        # binary64 vector arithmetic (per update five neighbour additions,
+        # the source addition, a multiply and two fused multiply-adds = 10
+        # flops; the rarely taken IEEE division aside) against the part's
+        # binary64 vector peak, at the largest group
+        big = str(max(args.small_group_sizes))
+        rate = batch[big]["resident"]["glups"] * 1e9 * 10 / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_resident (group of %s x 32^3)" % big,
+                           "achieved": round(rate, 3), "peak": 78.6, "unit": "TFLOP/s", "frac": round(rate / 78.6, 4),
+                           "flops_per_update": 10, "traffic": None,
+                           "note": "latency-bound plane steps (LDS round trip, barrier, dependent binary64 chains); "
+                                   "HBM traffic is one read and write of each block per launch"}
     print(json.dumps(out), flush=True)
 
 
