@@ -127,18 +127,18 @@ typedef struct jc_options {
                             single sweep.  Results bitwise the same. */
     int resident;        /* 1: on-chip sweeps for a small grid -- jc_iterate and the windows
                             of jc_solve run as one launch each, whatever their length: one
-                            work-group holds the block on chip (its iterate in registers, a
-                            plane and the ghost rings in LDS) and sweeps it that many times,
-                            so a solve costs one launch per residual check.  Needs a context
-                            of one block of at most 32 planes with (nx + 1) / 2 * ny <= 512
-                            cell pairs (one thread each, rounded up to whole waves of 64),
-                            at most that many threads' worth of ghost ring per plane
-                            (2 nx' + 2 ny, nx' = nx rounded up to even) and an LDS need of
-                            8 (2 (ny + 2)(nx' + 4) + nz (2 nx' + 2 ny)) bytes within 64 KiB
-                            (for instance 32^3, 64 x 16 x 32), no refinement, temporal = 0
-                            and overlap = 0; else JC_ERR_INVALID at creation.  Results bitwise equal to one-sweep launches.  After a
-                            window only the copy holding the iterate is defined (the other
-                            copy holds an older iterate).  0: off. */
+                            work-group holds the block on chip (its iterate in registers,
+                            two planes at a time and the ghost rings in LDS) and sweeps it
+                            that many times, so a solve costs one launch per residual check.
+                            Needs a context of one block of at most 32 planes with
+                            (nx + 1) / 2 * ny <= 512 cell pairs (one thread each) and an LDS
+                            need of 8 (4 ny nx' + 2 nz ny + 2 nz nx') bytes within 64 KiB
+                            (nx' = nx rounded up to even; for instance 32^3 or 64 x 8 x 32,
+                            not 64 x 16 x 32), no refinement, temporal = 0 and overlap = 0;
+                            else JC_ERR_INVALID at creation.  Results bitwise equal to
+                            one-sweep launches.  After a window only the copy holding the
+                            iterate is defined (the other copy holds an older iterate).
+                            0: off. */
 } jc_options;
 
 /* Result of a solve. */
@@ -289,12 +289,11 @@ int jc_solve_ir(jc_ctx* ctx, int inner_sweeps, double rtol, int64_t max_inner,
  * per launch (the same conditions and tiles; a count that is not a
  * multiple of three ends with a two-sweep launch or a single sweep);
  * bit 3 = resident sweeps: every jc_group_iterate window is one launch per
- * class and parity of the members' plane counts with one
- * work-group per member, which keeps its member's block on chip for the
- * whole window (members as for options.resident: one block of at most 32
- * planes, (nx + 1) / 2 * ny <= 512, the ring and LDS limits there, no
- * refinement; else JC_ERR_INVALID; not with bits 1 and 2; results bitwise
- * the same).
+ * class and parity of the members' (nz + 1) / 2 with one work-group per
+ * member, which keeps its member's block on chip for the whole window
+ * (members as for options.resident: one block of at most 32 planes,
+ * (nx + 1) / 2 * ny <= 512, the LDS limit there, no refinement; else
+ * JC_ERR_INVALID; not with bits 1 and 2; results bitwise the same).
  * tile: {cells per row 16|32|64 (or 96|128|256 when no member refines in
  * binary32 or bfloat16), rows 4|8|16|32 (64 to 1024 threads), planes >= 1} for every
  * launch of the group, or NULL for {64, 8, 32}; members' results do not

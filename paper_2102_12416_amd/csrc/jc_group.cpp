@@ -41,7 +41,7 @@ struct Class {
     std::vector<Item> items2;        // two-sweep tiles (groups that sweep twice per launch)
     std::vector<int> members;
     // resident sweeps: one item per member, split by launch variant (the
-    // kernel's step schedule depends on the parity of the plane count)
+    // kernel's step schedule depends on the parity of (nz + 1) / 2)
     std::vector<Item> itemsr[jc::kResidentVariants];
     size_t itemr0[jc::kResidentVariants] = {};       // first joint resident item of each split
     int max_pairs[jc::kResidentVariants] = {}, max_nz[jc::kResidentVariants] = {};
@@ -326,9 +326,8 @@ int jc_group_create(jc_ctx* const* ctxs, int n, void* hip_stream, int flags, con
         if ((flags & 8) && (c->opt.ir_enable || c->nb() != 1 ||
                             !jc::resident_fits(c->blocks[0].n[0], c->blocks[0].n[1], c->blocks[0].n[2])))
             return fail(JC_ERR_INVALID, "resident sweeps (flag 8) need members of one block of at most 32 planes "
-                                        "with (nx + 1) / 2 * ny <= 512 cell pairs, a ghost ring per plane no "
-                                        "longer than the work-group and an LDS need within 64 KiB, without "
-                                        "refinement");
+                                        "with (nx + 1) / 2 * ny <= 512 cell pairs and an LDS need within 64 KiB, "
+                                        "without refinement");
     }
     if (tile) {
         bool narrow = false;

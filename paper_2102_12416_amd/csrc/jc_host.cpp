@@ -259,8 +259,7 @@ int build_geometry(jc_ctx* c, const int64_t grid[3], const std::vector<int64_t> 
         return fail(JC_ERR_INVALID, "options.temporal needs a context of one block (no face pairs)");
     if (c->opt.resident && (c->nb() != 1 || !jc::resident_fits(c->blocks[0].n[0], c->blocks[0].n[1], c->blocks[0].n[2])))
         return fail(JC_ERR_INVALID, "options.resident needs a context of one block of at most 32 planes with "
-                                    "(nx + 1) / 2 * ny <= 512 cell pairs, a ghost ring per plane no longer than "
-                                    "the work-group and an LDS need within 64 KiB");
+                                    "(nx + 1) / 2 * ny <= 512 cell pairs and an LDS need within 64 KiB");
     default_tiles(c, &c->tile_x, &c->tile_y, &c->z_chunk);
     build_items(c);
     // the work-list region is sized for the finest tiling the tuner may pick
