@@ -5,7 +5,8 @@ For any cuts of any grid the blocks tile the grid exactly as the tensor
 product of the cuts, every paired face has its reverse with the opposite
 face and the face's area as count, global-boundary faces have no
 neighbour, and the work list of any valid tile shape (16- to 256-cell
-rows) holds exactly the tiles that cover every block once.
+rows) holds exactly the tiles that cover every block once.  Resident
+sweeps are accepted for exactly the blocks within the kernel's limits.
 """
 import ctypes
 import itertools
@@ -128,3 +129,26 @@ def test_work_list_covers_every_block_once(cuts, tx, ty, zc):
         assert tuple(out) == (tx, ty, zc, want)
     finally:
         L.lib.jc_destroy(ctx)
+
+
+@settings(max_examples=200, deadline=None)
+@given(nx=hs.integers(1, 80), ny=hs.integers(1, 600), nz=hs.integers(1, 40), src=hs.booleans())
+def test_resident_limits_property(nx, ny, nz, src):
+    """A one-block context takes options.resident exactly when the block has
+    at most 32 planes, at most 512 cell pairs per plane and an LDS need
+    (four plane buffers of (nx + 1) // 2 pairs by ny rows, and the x and y
+    ghost rings of every plane) of at most 64 KiB."""
+    pw = 2 * ((nx + 1) // 2)
+    ok = nz <= 32 and (nx + 1) // 2 * ny <= 512 and 8 * (4 * ny * pw + 2 * nz * ny + 2 * nz * pw) <= 65536
+    opt = L.Options()
+    opt.ir_dtype = L.JC_NONE
+    opt.with_source = int(src)
+    opt.resident = 1
+    ctx = ctypes.c_void_p()
+    g = L.i64((nx, ny, nz))
+    st = L.lib.jc_create(g, g, ctypes.byref(opt), ctypes.byref(ctx))
+    if ok:
+        assert st == 0, L.last_error()
+        L.lib.jc_destroy(ctx)
+    else:
+        assert st == L.JC_ERR_INVALID and "resident" in L.last_error()
