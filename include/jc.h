@@ -125,7 +125,8 @@ typedef struct jc_options {
                             per three sweeps (tiles of 8 or 16 rows); a count that is
                             not a multiple of three ends with a two-sweep launch or a
                             single sweep.  Results bitwise the same. */
-    int resident;        /* 1: on-chip sweeps for a small grid -- jc_iterate and the windows
+    int resident;        /* 1: on-chip sweeps for a small grid (the Jacobi sweep of section
+                            4.3, many per launch) -- jc_iterate and the windows
                             of jc_solve run as one launch each, whatever their length: one
                             work-group holds the block on chip (its iterate in registers,
                             two planes at a time and the ghost rings in LDS) and sweeps it

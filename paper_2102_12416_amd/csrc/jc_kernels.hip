@@ -1162,7 +1162,9 @@ k_sweep3(const BlockDesc* __restrict__ blocks, const Item* __restrict__ items, i
 
 // ---- resident sweeps: many sweeps of a small block in one launch ----
 //
-// The on-chip small-grid solver: one work-group holds a whole block of
+// The on-chip small-grid solver for the Jacobi sweep of paper section 4.3
+// (not a design of the paper: its blocks are swept once per launch and
+// exchange halos between sweeps): one work-group holds a whole block of
 // at most 32 planes and (nx + 1) / 2 * ny <= 512 cell pairs and runs any
 // number of Jacobi sweeps on it without leaving the compute unit, so a
 // small solve costs one launch per window instead of one per sweep (or
