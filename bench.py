@@ -82,7 +82,8 @@ def parse():
     ap.add_argument("--small-edges", type=int, nargs="*", default=[32, 24, 16],
                     help="small: cubic edges solved to 1e-10 with each launch form")
     ap.add_argument("--small-group-sizes", type=int, nargs="*", default=[256, 1024],
-                    help="small: group sizes of 32^3 members swept together")
+                    help="small: group sizes of members swept together")
+    ap.add_argument("--small-group-edge", type=int, default=32, help="small: cubic edge of the group members")
     ap.add_argument("--ir-edge", type=int, default=1024, help="refine: grid edge of the per-sweep rates")
     ap.add_argument("--ir-sweeps", type=int, default=100, help="refine: sweeps timed per precision")
     ap.add_argument("--ir-tile", default="", help="refine: tile_x,tile_y,z_chunk of the refinement solvers "
@@ -744,9 +745,10 @@ def bench_small(args):
     # many small solves at once: a group of 32^3 members, each form's
     # launches shared by all members (one work-group per member when resident)
     batch = {}
+    ge = args.small_group_edge
     for count in args.small_group_sizes:
-        batch[str(count)] = small_group_rates(args, count, 32)["forms"]
-        print("[bench] small group of %d x 32^3: %s" % (count, json.dumps(batch[str(count)])), file=sys.stderr,
+        batch[str(count)] = small_group_rates(args, count, ge)["forms"]
+        print("[bench] small group of %d x %d^3: %s" % (count, ge, json.dumps(batch[str(count)])), file=sys.stderr,
               flush=True)
     first = rows[str(args.small_edges[0])]
     best_other = min(first[t]["seconds_to_1e10"] for t in ("one_sweep", "two_sweeps", "three_sweeps"))
@@ -756,7 +758,7 @@ def bench_small(args):
            "higher_is_better": True, "data": "synthetic", "dtype": "f64",
            "config": {"workload": "small", "edges": list(args.small_edges), "rtol": 1e-10, "check_every": 50,
                       "mode": "fused, one block", "source": "U[-1,1) SplitMix64", "boundary": "U[0,1) SplitMix64"},
-           "forms": rows, "groups_of_32_cubed": batch}
+           "forms": rows, "group_edge": ge, "groups": batch}
     if batch:
         # the resident kernel is neither HBM- nor matrix-bound: price its
         # binary64 vector arithmetic (per update five neighbour additions,
@@ -765,7 +767,7 @@ def bench_small(args):
         # binary64 vector peak, at the largest group
         big = str(max(args.small_group_sizes))
         rate = batch[big]["resident"]["glups"] * 1e9 * 10 / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "k_resident (group of %s x 32^3)" % big,
+        out["roofline"] = {"bound": "alu", "kernel": "k_resident (group of %s x %d^3)" % (big, ge),
                            "achieved": round(rate, 3), "peak": 78.6, "unit": "TFLOP/s", "frac": round(rate / 78.6, 4),
                            "flops_per_update": 10, "traffic": None,
                            "note": "latency-bound plane steps (LDS round trip, barrier, dependent binary64 chains); "
