@@ -94,6 +94,9 @@ def parse():
     ap.add_argument("--serve-capacity-requests", type=int, default=0,
                     help="requests of the closed-loop capacity run (0: the same set as the timed run)")
     ap.add_argument("--serve-max-edge", type=int, default=384)
+    ap.add_argument("--serve-min-edge", type=int, default=32)
+    ap.add_argument("--serve-resident", action="store_true",
+                    help="serve: binary64 requests of edge <= 32 in a lane of resident sweeps")
     ap.add_argument("--serve-max-iter", type=int, default=20000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-lanes", default="64,160",
@@ -852,14 +855,14 @@ def bench_serve(args):
 
     def reqs(count, rate, seed):
         return [Request(id=r["id"], arrival=r["arrival"], n=r["n"], precision=r["precision"], seed=r["seed"])
-                for r in synth.serving_requests(count, rate, seed=seed, lo=32, hi=args.serve_max_edge)]
+                for r in synth.serving_requests(count, rate, seed=seed, lo=args.serve_min_edge, hi=args.serve_max_edge)]
 
     budget = int(args.serve_budget_gb * (1 << 30))
     lanes = () if args.serve_lanes in ("", "none") else tuple(int(v) for v in args.serve_lanes.split(","))
 
     def server():
         return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter,
-                      progress_every=15.0, lanes=lanes, temporal=tmode(args),
+                      progress_every=15.0, lanes=lanes, temporal=tmode(args), resident=args.serve_resident,
                       tile=[int(v) for v in args.serve_tile.split(",")] if args.serve_tile else None)
 
     cap = None
@@ -887,7 +890,8 @@ def bench_serve(args):
            "value": round(summ["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "dtype": "f64 / f32-refined",
            "config": {"workload": "serve", "requests": args.serve_requests, "rate_per_s": round(rate, 3),
-                      "edges": "log-uniform [32, %d]" % args.serve_max_edge, "precision": "Bernoulli(0.5) f64/f32",
+                      "edges": "log-uniform [%d, %d]" % (args.serve_min_edge, args.serve_max_edge),
+                      "precision": "Bernoulli(0.5) f64/f32", "resident_lane": bool(args.serve_resident),
                       "rtol": 1e-10, "max_iter": args.serve_max_iter, "window": 50,
                       "budget_gb": args.serve_budget_gb, "lanes": list(lanes), "tile": args.serve_tile or "64,8,32 (group default)",
                       "rate_source": "given" if args.serve_rate > 0 else "0.7 x closed-loop capacity"},

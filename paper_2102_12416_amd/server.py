@@ -93,12 +93,18 @@ class _Live:
     bytes: int
 
 
+# the largest cubic edge a resident block takes: at most 32 planes, (n + 1) / 2 * n
+# <= 512 cell pairs and 8 (4 n n' + 2 n n + 2 n n') <= 64 KiB of LDS (n' = n rounded up to even)
+RESIDENT_MAX_EDGE = 32
+
+
 class _Lane:
     """Requests of one size class: their own stream, group and window
     cadence, so a small solve never waits for the windows of large ones."""
 
-    def __init__(self, max_edge, device):
+    def __init__(self, max_edge, device, resident=False):
         self.max_edge = max_edge          # largest edge in this lane (None: unbounded)
+        self.resident = resident          # resident sweeps: one work-group per member, one launch per window
         self.stream = torch.cuda.Stream(device=device)
         self.active: list[_Live] = []
         self.pending: list[_Live] = []    # admitted, joining at the next window boundary
@@ -123,11 +129,15 @@ class Server:
     joins the first lane with n <= bound, else the last (unbounded) lane.
     An empty tuple serves everything in one group.  temporal: every size
     class gets a lane per precision, and every lane sweeps twice (True) or
-    three times (3) per launch (results bitwise the same)."""
+    three times (3) per launch (results bitwise the same).  resident: binary64
+    requests whose grid fits one compute unit (edges up to 32) go to a lane
+    of their own that sweeps each window in one launch with one work-group
+    per request (results bitwise the same)."""
 
     def __init__(self, budget_bytes: int, window: int = 50, rtol: float = 1e-10, max_iter: int = 20000,
                  device: str = "cuda:0", keep_fields: bool = False, use_graphs: bool = True,
-                 progress_every: float = 0.0, lanes=(64, 160), tile=None, temporal: bool = False):
+                 progress_every: float = 0.0, lanes=(64, 160), tile=None, temporal: bool = False,
+                 resident: bool = False):
         if window < 1 or max_iter % window:
             raise ValueError("max_iter must be a multiple of the window")
         bounds = [int(v) for v in lanes]
@@ -152,6 +162,7 @@ class Server:
         self.temporal = 3 if temporal == 3 else bool(temporal)
         if self.temporal is True and self.window % 2:
             raise ValueError("two sweeps per launch need an even window")
+        self.resident = bool(resident)
         self.max_members = 4096
         self.stats = dict(windows=0, group_builds=0, peak_members=0, peak_bytes=0, lane_windows=[])
         self.progress_every = float(progress_every)   # seconds between progress lines (0: none)
@@ -191,7 +202,8 @@ class Server:
         lane.close()
         if lane.active:
             lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream,
-                               tile=self.tile, temporal=self.temporal)
+                               tile=self.tile, temporal=False if lane.resident else self.temporal,
+                               resident=lane.resident)
             lane.key = tuple(l.req.id for l in lane.active)
             self.stats["group_builds"] += 1
 
@@ -242,6 +254,9 @@ class Server:
         lane_sets = {k: [_Lane(b, self.device) for b in self.lane_bounds] + [_Lane(None, self.device)]
                      for k in keys}
         lanes = [lane for k in keys for lane in lane_sets[k]]
+        small = _Lane(RESIDENT_MAX_EDGE, self.device, resident=True) if self.resident else None
+        if small is not None:
+            lanes.append(small)
         done: list[Result] = []
         used = 0
         t0 = time.perf_counter()
@@ -275,7 +290,10 @@ class Server:
                 if used + need > self.budget:
                     break
                 queue.popleft()
-                lane = self._lane_of(lane_sets[head.precision if self.temporal else None], head.n)
+                if small is not None and head.precision == "f64" and head.n <= RESIDENT_MAX_EDGE:
+                    lane = small
+                else:
+                    lane = self._lane_of(lane_sets[head.precision if self.temporal else None], head.n)
                 live = self._admit(head, clock(), lane.stream)
                 lane.pending.append(live)
                 used += live.bytes

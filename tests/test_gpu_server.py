@@ -165,3 +165,23 @@ def test_group_check_is_the_stopping_rule():
         assert g3.check(1e-10, 10 ** 6)[0] == (1.0, False)
     for s in solvers:
         s.close()
+
+
+def test_resident_lane_same_results():
+    """With resident=True the binary64 requests of edge <= 32 run in a lane
+    of their own (each window one launch, one work-group per request): every
+    result (sweeps, stop, residual, field) equals the run without it."""
+    reqs = REQS + [Request(id=6, arrival=0.0, n=12, precision="f64", seed=507),
+                   Request(id=7, arrival=0.0, n=31, precision="f64", seed=508),
+                   Request(id=8, arrival=0.0, n=33, precision="f64", seed=509)]
+    say("server resident lane")
+    kw = dict(budget_bytes=1 << 34, window=50, rtol=1e-10, max_iter=1500, keep_fields=True)
+    srv0 = Server(**kw)
+    base = srv0.run(reqs, realtime=False)
+    srv1 = Server(resident=True, **kw)
+    res = srv1.run(reqs, realtime=False)
+    assert len(srv1.stats["lane_windows"]) == len(srv0.stats["lane_windows"]) + 1
+    assert srv1.stats["lane_windows"][-1] > 0
+    for a, m in zip(base, res):
+        assert a.iters == m.iters and a.converged == m.converged and a.rel_resid == m.rel_resid, a.id
+        assert np.array_equal(a.field, m.field), a.id
