@@ -201,8 +201,11 @@ class Server:
     def _regroup(self, lane):
         lane.close()
         if lane.active:
-            lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs, stream=lane.stream,
-                               tile=self.tile, temporal=False if lane.resident else self.temporal,
+            # a resident lane's window is one launch per kernel variant: a
+            # graph of it would save nothing and cost an instantiation per
+            # membership change
+            lane.group = Group([l.solver for l in lane.active], use_graphs=self.use_graphs and not lane.resident,
+                               stream=lane.stream, tile=self.tile, temporal=False if lane.resident else self.temporal,
                                resident=lane.resident)
             lane.key = tuple(l.req.id for l in lane.active)
             self.stats["group_builds"] += 1
