@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--serve-min-edge", type=int, default=32)
     ap.add_argument("--serve-resident", action="store_true",
                     help="serve: binary64 requests of edge <= 32 in a lane of resident sweeps")
+    ap.add_argument("--serve-no-graphs", action="store_true",
+                    help="serve: launch every window eagerly instead of replaying a captured graph")
     ap.add_argument("--serve-max-iter", type=int, default=20000)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-lanes", default="64,160",
@@ -863,6 +865,7 @@ def bench_serve(args):
     def server():
         return Server(budget_bytes=budget, window=50, rtol=1e-10, max_iter=args.serve_max_iter,
                       progress_every=15.0, lanes=lanes, temporal=tmode(args), resident=args.serve_resident,
+                      use_graphs=not args.serve_no_graphs,
                       tile=[int(v) for v in args.serve_tile.split(",")] if args.serve_tile else None)
 
     cap = None
@@ -892,6 +895,7 @@ def bench_serve(args):
            "config": {"workload": "serve", "requests": args.serve_requests, "rate_per_s": round(rate, 3),
                       "edges": "log-uniform [%d, %d]" % (args.serve_min_edge, args.serve_max_edge),
                       "precision": "Bernoulli(0.5) f64/f32", "resident_lane": bool(args.serve_resident),
+                      "graphs": not args.serve_no_graphs,
                       "rtol": 1e-10, "max_iter": args.serve_max_iter, "window": 50,
                       "budget_gb": args.serve_budget_gb, "lanes": list(lanes), "tile": args.serve_tile or "64,8,32 (group default)",
                       "rate_source": "given" if args.serve_rate > 0 else "0.7 x closed-loop capacity"},
